@@ -1,0 +1,690 @@
+// Host runtime of the redve library: handle, parameter validation, device workspace, and the
+// driver of the FP iteration (Sec. II-B, eq. (7)) with full-cycling vector extrapolation
+// (Sec. III-C, Algorithm 3). Every arithmetic step runs in the HIP kernels; the host only
+// orders launches and reads back a few scalars (relative change, extrapolation info).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/redve.h"
+#include "internal.h"
+
+using namespace redve;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Workspace {
+    void* arena = nullptr;
+    size_t bytes = 0;
+    size_t cap_px = 0;
+    int cap_L = 0;
+    int cap_blocks = 0;
+    float *xa, *xb, *xc, *rhs, *r, *p0, *p1, *q, *u0, *u1, *d, *U;
+    double* partials;
+    unsigned* counter;
+    CgScalars* sc;
+    double* G;
+    double* norms;
+    VeInfo* info;
+};
+
+struct HostMirror {
+    double norms[2];
+    VeInfo info;
+};
+
+}  // namespace
+
+struct redve_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // operator H = S B
+    bool have_op = false;
+    std::vector<float> psf;
+    int kh = 0, kw = 0, decim = 1;
+    float* d_psf = nullptr;
+    double* d_psf64 = nullptr;
+    // sigma, lambda
+    double sigma = -1.0, lambda = -1.0;
+    // denoiser
+    bool have_den = false;
+    int T = 0, F = 0, J = 0, precision = REDVE_PREC_FP32;
+    double mu0 = 0, dmu = 0, gamma = 1;
+    std::vector<float> theta;
+    float* d_filt = nullptr;
+    float* d_rbfw = nullptr;
+    uint16_t* d_filt_bf16 = nullptr;
+    // solver
+    int method = REDVE_VE_NONE, L = 5, m = 0;
+    int cg_iters = 15, max_fp = 500, extra_fp = 0;
+    double tol = 1e-5;
+    double rank_eps = 1e-7;  // R_jj <= rank_eps * R_00 counts as rank deficient (FP32 data)
+    Workspace ws;
+    HostMirror* host = nullptr;  // pinned
+};
+
+namespace {
+
+int fail(redve_t h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(h, REDVE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK(h) HIP_TRY(h, hipGetLastError())
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ensure_workspace(redve_t h, int hx, int wx, int L) {
+    const size_t npx = (size_t)hx * wx;
+    // capacity for the grid reductions: tiled CG kernels, CG update, difference/Gram pass
+    const int H_blocks = std::max({linop_grid(hx, wx), cg_update_grid((int)npx),
+                                   diff_grid((int)npx), 1024});
+    Workspace& w = h->ws;
+    if (w.arena && w.cap_px >= npx && w.cap_L >= L && w.cap_blocks >= H_blocks) return REDVE_OK;
+    if (w.arena) {
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_TRY(h, hipFree(w.arena));
+        w.arena = nullptr;
+    }
+    const size_t cap_px = std::max(npx, w.cap_px);
+    const int cap_L = std::max(std::max(L, w.cap_L), 1);
+    const int cap_blocks = std::max(H_blocks, w.cap_blocks);
+    const size_t vec = align_up(cap_px * sizeof(float));
+    size_t bytes = vec * (11 + (size_t)cap_L);
+    const size_t o_part = bytes;
+    bytes += align_up((size_t)cap_blocks * 18 * sizeof(double));
+    const size_t o_cnt = bytes;
+    bytes += kAlign;
+    const size_t o_sc = bytes;
+    bytes += align_up(sizeof(CgScalars));
+    const size_t o_G = bytes;
+    bytes += align_up(REDVE_MAX_L * REDVE_MAX_L * sizeof(double));
+    const size_t o_norms = bytes;
+    bytes += kAlign;
+    const size_t o_info = bytes;
+    bytes += align_up(sizeof(VeInfo));
+    void* arena = nullptr;
+    if (hipMalloc(&arena, bytes) != hipSuccess)
+        return fail(h, REDVE_E_NOMEM, "device workspace allocation of " + std::to_string(bytes) +
+                                          " bytes failed");
+    char* base = (char*)arena;
+    float** vecs[] = {&w.xa, &w.xb, &w.xc, &w.rhs, &w.r, &w.p0, &w.p1, &w.q, &w.u0, &w.u1, &w.d};
+    for (int i = 0; i < 11; ++i) *vecs[i] = (float*)(base + vec * i);
+    w.U = (float*)(base + vec * 11);
+    w.partials = (double*)(base + o_part);
+    w.counter = (unsigned*)(base + o_cnt);
+    w.sc = (CgScalars*)(base + o_sc);
+    w.G = (double*)(base + o_G);
+    w.norms = (double*)(base + o_norms);
+    w.info = (VeInfo*)(base + o_info);
+    w.arena = arena;
+    w.bytes = bytes;
+    w.cap_px = cap_px;
+    w.cap_L = cap_L;
+    w.cap_blocks = cap_blocks;
+    HIP_TRY(h, hipMemsetAsync(arena, 0, bytes, h->stream));
+    return REDVE_OK;
+}
+
+Reduction red_of(redve_t h) { return Reduction{h->ws.partials, h->ws.counter, h->ws.cap_blocks}; }
+
+LinOp linop_of(redve_t h) {
+    const double is2 = 1.0 / (h->sigma * h->sigma);
+    return LinOp{h->d_psf, h->kh, h->kw, h->decim, (float)is2, (float)h->lambda, is2, h->lambda};
+}
+
+TnrdDev tnrd_of(redve_t h) {
+    TnrdDev d{};
+    d.stages = h->T;
+    d.nfilt = h->F;
+    d.nrbf = h->J;
+    d.mu0 = (float)h->mu0;
+    d.dmu = (float)h->dmu;
+    d.gamma = (float)h->gamma;
+    d.filters = h->d_filt;
+    d.rbf_w = h->d_rbfw;
+    for (int t = 0; t < h->T && t < kMaxStages; ++t) d.theta[t] = h->theta[t];
+    d.filt_bf16 = h->d_filt_bf16;
+    d.precision = h->precision;
+    return d;
+}
+
+int check_ready(redve_t h, bool need_den) {
+    if (!h->have_op) return fail(h, REDVE_E_STATE, "redve_set_operator was not called");
+    if (h->sigma <= 0) return fail(h, REDVE_E_STATE, "redve_set_noise was not called");
+    if (h->lambda <= 0) return fail(h, REDVE_E_STATE, "redve_set_lambda was not called");
+    if (need_den && !h->have_den) return fail(h, REDVE_E_STATE, "redve_set_denoiser was not called");
+    return REDVE_OK;
+}
+
+int check_image(redve_t h, int hx, int wx) {
+    if (hx < 2 || wx < 2) return fail(h, REDVE_E_ARG, "image sides must be >= 2");
+    if ((long long)hx * wx > (1LL << 30)) return fail(h, REDVE_E_ARG, "image too large");
+    return REDVE_OK;
+}
+
+// Denoiser f. residual = true writes f(x) - x (nothing, and *out_null = true, for T = 0);
+// otherwise f(x).
+int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool residual,
+                 bool* out_null) {
+    Workspace& w = h->ws;
+    const int n = H * W;
+    TnrdDev d = tnrd_of(h);
+    if (out_null) *out_null = false;
+    if (h->T == 0) {
+        if (residual) {
+            if (out_null) *out_null = true;
+        } else {
+            HIP_TRY(h, hipMemcpyAsync(out, x, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
+        }
+        return REDVE_OK;
+    }
+    const float* wprev = nullptr;
+    for (int t = 0; t < h->T; ++t) {
+        const bool last = t == h->T - 1;
+        float* dst = last ? out : ((t & 1) ? w.u1 : w.u0);
+        launch_tnrd_stage(d, t, wprev, x, dst, H, W, (last && !residual) ? 1 : 0, h->stream);
+        LAUNCH_CHECK(h);
+        wprev = dst;
+    }
+    return REDVE_OK;
+}
+
+// CG iterations on the correction: d accumulates sum alpha p; the last iteration writes
+// x_out = x_in + d. Requires r, p0 and the CG scalars set up by one of the init kernels.
+int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int iters) {
+    Workspace& w = h->ws;
+    const int n = H * W;
+    LinOp op = linop_of(h);
+    Reduction red = red_of(h);
+    float* pold = w.p0;
+    float* pnew = w.p1;
+    for (int it = 0; it < iters; ++it) {
+        const bool last = it == iters - 1;
+        launch_cg_q(op, w.r, pold, pnew, w.q, H, W, red, w.sc, h->stream);
+        launch_cg_update(w.d, w.r, pnew, w.q, n, it == 0 ? 1 : 0, x_in, last ? x_out : nullptr,
+                         red, w.sc, h->stream);
+        LAUNCH_CHECK(h);
+        std::swap(pold, pnew);
+    }
+    return REDVE_OK;
+}
+
+// iters CG iterations on A x = rhs: x_out starts at x_in (x_in != x_out).
+int run_cg(redve_t h, const float* rhs, const float* x_in, float* x_out, int H, int W, int iters) {
+    Workspace& w = h->ws;
+    const int n = H * W;
+    if (iters <= 0) {
+        HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
+        return REDVE_OK;
+    }
+    launch_cg_init(linop_of(h), x_in, rhs, w.r, w.p0, H, W, red_of(h), w.sc, h->stream);
+    LAUNCH_CHECK(h);
+    return cg_iterate(h, x_in, x_out, H, W, iters);
+}
+
+// One FP call, eq. (7): x_out = CG_{n_cg}(A, H^T y / sigma^2 + lambda f(x_in); start x_in),
+// computed as x_in + d with d the CG solution of A d = r0 from d = 0 (the same Krylov iterates),
+// r0 = H^T (y - H x_in) / sigma^2 + lambda (f(x_in) - x_in).
+int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, int W) {
+    Workspace& w = h->ws;
+    const int n = H * W;
+    bool s_null = false;
+    int rc = run_denoiser(h, x_in, H, W, w.rhs, true, &s_null);
+    if (rc) return rc;
+    if (h->cg_iters <= 0) {
+        HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
+        return REDVE_OK;
+    }
+    launch_cg_init_fp(linop_of(h), h->d_psf64, x_in, y, s_null ? nullptr : w.rhs, w.r, w.p0, H, W,
+                      red_of(h), w.sc, h->stream);
+    LAUNCH_CHECK(h);
+    return cg_iterate(h, x_in, x_out, H, W, h->cg_iters);
+}
+
+int read_back(redve_t h, bool info) {
+    HIP_TRY(h, hipMemcpyAsync(h->host->norms, h->ws.norms, sizeof(double) * 2,
+                              hipMemcpyDeviceToHost, h->stream));
+    if (info)
+        HIP_TRY(h, hipMemcpyAsync(&h->host->info, h->ws.info, sizeof(VeInfo), hipMemcpyDeviceToHost,
+                                  h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return REDVE_OK;
+}
+
+float* third(float* a, float* b, float* c, float* not1, float* not2) {
+    if (a != not1 && a != not2) return a;
+    if (b != not1 && b != not2) return b;
+    return c;
+}
+
+struct Progress {
+    double last = -1.0;
+    int grow = 0;
+    // returns 0, or an error code for a non-finite or clearly diverging relative change
+    int check(double d) {
+        if (!std::isfinite(d)) return REDVE_E_NONFINITE;
+        grow = (last >= 0 && d > last) ? grow + 1 : 0;
+        last = d;
+        if (grow >= 3 && d > 1.0) return REDVE_E_DIVERGED;
+        return REDVE_OK;
+    }
+};
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+int redve_create(redve_t* out, int device, void* hip_stream) {
+    if (!out) return REDVE_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return REDVE_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return REDVE_E_HIP;
+    redve_t h = new redve_ctx();
+    h->device = device;
+    h->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void**)&h->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return REDVE_E_NOMEM;
+    }
+    *out = h;
+    return REDVE_OK;
+}
+
+int redve_destroy(redve_t h) {
+    if (!h) return REDVE_E_ARG;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    if (h->ws.arena) hipFree(h->ws.arena);
+    hipFree(h->d_psf);
+    hipFree(h->d_psf64);
+    hipFree(h->d_filt);
+    hipFree(h->d_rbfw);
+    hipFree(h->d_filt_bf16);
+    hipHostFree(h->host);
+    delete h;
+    return REDVE_OK;
+}
+
+int redve_set_stream(redve_t h, void* hip_stream) {
+    if (!h) return REDVE_E_ARG;
+    h->stream = (hipStream_t)hip_stream;
+    return REDVE_OK;
+}
+
+const char* redve_last_error(redve_t h) { return h ? h->err.c_str() : "null handle"; }
+
+size_t redve_workspace_bytes(redve_t h, int hx, int wx) {
+    if (!h || hx <= 0 || wx <= 0) return 0;
+    const size_t vec = align_up((size_t)hx * wx * sizeof(float));
+    return vec * (11 + (size_t)std::max(h->L, 1)) + 64 * 1024;
+}
+
+int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) {
+    if (!h) return REDVE_E_ARG;
+    if (!psf || kh < 1 || kw < 1 || !(kh & 1) || !(kw & 1) || kh > REDVE_MAX_PSF ||
+        kw > REDVE_MAX_PSF)
+        return fail(h, REDVE_E_ARG, "psf must be odd-sized, at most 15 x 15");
+    if (decim < 1 || decim > REDVE_MAX_DECIM) return fail(h, REDVE_E_ARG, "decim must be in 1..4");
+    for (int i = 0; i < kh * kw; ++i)
+        if (!std::isfinite(psf[i])) return fail(h, REDVE_E_ARG, "psf has non-finite taps");
+    HIP_TRY(h, hipSetDevice(h->device));
+    h->psf.assign(kh * kw, 0.f);
+    for (int i = 0; i < kh * kw; ++i) h->psf[i] = (float)psf[i];
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->d_psf) HIP_TRY(h, hipFree(h->d_psf));
+    if (h->d_psf64) HIP_TRY(h, hipFree(h->d_psf64));
+    h->d_psf = nullptr;
+    h->d_psf64 = nullptr;
+    HIP_TRY(h, hipMalloc(&h->d_psf, sizeof(float) * kh * kw));
+    HIP_TRY(h, hipMalloc(&h->d_psf64, sizeof(double) * kh * kw));
+    HIP_TRY(h, hipMemcpy(h->d_psf, h->psf.data(), sizeof(float) * kh * kw, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_psf64, psf, sizeof(double) * kh * kw, hipMemcpyHostToDevice));
+    h->kh = kh;
+    h->kw = kw;
+    h->decim = decim;
+    h->have_op = true;
+    return REDVE_OK;
+}
+
+int redve_set_noise(redve_t h, double sigma) {
+    if (!h) return REDVE_E_ARG;
+    if (!(sigma > 0) || !std::isfinite(sigma)) return fail(h, REDVE_E_ARG, "sigma must be > 0");
+    h->sigma = sigma;
+    return REDVE_OK;
+}
+
+int redve_set_lambda(redve_t h, double lambda) {
+    if (!h) return REDVE_E_ARG;
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(h, REDVE_E_ARG, "lambda must be > 0");
+    h->lambda = lambda;
+    return REDVE_OK;
+}
+
+int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
+    if (!h) return REDVE_E_ARG;
+    if (!p) return fail(h, REDVE_E_ARG, "null denoiser");
+    if (p->stages < 0 || p->stages > kMaxStages) return fail(h, REDVE_E_ARG, "stages must be 0..16");
+    if (p->ksize != 5) return fail(h, REDVE_E_ARG, "ksize must be 5");
+    if (p->stages > 0) {
+        if (p->nfilt < 1 || p->nfilt > REDVE_MAX_FILTERS) return fail(h, REDVE_E_ARG, "nfilt out of range");
+        if (p->nrbf < 1 || p->nrbf > REDVE_MAX_RBF) return fail(h, REDVE_E_ARG, "nrbf out of range");
+        if (!(p->gamma > 0) || !std::isfinite(p->mu0) || !std::isfinite(p->dmu))
+            return fail(h, REDVE_E_ARG, "bad RBF grid");
+        if (!p->filters || !p->rbf_w || !p->react) return fail(h, REDVE_E_ARG, "null denoiser array");
+        const int ks2 = 25;
+        for (int f = 0; f < p->stages * p->nfilt; ++f) {
+            double s = 0, a = 0;
+            for (int k = 0; k < ks2; ++k) {
+                const double v = p->filters[(size_t)f * ks2 + k];
+                if (!std::isfinite(v)) return fail(h, REDVE_E_ARG, "non-finite filter tap");
+                s += v;
+                a += fabs(v);
+            }
+            if (fabs(s) > 1e-6 * a) return fail(h, REDVE_E_ARG, "filters must have zero mean");
+        }
+        for (size_t i = 0; i < (size_t)p->stages * p->nfilt * p->nrbf; ++i)
+            if (!std::isfinite(p->rbf_w[i])) return fail(h, REDVE_E_ARG, "non-finite RBF weight");
+        for (int t = 0; t < p->stages; ++t)
+            if (!std::isfinite(p->react[t])) return fail(h, REDVE_E_ARG, "non-finite reaction weight");
+    }
+    if (p->precision != REDVE_PREC_FP32 && p->precision != REDVE_PREC_BF16)
+        return fail(h, REDVE_E_ARG, "precision must be FP32 or BF16");
+    HIP_TRY(h, hipSetDevice(h->device));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    hipFree(h->d_filt);
+    hipFree(h->d_rbfw);
+    hipFree(h->d_filt_bf16);
+    h->d_filt = h->d_rbfw = nullptr;
+    h->d_filt_bf16 = nullptr;
+    h->T = p->stages;
+    h->F = p->stages > 0 ? p->nfilt : 0;
+    h->J = p->stages > 0 ? p->nrbf : 0;
+    h->mu0 = p->mu0;
+    h->dmu = p->dmu;
+    h->gamma = p->gamma;
+    h->precision = p->precision;
+    h->theta.assign(h->T, 0.f);
+    if (h->T > 0) {
+        const size_t nf = (size_t)h->T * h->F * 25, nw = (size_t)h->T * h->F * h->J;
+        std::vector<float> f(nf), w(nw);
+        std::vector<uint16_t> fb(nf);
+        for (size_t i = 0; i < nf; ++i) {
+            f[i] = (float)p->filters[i];
+            // round-to-nearest-even FP32 -> BF16
+            uint32_t bits;
+            memcpy(&bits, &f[i], 4);
+            bits += 0x7FFFu + ((bits >> 16) & 1u);
+            fb[i] = (uint16_t)(bits >> 16);
+        }
+        for (size_t i = 0; i < nw; ++i) w[i] = (float)p->rbf_w[i];
+        for (int t = 0; t < h->T; ++t) h->theta[t] = (float)p->react[t];
+        HIP_TRY(h, hipMalloc(&h->d_filt, nf * sizeof(float)));
+        HIP_TRY(h, hipMalloc(&h->d_rbfw, nw * sizeof(float)));
+        HIP_TRY(h, hipMalloc(&h->d_filt_bf16, nf * sizeof(uint16_t)));
+        HIP_TRY(h, hipMemcpy(h->d_filt, f.data(), nf * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_rbfw, w.data(), nw * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_filt_bf16, fb.data(), nf * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
+    h->have_den = true;
+    return REDVE_OK;
+}
+
+int redve_set_extrapolation(redve_t h, int method, int L, int m) {
+    if (!h) return REDVE_E_ARG;
+    if (method < REDVE_VE_NONE || method > REDVE_VE_SVD_MPE) return fail(h, REDVE_E_ARG, "bad method");
+    if (L < 2 || L > REDVE_MAX_L) return fail(h, REDVE_E_ARG, "L must be 2..16");
+    if (m < 0) return fail(h, REDVE_E_ARG, "m must be >= 0");
+    h->method = method;
+    h->L = L;
+    h->m = m;
+    return REDVE_OK;
+}
+
+int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int extra_fp) {
+    if (!h) return REDVE_E_ARG;
+    if (cg_iters < 0 || max_fp_calls < 0 || extra_fp < 0 || !(tol >= 0) || !std::isfinite(tol))
+        return fail(h, REDVE_E_ARG, "solver settings out of range");
+    h->cg_iters = cg_iters;
+    h->max_fp = max_fp_calls;
+    h->tol = tol;
+    h->extra_fp = extra_fp;
+    return REDVE_OK;
+}
+
+int redve_apply_H(redve_t h, const float* x, int hx, int wx, float* y) {
+    if (!h) return REDVE_E_ARG;
+    if (!x || !y) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc) return rc;
+    if (!h->have_op) return fail(h, REDVE_E_STATE, "redve_set_operator was not called");
+    HIP_TRY(h, hipSetDevice(h->device));
+    LinOp op = linop_of(h);
+    launch_apply_H(op, x, hx, wx, y, h->stream);
+    LAUNCH_CHECK(h);
+    return REDVE_OK;
+}
+
+int redve_apply_Ht(redve_t h, const float* y, int hx, int wx, float* out) {
+    if (!h) return REDVE_E_ARG;
+    if (!y || !out) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc) return rc;
+    if (!h->have_op) return fail(h, REDVE_E_STATE, "redve_set_operator was not called");
+    HIP_TRY(h, hipSetDevice(h->device));
+    LinOp op = linop_of(h);
+    launch_apply_Ht(op, y, hx, wx, 1.0f, out, h->stream);
+    LAUNCH_CHECK(h);
+    return REDVE_OK;
+}
+
+int redve_apply_A(redve_t h, const float* p, int hx, int wx, float* out) {
+    if (!h) return REDVE_E_ARG;
+    if (!p || !out) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc || (rc = check_ready(h, false))) return rc;
+    HIP_TRY(h, hipSetDevice(h->device));
+    launch_apply_A(linop_of(h), p, hx, wx, out, h->stream);
+    LAUNCH_CHECK(h);
+    return REDVE_OK;
+}
+
+int redve_cg(redve_t h, const float* rhs, float* x, int hx, int wx, int iters) {
+    if (!h) return REDVE_E_ARG;
+    if (!rhs || !x || iters < 0) return fail(h, REDVE_E_ARG, "bad argument");
+    int rc = check_image(h, hx, wx);
+    if (rc || (rc = check_ready(h, false))) return rc;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    const size_t n = (size_t)hx * wx;
+    HIP_TRY(h, hipMemcpyAsync(h->ws.xa, x, n * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+    return run_cg(h, rhs, h->ws.xa, x, hx, wx, iters);
+}
+
+int redve_denoise(redve_t h, const float* x, int hx, int wx, float* out) {
+    if (!h) return REDVE_E_ARG;
+    if (!x || !out || x == out) return fail(h, REDVE_E_ARG, "bad pointers");
+    int rc = check_image(h, hx, wx);
+    if (rc) return rc;
+    if (!h->have_den) return fail(h, REDVE_E_STATE, "redve_set_denoiser was not called");
+    HIP_TRY(h, hipSetDevice(h->device));
+    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    return run_denoiser(h, x, hx, wx, out, false, nullptr);
+}
+
+int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, float* out) {
+    if (!h) return REDVE_E_ARG;
+    if (!y || !x || !out || x == out) return fail(h, REDVE_E_ARG, "bad pointers");
+    int rc = check_image(h, hx, wx);
+    if (rc || (rc = check_ready(h, true))) return rc;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    return fp_call(h, y, x, out, hx, wx);
+}
+
+int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* out,
+                      double* gamma, int* breakdown) {
+    if (!h) return REDVE_E_ARG;
+    if (!xs || !out) return fail(h, REDVE_E_ARG, "null pointer");
+    if (L < 2 || L > REDVE_MAX_L) return fail(h, REDVE_E_ARG, "L must be 2..16");
+    if (h->method == REDVE_VE_NONE) return fail(h, REDVE_E_STATE, "no extrapolation method set");
+    int rc = check_image(h, hx, wx);
+    if (rc) return rc;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if ((rc = ensure_workspace(h, hx, wx, L))) return rc;
+    const int n = hx * wx;
+    Workspace& w = h->ws;
+    for (int j = 0; j < L; ++j) {
+        launch_diff_gram(xs + (size_t)(j + 1) * n, xs + (size_t)j * n, w.U, j, L, n, w.G, w.norms,
+                         red_of(h), h->stream);
+        LAUNCH_CHECK(h);
+    }
+    launch_ve_solve(w.G, L, L, h->method, h->rank_eps, w.info, h->stream);
+    launch_ve_combine(xs, w.U, n, w.info, out, h->stream);
+    LAUNCH_CHECK(h);
+    if ((rc = read_back(h, true))) return rc;
+    if (gamma)
+        for (int j = 0; j < L; ++j) gamma[j] = h->host->info.gamma[j];
+    if (breakdown) *breakdown = h->host->info.breakdown;
+    return REDVE_OK;
+}
+
+int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, float* x, int hx,
+                int wx, redve_stats_t* st) {
+    if (!h) return REDVE_E_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (st) memset(st, 0, sizeof(*st));
+    if (!y || !x) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc || (rc = check_ready(h, true))) return rc;
+    if (hy != (hx + h->decim - 1) / h->decim || wy != (wx + h->decim - 1) / h->decim)
+        return fail(h, REDVE_E_ARG, "observation size does not match ceil(x size / decim)");
+    HIP_TRY(h, hipSetDevice(h->device));
+    const int L = h->method == REDVE_VE_NONE ? 1 : h->L;
+    if ((rc = ensure_workspace(h, hx, wx, L))) return rc;
+    Workspace& w = h->ws;
+    const int n = hx * wx;
+    const size_t bytes = sizeof(float) * n;
+    LinOp op = linop_of(h);
+    Reduction red = red_of(h);
+
+    // x0 (default: y, or decim^2 H^T y for SR)
+    if (x0)
+        HIP_TRY(h, hipMemcpyAsync(w.xa, x0, bytes, hipMemcpyDeviceToDevice, h->stream));
+    else if (h->decim == 1)
+        HIP_TRY(h, hipMemcpyAsync(w.xa, y, bytes, hipMemcpyDeviceToDevice, h->stream));
+    else {
+        launch_apply_Ht(op, y, hx, wx, (float)(h->decim * h->decim), w.xa, h->stream);
+        LAUNCH_CHECK(h);
+    }
+
+    int calls = 0, cycles = 0, breakdowns = 0, status = REDVE_OK;
+    double delta = INFINITY, gl1max = 0.0;
+    Progress prog;
+    float* x_cur = w.xa;
+
+    if (h->method == REDVE_VE_NONE) {
+        float* nxt = w.xb;
+        while (calls < h->max_fp) {
+            if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
+            ++calls;
+            launch_diff_gram(nxt, x_cur, nullptr, 0, 1, n, nullptr, w.norms, red, h->stream);
+            LAUNCH_CHECK(h);
+            if ((rc = read_back(h, false))) return rc;
+            delta = sqrt(h->host->norms[0] / h->host->norms[1]);
+            std::swap(x_cur, nxt);
+            if ((status = prog.check(delta))) break;
+            if (delta < h->tol) break;
+        }
+    } else {
+        // Algorithm 3 (full cycling): m FP calls, then L = kappa+1 more whose differences form
+        // U; extrapolate (Algorithm 1) and restart from x_(m,kappa).
+        while (calls < h->max_fp) {
+            float* base = x_cur;  // x_0 of this cycle
+            float* wbase = nullptr;
+            float* cur = base;
+            bool early = false;
+            if (h->m == 0) wbase = base;
+            for (int i = 0; i < h->m + L; ++i) {
+                if (calls >= h->max_fp) {
+                    early = true;
+                    break;
+                }
+                float* nxt = third(w.xa, w.xb, w.xc, cur, wbase ? wbase : cur);
+                if ((rc = fp_call(h, y, cur, nxt, hx, wx))) return rc;
+                ++calls;
+                if (i >= h->m) {
+                    launch_diff_gram(nxt, cur, w.U, i - h->m, L, n, w.G, w.norms, red, h->stream);
+                    LAUNCH_CHECK(h);
+                }
+                cur = nxt;
+                if (i == h->m - 1) wbase = cur;
+            }
+            if (early) {
+                x_cur = cur;
+                break;
+            }
+            launch_ve_solve(w.G, L, L, h->method, h->rank_eps, w.info, h->stream);
+            launch_ve_combine(wbase, w.U, n, w.info, wbase, h->stream);
+            LAUNCH_CHECK(h);
+            x_cur = wbase;
+            if ((rc = read_back(h, true))) return rc;
+            ++cycles;
+            if (h->host->info.breakdown)
+                ++breakdowns;
+            else
+                gl1max = std::max(gl1max, h->host->info.gamma_l1);
+            delta = sqrt(h->host->norms[0] / h->host->norms[1]);
+            if (!std::isfinite(h->host->info.gamma_l1)) {
+                status = REDVE_E_NONFINITE;
+                break;
+            }
+            if ((status = prog.check(delta))) break;
+            if (delta < h->tol) break;
+        }
+    }
+    if (status == REDVE_OK) {
+        for (int e = 0; e < h->extra_fp; ++e) {
+            float* nxt = third(w.xa, w.xb, w.xc, x_cur, x_cur);
+            if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
+            ++calls;
+            x_cur = nxt;
+        }
+    }
+    HIP_TRY(h, hipMemcpyAsync(x, x_cur, bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (st) {
+        st->fp_calls = calls;
+        st->cycles = cycles;
+        st->breakdowns = breakdowns;
+        st->status = status;
+        st->final_delta = delta;
+        st->max_gamma_l1 = gl1max;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != REDVE_OK)
+        return fail(h, status, status == REDVE_E_NONFINITE ? "iterate became non-finite"
+                                                            : "iteration diverged");
+    return REDVE_OK;
+}
+
+}  // extern "C"

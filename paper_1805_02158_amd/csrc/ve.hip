@@ -1,0 +1,293 @@
+// Vector extrapolation on the GPU (Sec. III-B): MPE (Algorithm 1), RRE (eq. (19)), SVD-MPE.
+//
+// The N x (kappa+1) difference matrix U (Algorithm 1, step 1) lives in HBM, one FP32 image per
+// column, written as each FP iterate arrives (the in-place storage remark of Sec. III-B keeps
+// kappa+2 vectors; here: x_m plus the columns). Instead of running modified Gram-Schmidt
+// (Algorithm 2) over the tall matrix, which would need kappa+1 dependent passes, each new
+// column's FP64 inner products with the previous columns are accumulated in the same pass that
+// forms it: the Gram matrix G = U^T U. Its Cholesky factor is the R of Algorithm 2 (QR of U
+// gives U^T U = R^T R with the same positive-diagonal R), and Algorithm 1 only needs R and
+// Q_{kappa-1} eta = U_{kappa-1} R_{kappa-1}^{-1} eta = U_{kappa-1} xi. So the extrapolated vector
+// is x_m + U_{kappa-1} xi, one more streaming pass. The L x L work is one FP64 thread.
+#include <math.h>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace redve {
+
+namespace {
+
+constexpr int DIFF_MAX_BLOCKS = 1024;
+
+// One pass over two consecutive iterates: u = x_new - x_old, its inner products with the
+// NC earlier columns, ||u||^2 and ||x_old||^2.
+template <int NC>
+__global__ __launch_bounds__(kThreads) void k_diff_gram(const float* __restrict__ x_new,
+                                                        const float* __restrict__ x_old,
+                                                        float* __restrict__ U, int ldG, int n,
+                                                        double* __restrict__ G,
+                                                        double* __restrict__ norms,
+                                                        Reduction red) {
+    constexpr int NV = NC + 2;
+    __shared__ double sred[NV * kThreads / 64];
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    const int stride = gridDim.x * kThreads;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const float xo = x_old[i];
+        const float uv = x_new[i] - xo;
+        if (U) U[(size_t)NC * n + i] = uv;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += (double)uv * (double)U[(size_t)k * n + i];
+        acc[NC] += (double)uv * (double)uv;
+        acc[NC + 1] += (double)xo * (double)xo;
+    }
+    block_sum<NV>(acc, sred);
+    double tot[NV];
+    if (grid_sum<NV>(acc, tot, red, blockIdx.x, gridDim.x, sred) && threadIdx.x == 0) {
+        if (G) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                G[NC * ldG + k] = tot[k];
+                G[k * ldG + NC] = tot[k];
+            }
+            G[NC * ldG + NC] = tot[NC];
+        }
+        norms[0] = tot[NC];
+        norms[1] = tot[NC + 1];
+    }
+}
+
+// ---- small dense FP64 algebra, one thread ----------------------------------------------
+
+constexpr int MAXL = 32;
+
+__device__ void back_sub(const double (*R)[MAXL], int k, const double* b, double* x) {
+    for (int i = k - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < k; ++j) s -= R[i][j] * x[j];
+        x[i] = s / R[i][i];
+    }
+}
+
+__device__ void fwd_sub_t(const double (*R)[MAXL], int k, const double* b, double* x) {
+    for (int i = 0; i < k; ++i) {
+        double s = b[i];
+        for (int j = 0; j < i; ++j) s -= R[j][i] * x[j];
+        x[i] = s / R[i][i];
+    }
+}
+
+__device__ bool full_rank(const double (*R)[MAXL], int k, double eps) {
+    if (k == 0) return true;
+    if (!(R[0][0] > 0.0)) return false;
+    for (int j = 0; j < k; ++j)
+        if (!(fabs(R[j][j]) > eps * R[0][0])) return false;
+    return true;
+}
+
+// MPE (Algorithm 1, step 2): R_{k-1} c' = -r_{k+1}, c = (c', 1), gamma = c / sum(c).
+__device__ bool mpe(const double (*R)[MAXL], int k, double eps, double* gamma) {
+    if (!full_rank(R, k, eps)) return false;
+    double c[MAXL], rhs[MAXL];
+    for (int i = 0; i < k; ++i) rhs[i] = -R[i][k];
+    back_sub(R, k, rhs, c);
+    c[k] = 1.0;
+    double s = 0.0, a = 0.0;
+    for (int i = 0; i <= k; ++i) {
+        s += c[i];
+        a += fabs(c[i]);
+    }
+    if (!(fabs(s) > 1e-12 * a)) return false;
+    for (int i = 0; i <= k; ++i) gamma[i] = c[i] / s;
+    return true;
+}
+
+// RRE (eq. (19)): R^T R d = 1, gamma = d / sum(d). A dependent last column: MPE's null vector
+// attains ||U gamma|| = 0; if MPE does not exist either, RRE_k = RRE_{k-1} (Sec. III-B).
+__device__ int rre(const double (*R)[MAXL], int k, double eps, double* gamma) {
+    while (true) {
+        if (full_rank(R, k + 1, eps)) {
+            double ones[MAXL], w[MAXL], d[MAXL];
+            for (int i = 0; i <= k; ++i) ones[i] = 1.0;
+            fwd_sub_t(R, k + 1, ones, w);
+            back_sub(R, k + 1, w, d);
+            double s = 0.0;
+            for (int i = 0; i <= k; ++i) s += d[i];
+            for (int i = 0; i <= k; ++i) gamma[i] = d[i] / s;
+            return k;
+        }
+        if (k == 0) {
+            gamma[0] = 1.0;
+            return 0;
+        }
+        if (mpe(R, k, eps, gamma)) return k;
+        --k;
+    }
+}
+
+// SVD-MPE (Sec. III-B): gamma = v / sum(v), v the right singular vector of the smallest
+// singular value of R, by one-sided Jacobi rotations on the columns of R.
+__device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma) {
+    const int n = k + 1;
+    double A[MAXL][MAXL], V[MAXL][MAXL];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            A[i][j] = (j >= i) ? R[i][j] : 0.0;
+            V[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    al += A[i][p] * A[i][p];
+                    be += A[i][q] * A[i][q];
+                    ga += A[i][p] * A[i][q];
+                }
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                off = fmax(off, fabs(ga) / sqrt(al * be));
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                for (int i = 0; i < n; ++i) {
+                    const double ap = A[i][p], aq = A[i][q];
+                    A[i][p] = c * ap - s * aq;
+                    A[i][q] = s * ap + c * aq;
+                    const double vp = V[i][p], vq = V[i][q];
+                    V[i][p] = c * vp - s * vq;
+                    V[i][q] = s * vp + c * vq;
+                }
+            }
+        if (off <= 1e-15) break;
+    }
+    int jmin = 0;
+    double smin = INFINITY;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += A[i][j] * A[i][j];
+        if (s < smin) {
+            smin = s;
+            jmin = j;
+        }
+    }
+    double s = 0.0, a = 0.0;
+    for (int i = 0; i < n; ++i) {
+        s += V[i][jmin];
+        a += fabs(V[i][jmin]);
+    }
+    if (!(fabs(s) > 1e-12 * a)) return false;
+    for (int i = 0; i < n; ++i) gamma[i] = V[i][jmin] / s;
+    return true;
+}
+
+__global__ void k_ve_solve(const double* __restrict__ G, int ldG, int L, int method,
+                           double rank_eps, VeInfo* __restrict__ info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // Cholesky G = R^T R (upper R). A column whose pivot falls under the rank threshold gets
+    // R_ii = 0 and a zero row, as modified Gram-Schmidt gives a zero q_i for it.
+    double R[MAXL][MAXL];
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < L; ++j) R[i][j] = 0.0;
+    for (int i = 0; i < L; ++i) {
+        double d = G[i * ldG + i];
+        for (int k = 0; k < i; ++k) d -= R[k][i] * R[k][i];
+        double rii = sqrt(fmax(d, 0.0));
+        if (i > 0 && !(rii > rank_eps * R[0][0])) rii = 0.0;
+        R[i][i] = rii;
+        for (int j = i + 1; j < L; ++j) {
+            double s = G[i * ldG + j];
+            for (int k = 0; k < i; ++k) s -= R[k][i] * R[k][j];
+            R[i][j] = rii > 0.0 ? s / rii : 0.0;
+        }
+    }
+    double gamma[MAXL];
+    int k = L - 1;
+    bool ok;
+    if (method == 1) {
+        ok = mpe(R, k, rank_eps, gamma);
+    } else if (method == 2) {
+        k = rre(R, k, rank_eps, gamma);
+        ok = true;
+    } else {
+        ok = svd_mpe(R, k, gamma);
+    }
+    for (int i = 0; i < MAXL; ++i) {
+        info->xi[i] = 0.0;
+        info->gamma[i] = 0.0;
+    }
+    if (!ok) {
+        // no extrapolation: x_m + sum of all L differences = the last FP iterate
+        for (int j = 0; j < L; ++j) info->xi[j] = 1.0;
+        info->ncols = L;
+        info->breakdown = 1;
+        info->kappa_used = L - 1;
+        info->gamma_l1 = 0.0;
+        return;
+    }
+    // Algorithm 1, step 3: xi_0 = 1 - gamma_0, xi_j = xi_{j-1} - gamma_j (j < kappa)
+    double acc = 1.0, l1 = 0.0;
+    for (int j = 0; j < k; ++j) {
+        acc -= gamma[j];
+        info->xi[j] = acc;
+    }
+    for (int j = 0; j <= k; ++j) {
+        info->gamma[j] = gamma[j];
+        l1 += fabs(gamma[j]);
+    }
+    info->ncols = k;
+    info->breakdown = 0;
+    info->kappa_used = k;
+    info->gamma_l1 = l1;
+}
+
+// Algorithm 1, step 4: x_(m,kappa) = x_m + U_{kappa-1} xi (= x_m + Q_{kappa-1} eta).
+__global__ __launch_bounds__(kThreads) void k_ve_combine(const float* __restrict__ x_m,
+                                                         const float* __restrict__ U, int n,
+                                                         const VeInfo* __restrict__ info,
+                                                         float* __restrict__ out) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int nc = info->ncols;
+    double acc = (double)x_m[i];
+    for (int j = 0; j < nc; ++j) acc += info->xi[j] * (double)U[(size_t)j * n + i];
+    out[i] = (float)acc;
+}
+
+}  // namespace
+
+int diff_grid(int n) {
+    const int b = (n + kThreads - 1) / kThreads;
+    return b < DIFF_MAX_BLOCKS ? (b > 0 ? b : 1) : DIFF_MAX_BLOCKS;
+}
+
+void launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, int ldG, int n,
+                      double* G, double* norms, Reduction red, hipStream_t st) {
+    const int g = diff_grid(n);
+#define REDVE_DG(J)                                                                              \
+    case J:                                                                                      \
+        k_diff_gram<J><<<g, kThreads, 0, st>>>(x_new, x_old, U, ldG, n, G, norms, red);          \
+        break;
+    switch (j) {
+        REDVE_DG(0) REDVE_DG(1) REDVE_DG(2) REDVE_DG(3) REDVE_DG(4) REDVE_DG(5) REDVE_DG(6)
+        REDVE_DG(7) REDVE_DG(8) REDVE_DG(9) REDVE_DG(10) REDVE_DG(11) REDVE_DG(12) REDVE_DG(13)
+        REDVE_DG(14) REDVE_DG(15)
+        default: break;
+    }
+#undef REDVE_DG
+}
+
+void launch_ve_solve(const double* G, int ldG, int L, int method, double rank_eps, VeInfo* info,
+                     hipStream_t st) {
+    k_ve_solve<<<1, 64, 0, st>>>(G, ldG, L, method, rank_eps, info);
+}
+
+void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,
+                       hipStream_t st) {
+    k_ve_combine<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(x_m, U, n, info, out);
+}
+
+}  // namespace redve

@@ -1,0 +1,395 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by element.
+
+Inputs are seeded and synthetic; the GPU receives the FP32 rounding of the oracle's inputs and
+the oracle recomputes on those same FP32 values in FP64. Tolerances (relative L2):
+  single operators (blur, adjoint, A)  2e-6   FP32 sums of <= 225 products
+  CG, denoiser, one FP call            2e-5   FP32 recurrences over 15 iterations / 5 stages
+  solves                               1e-4   the FP32 bar for results
+Extrapolated vectors can be ill-conditioned functions of the iterates (sum |gamma| reaches 1e4
+in early super-resolution cycles): rounding the FP64 oracle's own iterates to FP32 after every
+FP call then moves its result by more than 1e-4. For a solve stopped at a fixed FP-call count
+the bound is max(1e-4, 3 x that movement), which the test measures with the oracle; converged
+results are held to 1e-4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def restorer(prob=None, **kw):
+    from paper_1805_02158_amd import Restorer
+    r = Restorer(0)
+    if prob is not None:
+        r.configure(prob, **kw)
+    return r
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+PSFS = {"u9": W.psf_uniform(9), "g7": W.psf_gaussian(7, 1.6),
+        "asym": np.random.default_rng(5).standard_normal((5, 3))}
+SHAPES = [(64, 64), (37, 53), (5, 7), (2, 2), (16, 33), (256, 256), (300, 130)]
+
+
+# ------------------------------------------------------------------ operators
+
+
+@pytest.mark.parametrize("psf", list(PSFS))
+@pytest.mark.parametrize("decim", [1, 3])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_operators(torch, orc, psf, decim, shape):
+    say("operators", psf, decim, shape)
+    k = PSFS[psf]
+    r = restorer()
+    r.set_operator(k, decim).set_noise(5.0 if decim > 1 else math.sqrt(2)).set_lambda(0.02)
+    rng = np.random.default_rng(hash((psf, decim, shape)) % 2**32)
+    x = f32(rng.uniform(0, 255, shape))
+    ky = f32(k)
+    y = host(r.apply_H(dev(torch, x)))
+    assert rel(y, orc.apply_H(x, ky, decim)) <= 2e-6
+    z = f32(rng.standard_normal(orc.lr_shape(*shape, decim)) * 50)
+    ht = host(r.apply_Ht(dev(torch, z), *shape))
+    assert rel(ht, orc.apply_Ht(z, shape, ky, decim)) <= 2e-6
+    sig = 5.0 if decim > 1 else math.sqrt(2)
+    a = host(r.apply_A(dev(torch, x)))
+    assert rel(a, orc.apply_A(x, ky, decim, sig, 0.02)) <= 2e-6
+
+
+@pytest.mark.parametrize("shape,psf,decim", [((64, 64), "u9", 1), ((37, 53), "g7", 3),
+                                             ((256, 256), "u9", 1), ((8, 8), "g7", 1)])
+def test_cg(torch, orc, shape, psf, decim):
+    say("cg", shape, psf, decim)
+    k = PSFS[psf]
+    sig = 5.0 if decim > 1 else math.sqrt(2)
+    r = restorer()
+    r.set_operator(k, decim).set_noise(sig).set_lambda(0.02)
+    rng = np.random.default_rng(7)
+    x0 = f32(rng.uniform(0, 255, shape))
+    rhs = f32(orc.apply_A(rng.uniform(0, 255, shape), k, decim, sig, 0.02))
+    for iters in (0, 1, 15):
+        xg = host(r.cg(dev(torch, rhs), dev(torch, x0), iters))
+        xo = orc.cg(rhs, x0, f32(k), decim, sig, 0.02, iters)
+        assert rel(xg, xo) <= 2e-5, iters
+
+
+# ------------------------------------------------------------------ denoiser
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (37, 53), (2, 2), (3, 5), (17, 16), (256, 256)])
+def test_denoiser(torch, orc, shape):
+    say("denoiser", shape)
+    d = W.make_denoiser()
+    r = restorer()
+    r.set_denoiser(d)
+    x = f32(W.make_image(*shape, 77) + 5 * W.make_noise(shape, 78))
+    g = host(r.denoise(dev(torch, x)))
+    o = orc.denoise(x, orc.Denoiser(d))
+    assert rel(g, o) <= 2e-5
+    assert np.abs(g - o).max() <= 2e-3
+
+
+def test_denoiser_constant_and_identity(torch, orc):
+    say("denoiser constant")
+    r = restorer()
+    r.set_denoiser(W.make_denoiser())
+    for c in (0.0, 37.5, 255.0):
+        x = np.full((40, 24), c)
+        assert np.abs(host(r.denoise(dev(torch, x))) - c).max() <= 1e-3 * max(c, 1)
+    r.set_denoiser(W.identity_denoiser())
+    x = np.random.default_rng(1).uniform(0, 255, (19, 23))
+    assert np.array_equal(host(r.denoise(dev(torch, x))), f32(x))
+
+
+# ------------------------------------------------------------------ one FP call
+
+
+@pytest.mark.parametrize("name", ["tiny", "c0"])
+def test_fp_step(torch, orc, name):
+    say("fp_step", name)
+    prob = W.problem(name)
+    op = orc.OracleProblem(prob, y=f32(orc.OracleProblem(prob).y))
+    r = restorer(prob)
+    x = f32(op.y)
+    for _ in range(3):
+        xg = host(r.fp_step(dev(torch, op.y), dev(torch, x)))
+        xo = op.fp(x)
+        say(f"  rel L2 {rel(xg, xo):.2e}, relative to the step {rel(xg - x, xo - x):.2e}")
+        assert rel(xg, xo) <= 2e-5
+        assert rel(xg - x, xo - x) <= 1e-4
+        x = f32(xo)
+
+
+# ------------------------------------------------------------------ extrapolation
+
+
+@pytest.mark.parametrize("method", ["mpe", "rre", "svd_mpe"])
+@pytest.mark.parametrize("L", [2, 5, 8])
+def test_extrapolate(torch, orc, method, L):
+    say("extrapolate", method, L)
+    prob = W.problem("tiny")
+    op = orc.OracleProblem(prob)
+    xs = [f32(op.y)]
+    for _ in range(L):
+        xs.append(f32(op.fp(xs[-1])))
+    r = restorer(prob, method=method, L=L)
+    xg, gam, bd = r.extrapolate(dev(torch, np.stack(xs)))
+    xo, go, bo = orc.ve_step(xs, method)
+    assert bd == bo
+    assert rel(host(xg), xo.reshape(op.shape)) <= 2e-6
+    if go is not None and len(go) == L:
+        assert np.abs(gam - go).max() <= 1e-6 * max(1.0, np.abs(go).max())
+
+
+def test_extrapolate_linear_exactness(torch, orc):
+    """Sec. III-A through the GPU path: a linear iteration with 3 distinct eigenvalues is
+    extrapolated to its fixed point from kappa + 2 = 5 iterates (L = 4)."""
+    say("extrapolate linear")
+    rng = np.random.default_rng(3)
+    shape = (32, 32)
+    N = shape[0] * shape[1]
+    v = [rng.standard_normal(N) for _ in range(3)]
+    lam = [0.8, -0.5, 0.3]
+    xstar = rng.uniform(50, 200, N)
+    coef = rng.standard_normal(3) * 5
+    xs = [xstar + sum(coef[i] * lam[i] ** k * v[i] for i in range(3)) for k in range(5)]
+    xs32 = [f32(x) for x in xs]
+    for method in ("mpe", "rre", "svd_mpe"):
+        r = restorer()
+        r.set_extrapolation(method, 4, 0)
+        xg, _, bd = r.extrapolate(dev(torch, np.stack([x.reshape(shape) for x in xs32])))
+        assert not bd
+        # L = 4 columns of differences span 3 modes: rank 3 -> exact up to FP32 input rounding
+        assert rel(host(xg).ravel(), xstar) <= 1e-5, method
+
+
+# ------------------------------------------------------------------ whole solves
+
+
+def _oracle_solve(orc, prob, y32, method, L, m, tol, calls):
+    op = orc.OracleProblem(prob, y=y32)
+    return orc.solve(op, method, L=L, m=m, tol=tol, max_calls=calls), op
+
+
+class _RoundedState:
+    """The oracle's FP map with its output rounded to FP32 (the state a FP32 solver keeps)."""
+
+    def __init__(self, op):
+        self.op, self.shape = op, op.shape
+
+    def x0(self):
+        return f32(self.op.x0())
+
+    def fp(self, x):
+        return f32(self.op.fp(x))
+
+
+def _bound(orc, op, ref, method, L, m, calls):
+    """max(1e-4, 3 x the movement of the oracle's result under FP32 rounding of its state)."""
+    if method == "none":
+        return 1e-4
+    moved = orc.solve(_RoundedState(op), method, L=L, m=m, tol=0.0, max_calls=calls)
+    floor = rel(moved.x, ref.x)
+    say(f"  FP32-state sensitivity of the oracle: {floor:.2e}")
+    return max(1e-4, 3.0 * floor)
+
+
+@pytest.mark.parametrize("name,method,L,calls", [("c0", "none", 5, 20), ("c0", "rre", 5, 20),
+                                                 ("c0", "mpe", 5, 20), ("c0", "svd_mpe", 5, 20),
+                                                 ("tiny", "rre", 3, 13), ("tiny", "mpe", 4, 7)])
+def test_solve_fixed_schedule(torch, orc, name, method, L, calls):
+    say("solve", name, method, L, calls)
+    prob = W.problem(name)
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref, op = _oracle_solve(orc, prob, y32, method, L, 0, 0.0, calls)
+    r = restorer(prob, method=method, L=L, m=0, tol=0.0, max_fp_calls=calls)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    assert st["fp_calls"] == ref.calls and st["cycles"] == ref.cycles
+    assert st["breakdowns"] == ref.breakdowns
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle: {err:.2e}")
+    assert err <= _bound(orc, op, ref, method, L, 0, calls)
+
+
+def test_solve_m_positive(torch, orc):
+    say("solve m>0")
+    prob = W.problem("tiny")
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref, op = _oracle_solve(orc, prob, y32, "rre", 3, 2, 0.0, 16)
+    r = restorer(prob, method="rre", L=3, m=2, tol=0.0, max_fp_calls=16)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    assert st["fp_calls"] == 16 and st["cycles"] == ref.cycles == 3
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle: {err:.2e}")
+    assert err <= _bound(orc, op, ref, "rre", 3, 2, 16)
+
+
+@pytest.mark.parametrize("method", ["rre", "mpe"])
+def test_solve_c1_full_size(torch, orc, method):
+    """The benchmark workload (256x256, uniform 9x9, L = 5) at its launch configuration, at a
+    fixed schedule of two cycles."""
+    say("solve c1", method)
+    prob = W.problem("c1")
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref, op = _oracle_solve(orc, prob, y32, method, 5, 0, 0.0, 10)
+    r = restorer(prob, method=method, tol=0.0, max_fp_calls=10)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    assert st["cycles"] == 2
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle: {err:.2e}")
+    assert err <= _bound(orc, op, ref, method, 5, 0, 10)
+
+
+def test_solve_sr(torch, orc):
+    """3x super-resolution (Gaussian 7x7 + decimation, sigma 5) with RRE, L = 8, on a 130x97
+    image (LR 44x33), one cycle plus a partial one."""
+    say("solve sr")
+    x_true = W.make_image(130, 97, 1234)
+    prob = W.Problem("sr", x_true, W.psf_gaussian(7, 1.6), 3, 5.0, 0.02,
+                     W.make_noise(W.lr_shape(130, 97, 3), 4321), 15, W.make_denoiser(),
+                     "rre", 8, 0, 0.0, 11)
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref, op = _oracle_solve(orc, prob, y32, "rre", 8, 0, 0.0, 11)
+    r = restorer(prob)
+    x, st = r.solve(dev(torch, y32), 130, 97)
+    assert st["fp_calls"] == 11 and st["cycles"] == 1
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle: {err:.2e}")
+    assert err <= _bound(orc, op, ref, "rre", 8, 0, 11)
+
+
+def test_solve_identity_denoiser(torch, orc):
+    say("solve identity denoiser")
+    prob = W.problem("tiny")
+    prob.denoiser = W.identity_denoiser()
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref, op = _oracle_solve(orc, prob, y32, "rre", 5, 0, 0.0, 10)
+    r = restorer(prob, method="rre", L=5, tol=0.0, max_fp_calls=10)
+    x, _ = r.solve(dev(torch, y32), *prob.hr_shape)
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle: {err:.2e}")
+    assert err <= _bound(orc, op, ref, "rre", 5, 0, 10)
+
+
+def test_solve_converges_to_fixed_point(torch, orc):
+    """Tolerance-driven RRE solve of the benchmark workload: the FP64 RED gradient at the GPU
+    result has fallen by 1e3 and the result matches the oracle's fixed point."""
+    say("solve converged c1")
+    prob = W.problem("c1")
+    op = orc.OracleProblem(prob)
+    y32 = f32(op.y)
+    op = orc.OracleProblem(prob, y=y32)
+    r = restorer(prob, method="rre", tol=1e-5, max_fp_calls=200)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    xg = host(x)
+    say("  stats", st)
+    g0 = np.linalg.norm(op.gradient(op.x0()))
+    assert np.linalg.norm(op.gradient(xg)) <= 1e-3 * g0
+    ref = orc.solve(op, "rre", L=5, m=0, tol=1e-8, max_calls=200)
+    err = rel(xg, ref.x)
+    say(f"  rel L2 vs oracle fixed point: {err:.2e}")
+    assert err <= 1e-4
+    assert abs(orc.psnr(xg, prob.x_true) - orc.psnr(ref.x, prob.x_true)) <= 0.01
+
+
+def test_solve_sr_converges(torch, orc):
+    """3x super-resolution solved to tolerance: the result matches the oracle's fixed point."""
+    say("solve sr converged")
+    x_true = W.make_image(130, 97, 1234)
+    prob = W.Problem("sr", x_true, W.psf_gaussian(7, 1.6), 3, 5.0, 0.02,
+                     W.make_noise(W.lr_shape(130, 97, 3), 4321), 15, W.make_denoiser(),
+                     "rre", 8, 0, 1e-5, 400)
+    y32 = f32(orc.OracleProblem(prob).y)
+    op = orc.OracleProblem(prob, y=y32)
+    r = restorer(prob)
+    x, st = r.solve(dev(torch, y32), 130, 97)
+    say("  stats", st)
+    ref = orc.solve(op, "rre", L=8, m=0, tol=1e-9, max_calls=400)
+    err = rel(host(x), ref.x)
+    say(f"  rel L2 vs oracle fixed point: {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_solve_deterministic(torch):
+    say("determinism")
+    prob = W.problem("c0")
+    import oracle
+    y32 = f32(oracle.OracleProblem(prob).y)
+    r = restorer(prob, method="rre", tol=0.0, max_fp_calls=10)
+    a, _ = r.solve(dev(torch, y32), 64, 64)
+    b, _ = r.solve(dev(torch, y32), 64, 64)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ argument checking
+
+
+def test_errors(torch):
+    import paper_1805_02158_amd as P
+    say("errors")
+    r = restorer()
+    y = torch.zeros((8, 8), device="cuda")
+    with pytest.raises(P.RedveError) as e:
+        r.solve(y, 8, 8)
+    assert e.value.code == P.E_STATE
+    with pytest.raises(P.RedveError) as e:
+        r.set_operator(np.ones((4, 4)) / 16, 1)
+    assert e.value.code == P.E_ARG
+    with pytest.raises(P.RedveError) as e:
+        r.set_extrapolation("rre", 1, 0)
+    assert e.value.code == P.E_ARG
+    with pytest.raises(P.RedveError) as e:
+        r.set_noise(0.0)
+    assert e.value.code == P.E_ARG
+    d = W.make_denoiser()
+    bad = W.DenoiserParams(d.stages, d.nfilt, d.ksize, d.nrbf, d.mu0, d.dmu, d.gamma,
+                           d.filters + 0.1, d.rbf_w, d.react)
+    with pytest.raises(P.RedveError) as e:
+        r.set_denoiser(bad)
+    assert e.value.code == P.E_ARG
+    prob = W.problem("tiny")
+    r.configure(prob)
+    with pytest.raises(P.RedveError) as e:
+        r.solve(torch.zeros((10, 10), device="cuda"), 32, 32)  # y shape mismatch
+    assert e.value.code == P.E_ARG
+    with pytest.raises(P.RedveError) as e:
+        r.solve(torch.zeros((1, 1), device="cuda"), 1, 1)
+    assert e.value.code == P.E_ARG
