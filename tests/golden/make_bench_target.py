@@ -1,0 +1,64 @@
+"""Writes bench_target_c1.json: the oracle-converged PSNR of the 256x256 deblurring workload.
+
+Calls only the FP64 oracle and the seeded workload generator. The target is the PSNR of plain
+FP (eq. (7)) run until the relative change of consecutive iterates is below 1e-6 (cap 1000 FP
+calls). For context it also records, for the oracle itself, the FP-call count after which
+every returned vector stays within 0.05 dB of that PSNR (plain FP, RRE and MPE with L = 5).
+
+Run: python tests/golden/make_bench_target.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workload as W  # noqa: E402
+
+BAND_DB = 0.05
+
+
+def stable_from(trace, target, band=BAND_DB):
+    """Smallest FP-call count from which every returnable vector is within `band` dB."""
+    n_star = None
+    for calls, p in trace:
+        if abs(p - target) <= band:
+            if n_star is None:
+                n_star = calls
+        else:
+            n_star = None
+    return n_star
+
+
+def main():
+    prob = W.problem("c1")
+    op = oracle.OracleProblem(prob)
+    t0 = time.time()
+    ref = oracle.solve(op, "none", tol=1e-6, max_calls=1000)
+    psnr_star = oracle.psnr(ref.x, prob.x_true)
+    out = {
+        "workload": "c1: 256x256 synthetic image, uniform 9x9 blur, sigma sqrt(2), lambda 0.02, "
+                    "15 CG iterations, seeded TNRD-style denoiser (5 stages x 24 filters)",
+        "psnr_star_db": psnr_star,
+        "psnr_input_db": oracle.psnr(op.y, prob.x_true),
+        "oracle_fp_calls_to_1e-6": ref.calls,
+        "band_db": BAND_DB,
+        "oracle_threads": oracle.num_threads(),
+    }
+    for method in ("none", "rre", "mpe"):
+        tr = []
+        oracle.solve(op, method, L=5, m=0, tol=1e-6, max_calls=300,
+                     on_vector=lambda c, v: tr.append((c, oracle.psnr(v, prob.x_true))))
+        out[f"oracle_n_star_{method}"] = stable_from(tr, psnr_star)
+    out["seconds"] = round(time.time() - t0, 1)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bench_target_c1.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()
