@@ -9,32 +9,25 @@ namespace redve {
 
 constexpr int kThreads = 256;  // threads per workgroup of every tiled kernel (4 waves)
 constexpr int kMaxStages = 16; // denoiser stages
+constexpr int kMaxRbfWindow = 16;  // half-width (in centres) of the exact RBF window
 
-// Scalars of one CG solve, device resident. Read by every workgroup of the next kernel;
-// written by the last workgroup of the kernel that finishes the corresponding reduction.
-struct CgScalars {
-    double rho0;   // r.r of the current residual
-    double pq;     // p.(A p)
-    double alpha;  // step length
-    double beta;   // direction update weight
-};
+constexpr int kMaxRedBlocks = 1024;  // workgroups of any kernel that publishes partial sums
+constexpr int kMaxPsf = 15;
 
-// Grid-wide deterministic reduction: per-workgroup FP64 partials plus a completion counter.
-// The last workgroup to finish sums the partials in workgroup order and resets the counter.
-struct Reduction {
-    double* partials;   // nvals * capacity doubles
-    unsigned* counter;  // one counter, zero between kernels
-    int capacity;       // max workgroups
-};
-
-// Linear operator H = S B (eq. (1)) and the CG pieces (footnote to eq. (7)).
+// Linear operator H = S B (eq. (1)) and the CG pieces (footnote to eq. (7)). Passed by value:
+// the PSF taps live in kernel-argument registers. A rank-1 PSF (both blurs of the paper's
+// experiments) is applied as a column pass and a row pass: psf[a][b] = col[a] * row[b].
 struct LinOp {
-    const float* psf;  // device copy, kh*kw, row-major
+    const float* psf;  // device copy, kh*kw, row-major (general 2-D path)
+    const double* psf64;
     int kh, kw, decim;
+    int separable;
     float inv_s2;      // 1 / sigma^2
     float lambda;
     double inv_s2_d;   // the same in FP64 (residual accumulation)
     double lambda_d;
+    float row[kMaxPsf], col[kMaxPsf];
+    double row_d[kMaxPsf], col_d[kMaxPsf];
 };
 
 // Denoiser parameters on the device (FP32; BF16 copies of the filters for the MFMA path).
@@ -46,6 +39,7 @@ struct TnrdDev {
     float theta[kMaxStages]; // reaction weights theta_t (kernel arguments)
     const uint16_t* filt_bf16;  // T*F*25 bf16 bits
     int precision;
+    int kwin;                   // RBF window half-width: centres beyond it add < 1e-12 w
 };
 
 // ---- launchers (all asynchronous on `st`) ----------------------------------------------
@@ -53,50 +47,63 @@ void launch_apply_H(const LinOp& op, const float* x, int H, int W, float* y, hip
 void launch_apply_Ht(const LinOp& op, const float* y, int H, int W, float scale, float* out,
                      hipStream_t st);
 void launch_apply_A(const LinOp& op, const float* p, int H, int W, float* out, hipStream_t st);
-int linop_grid(int H, int W);  // workgroups of the tiled CG kernels
-// CG on A x = rhs warm-started at x_in (generic right-hand side).
-void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, float* p,
-                    int H, int W, Reduction red, CgScalars* sc, hipStream_t st);
+
+// CG with reductions split across kernels: every reducing kernel publishes FP64 partials per
+// workgroup (grid <= kMaxRedBlocks) and the next kernel re-sums them. `Partials` names a
+// published array (value v at p + v * kMaxRedBlocks) and the number of workgroups that wrote it.
+struct Partials {
+    double* p;
+    int n;
+};
+// CG start for A x = rhs warm-started at x_in (generic right-hand side): r = rhs - A x_in.
+void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, int H, int W,
+                    hipStream_t st);
 // CG start of one FP call: r = H^T (y - H x) / sigma^2 + lambda s, s = f(x) - x (may be null).
-void launch_cg_init_fp(const LinOp& op, const double* psf64, const float* x, const float* y,
-                       const float* s, float* r, float* p, int H, int W, Reduction red,
-                       CgScalars* sc, hipStream_t st);
-void launch_cg_q(const LinOp& op, const float* r, const float* p_old, float* p_new, float* q,
-                 int H, int W, Reduction red, CgScalars* sc, hipStream_t st);
-// d (+)= alpha p, r -= alpha q; with x_out != null: x_out = x_in + d instead of storing d.
-void launch_cg_update(float* d, float* r, const float* p, const float* q, int n, int first,
-                      const float* x_in, float* x_out, Reduction red, CgScalars* sc,
+void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
+                       int H, int W, hipStream_t st);
+// w0 = A r0; publishes r0.r0 and w0.r0.
+Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, double* part,
                       hipStream_t st);
-int cg_update_grid(int n);
-void launch_axpb(const float* b0, const float* u, float lambda, float* out, int n,
-                 hipStream_t st);
+// One single-reduction CG iteration k (see linear.hip); hist_prev holds (alpha, rho) of
+// iteration k-1, hist_cur receives those of iteration k. The last iteration writes
+// x_out = x_in + d only.
+Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const float* r_in,
+                        const float* w_in, const float* s_in, float* r_out, float* w_out,
+                        float* s_out, float* p, float* d, const float* x_in, float* x_out,
+                        Partials rm, const double* hist_prev, double* hist_cur, double* part,
+                        hipStream_t st);
 
 int tnrd_grid(int H, int W);
+size_t tnrd_smem_bytes(int F, int J);
 // One denoiser stage in residual form: w_t = w_{t-1} - sum_i K_i^T phi_i(K_i (f + w_{t-1}))
 // - theta_t w_{t-1}, with w = u - f (w_prev null: w_0 = 0). out_mode 0 writes w_t, 1 writes
 // f + w_t (= u_t).
 void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st);
 
-// Differences, Gram row and norms of two consecutive iterates.
+// Differences, Gram row and norms of two consecutive iterates, as published partials:
 //   u = x_new - x_old (stored in U + j*n when U != nullptr),
-//   G[j][i] = G[i][j] = u . U_i for i < j, G[j][j] = u . u,
-//   norms[0] = ||u||^2, norms[1] = ||x_old||^2.
-int diff_grid(int n);
-void launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, int ldG, int n,
-                      double* G, double* norms, Reduction red, hipStream_t st);
-// Small FP64 solve on the L x L Gram matrix: gamma, xi, number of columns to combine, info.
+//   values k < j: u . U_k;  value j: u . u;  value j+1: x_old . x_old.
+// Writes (j + 2) arrays of kMaxRedBlocks partials at part; returns the workgroup count.
+int launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, int n, double* part,
+                     hipStream_t st);
+// Result of the small FP64 solve on the L x L Gram matrix.
 struct VeInfo {
     double xi[32];
     double gamma[32];
     double gamma_l1;
+    double uu, xx;   // ||u_last||^2, ||x_prev||^2 of the last difference (relative change)
     int ncols;       // columns of U combined (kappa, or L on breakdown)
     int breakdown;   // 1 if the extrapolation did not exist
     int kappa_used;  // kappa after any RRE column drops
     int pad;
 };
-void launch_ve_solve(const double* G, int ldG, int L, int method, double rank_eps, VeInfo* info,
-                     hipStream_t st);
+// Sums the partials of the L difference passes (column j's at part + j * win_stride, each
+// written by nblk workgroups) into G, then Cholesky / MPE / RRE / SVD-MPE.
+void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int method,
+                     double rank_eps, VeInfo* info, hipStream_t st);
+// Sums the partials of a single difference pass (j = 0) into info->uu, info->xx.
+void launch_delta(const double* part, int nblk, VeInfo* info, hipStream_t st);
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,
                        hipStream_t st);
 

@@ -3,9 +3,11 @@
 //
 // Layout: images row-major FP32, dense rows. B is periodic (block-circulant).
 // The CG matrix-vector product q = (H^T H / sigma^2 + lambda I) p is an LDS-tiled stencil: a
-// workgroup loads its TH x TW tile of p plus a 2r halo (wrapped), forms B p on the tile plus an
-// r halo, masks it by the decimation pattern S^T S, and applies B^T on the tile. One HBM read
-// of p (plus halo) and one write of q per iteration; the dot products are FP64.
+// workgroup loads a TH x TW tile of p plus a 2r halo (wrapped), forms B p on the tile plus an
+// r halo, masks it by the decimation pattern S^T S, and applies B^T on the tile. A rank-1 PSF
+// is applied as separate column and row passes (2 (kh + kw) taps per pixel instead of
+// 2 kh kw). Reducing kernels loop over tiles with at most kMaxRedBlocks workgroups, publish
+// one FP64 partial per workgroup, and the next kernel re-sums them (see reduce.h).
 #include "internal.h"
 #include "reduce.h"
 
@@ -13,9 +15,10 @@ namespace redve {
 
 namespace {
 
-constexpr int TH = 16, TW = 32;  // CG tile: 512 outputs per 256-thread workgroup
-constexpr int MAXR = 7;           // PSF half-size limit (15 x 15)
+constexpr int TH = 16, TW = 16;  // CG tile: 256 outputs per 256-thread workgroup
+constexpr int MAXR = (kMaxPsf - 1) / 2;
 constexpr int PH = TH + 4 * MAXR, PW = TW + 4 * MAXR;
+constexpr int NO = TH * TW / kThreads;  // outputs per thread
 
 __device__ inline int wrapi(int i, int n) {
     int r = i % n;
@@ -62,105 +65,180 @@ __global__ __launch_bounds__(kThreads) void k_apply_Ht(const float* __restrict__
     out[idx] = scale * acc;
 }
 
-// Shared body of the tiled A-product. Loads P = src0 + beta * src1 (src1 may be null) on the
-// tile + 2r halo, computes q = A P on the tile. Returns P and q at the thread's outputs.
-struct TileIO {
-    float p[TH * TW / kThreads];
-    float q[TH * TW / kThreads];
+// LDS scratch of one tile product: three regions of PH x PW.
+struct TileSmem {
+    float p[PH * PW];  // P region: tile + 2r halo
+    float h[PH * PW];  // row-pass results
+    float t[PH * PW];  // masked B P on tile + r halo
 };
 
-__device__ inline void tile_apply_A(const LinOp op, const float* __restrict__ src0,
-                                    const float* __restrict__ src1, float beta, int H, int W,
-                                    int r0, int c0, float* sp, float* sb, TileIO& io) {
-    const int rh = op.kh / 2, rw = op.kw / 2;
-    const int ph = TH + 4 * rh, pw = TW + 4 * rw;  // P region
+// q = A P on the tile at (r0, c0). P must already be in sm.p on the tile + 2r halo (region
+// origin (r0 - 2rh, c0 - 2rw)). Returns P and q at the thread's NO outputs. RS > 0: separable
+// PSF of compile-time radius RS (fully unrolled passes); RS == 0: runtime sizes (separable or
+// general 2-D).
+template <int RS>
+__device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, int c0,
+                                       TileSmem& sm, float (&pc)[NO], float (&q)[NO]) {
+    const int rh = RS ? RS : op.kh / 2, rw = RS ? RS : op.kw / 2;
+    const int kh = 2 * rh + 1, kw = 2 * rw + 1;
+    const int ph = TH + 4 * rh;                    // P region rows
     const int bh = TH + 2 * rh, bw = TW + 2 * rw;  // B P region
-    for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
-        const int pr = e / pw, pc = e % pw;
-        const size_t g = (size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W);
-        float v = src0[g];
-        if (src1) v += beta * src1[g];
-        sp[pr * PW + pc] = v;
-    }
-    __syncthreads();
     const int s = op.decim;
-    for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
-        const int br = e / bw, bc = e % bw;
-        const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
-        float acc = 0.f;
-        if (gr % s == 0 && gc % s == 0) {
-            for (int a = -rh; a <= rh; ++a) {
-                const float* prow = sp + (br + rh - a) * PW + bc + rw;
-                const float* krow = op.psf + (a + rh) * op.kw + rw;
-                for (int b = -rw; b <= rw; ++b) acc += krow[b] * prow[-b];
+    if (RS || op.separable) {
+        // row pass over all P rows, B columns: h[pr][bc] = sum_b row[b] P[pr][bc + 2rw - b]
+        for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
+            const int pr = e / bw, bc = e % bw;
+            const float* prow = sm.p + pr * PW + bc + 2 * rw;
+            float acc = 0.f;
+#pragma unroll
+            for (int b = 0; b < (RS ? 2 * RS + 1 : kMaxPsf); ++b) {
+                if (!RS && b >= kw) break;
+                acc += op.row[b] * prow[-b];
             }
+            sm.h[pr * PW + bc] = acc;
         }
-        sb[br * PW + bc] = acc;
+        __syncthreads();
+        // column pass + decimation mask: t[br][bc] = m * sum_a col[a] h[br + 2rh - a][bc]
+        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+            const int br = e / bw, bc = e % bw;
+            float acc = 0.f;
+            bool keep = true;
+            if (s > 1) {
+                const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
+                keep = gr % s == 0 && gc % s == 0;
+            }
+            if (keep) {
+                const float* hcol = sm.h + (br + 2 * rh) * PW + bc;
+#pragma unroll
+                for (int a = 0; a < (RS ? 2 * RS + 1 : kMaxPsf); ++a) {
+                    if (!RS && a >= kh) break;
+                    acc += op.col[a] * hcol[-a * PW];
+                }
+            }
+            sm.t[br * PW + bc] = acc;
+        }
+        __syncthreads();
+        // B^T row pass: h[br][tc] = sum_b row[b] t[br][tc + b]
+        for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
+            const int br = e / TW, tc = e % TW;
+            const float* trow = sm.t + br * PW + tc;
+            float acc = 0.f;
+#pragma unroll
+            for (int b = 0; b < (RS ? 2 * RS + 1 : kMaxPsf); ++b) {
+                if (!RS && b >= kw) break;
+                acc += op.row[b] * trow[b];
+            }
+            sm.h[br * PW + tc] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int tr = o / TW, tc = o % TW;
+            const float* hcol = sm.h + tr * PW + tc;
+            float acc = 0.f;
+#pragma unroll
+            for (int a = 0; a < (RS ? 2 * RS + 1 : kMaxPsf); ++a) {
+                if (!RS && a >= kh) break;
+                acc += op.col[a] * hcol[a * PW];
+            }
+            pc[k] = sm.p[(tr + 2 * rh) * PW + tc + 2 * rw];
+            q[k] = op.inv_s2 * acc + op.lambda * pc[k];
+        }
+    } else {
+        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+            const int br = e / bw, bc = e % bw;
+            const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
+            float acc = 0.f;
+            if (gr % s == 0 && gc % s == 0) {
+                for (int a = -rh; a <= rh; ++a) {
+                    const float* prow = sm.p + (br + rh - a) * PW + bc + rw;
+                    const float* krow = op.psf + (a + rh) * op.kw + rw;
+                    for (int b = -rw; b <= rw; ++b) acc += krow[b] * prow[-b];
+                }
+            }
+            sm.t[br * PW + bc] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int tr = o / TW, tc = o % TW;
+            float acc = 0.f;
+            for (int a = -rh; a <= rh; ++a) {
+                const float* trow = sm.t + (tr + a + rh) * PW + tc + rw;
+                const float* krow = op.psf + (a + rh) * op.kw + rw;
+                for (int b = -rw; b <= rw; ++b) acc += krow[b] * trow[b];
+            }
+            pc[k] = sm.p[(tr + 2 * rh) * PW + tc + 2 * rw];
+            q[k] = op.inv_s2 * acc + op.lambda * pc[k];
+        }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < TH * TW / kThreads; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int tr = o / TW, tc = o % TW;
-        float acc = 0.f;
-        for (int a = -rh; a <= rh; ++a) {
-            const float* brow = sb + (tr + a + rh) * PW + tc + rw;
-            const float* krow = op.psf + (a + rh) * op.kw + rw;
-            for (int b = -rw; b <= rw; ++b) acc += krow[b] * brow[b];
-        }
-        const float pc = sp[(tr + 2 * rh) * PW + tc + 2 * rw];
-        io.p[k] = pc;
-        io.q[k] = op.inv_s2 * acc + op.lambda * pc;
-    }
 }
 
+// Loads f(g) for every position of the P region of the tile at (r0, c0) into sm.p.
+template <int RS, typename F>
+__device__ inline void tile_load(const LinOp& op, int H, int W, int r0, int c0, TileSmem& sm,
+                                 F f) {
+    const int rh = RS ? RS : op.kh / 2, rw = RS ? RS : op.kw / 2;
+    const int ph = TH + 4 * rh, pw = TW + 4 * rw;
+    for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
+        const int pr = e / pw, pcol = e % pw;
+        const size_t g = (size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pcol, W);
+        sm.p[pr * PW + pcol] = f(g);
+    }
+    __syncthreads();
+}
+
+__device__ inline void tile_origin(int t, int W, int& r0, int& c0) {
+    const int ntx = (W + TW - 1) / TW;
+    r0 = (t / ntx) * TH;
+    c0 = (t % ntx) * TW;
+}
+
+__device__ inline int ntiles(int H, int W) { return ((H + TH - 1) / TH) * ((W + TW - 1) / TW); }
+
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_apply_A(const LinOp op, const float* __restrict__ p,
                                                       int H, int W, float* __restrict__ out) {
-    __shared__ float sp[PH * PW];
-    __shared__ float sb[PH * PW];
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
-    TileIO io;
-    tile_apply_A(op, p, nullptr, 0.f, H, W, r0, c0, sp, sb, io);
+    __shared__ TileSmem sm;
+    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+        int r0, c0;
+        tile_origin(t, W, r0, c0);
+        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return p[g]; });
+        float pc[NO], q[NO];
+        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
 #pragma unroll
-    for (int k = 0; k < TH * TW / kThreads; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int gr = r0 + o / TW, gc = c0 + o % TW;
-        if (gr < H && gc < W) out[(size_t)gr * W + gc] = io.q[k];
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int gr = r0 + o / TW, gc = c0 + o % TW;
+            if (gr < H && gc < W) out[(size_t)gr * W + gc] = q[k];
+        }
     }
 }
 
-// CG start for A x = rhs warm-started at x: r = rhs - A x, p = r, rho0 = r.r, beta = 0.
-// The iterations then accumulate the correction d (x_out = x + d).
+// Generic CG start: r = rhs - A x_in.
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init(const LinOp op, const float* __restrict__ x_in,
                                                       const float* __restrict__ rhs,
-                                                      float* __restrict__ r,
-                                                      float* __restrict__ p, int H, int W,
-                                                      Reduction red, CgScalars* sc) {
-    __shared__ float sp[PH * PW];
-    __shared__ float sb[PH * PW];
-    __shared__ double sred[kThreads / 64];
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
-    TileIO io;
-    tile_apply_A(op, x_in, nullptr, 0.f, H, W, r0, c0, sp, sb, io);
-    double acc[1] = {0.0};
+                                                      float* __restrict__ r, int H, int W) {
+    __shared__ TileSmem sm;
+    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+        int r0, c0;
+        tile_origin(t, W, r0, c0);
+        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return x_in[g]; });
+        float pc[NO], q[NO];
+        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
 #pragma unroll
-    for (int k = 0; k < TH * TW / kThreads; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int gr = r0 + o / TW, gc = c0 + o % TW;
-        if (gr < H && gc < W) {
-            const size_t g = (size_t)gr * W + gc;
-            const float rv = rhs[g] - io.q[k];
-            r[g] = rv;
-            p[g] = rv;
-            acc[0] += (double)rv * (double)rv;
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int gr = r0 + o / TW, gc = c0 + o % TW;
+            if (gr < H && gc < W) {
+                const size_t g = (size_t)gr * W + gc;
+                r[g] = rhs[g] - q[k];
+            }
         }
-    }
-    block_sum<1>(acc, sred);
-    double tot[1];
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x, nblk = gridDim.x * gridDim.y;
-    if (grid_sum<1>(acc, tot, red, blk, nblk, sred) && threadIdx.x == 0) {
-        sc->rho0 = tot[0];
-        sc->beta = 0.0;
     }
 }
 
@@ -168,167 +246,218 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const LinOp op, const floa
 //   r = rhs - A x = H^T (y - H x) / sigma^2 + lambda (f(x) - x),
 // both terms small near the fixed point; the data term is accumulated in FP64 from the FP32
 // image, so r carries no rounding of the O(|x|) quantities rhs and A x. s = f(x) - x (null:
-// the identity denoiser, s = 0). p = r, rho0 = r.r, beta = 0.
-__global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const double* __restrict__ psf64,
-                                                         const float* __restrict__ x,
+// the identity denoiser, s = 0).
+__global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const float* __restrict__ x,
                                                          const float* __restrict__ y,
                                                          const float* __restrict__ s,
-                                                         float* __restrict__ r,
-                                                         float* __restrict__ p, int H, int W,
-                                                         Reduction red, CgScalars* sc) {
+                                                         float* __restrict__ r, int H, int W) {
     __shared__ float sp[PH * PW];
     __shared__ double se[PH * PW];
-    __shared__ double sred[kThreads / 64];
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
+    __shared__ double sh[PH * PW];
     const int rh = op.kh / 2, rw = op.kw / 2, dec = op.decim;
     const int ph = TH + 4 * rh, pw = TW + 4 * rw;
     const int bh = TH + 2 * rh, bw = TW + 2 * rw;
     const int wy = (W + dec - 1) / dec;
-    for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
-        const int pr = e / pw, pc = e % pw;
-        sp[pr * PW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
-    }
-    __syncthreads();
-    // e = S^T (y - S B x) on the tile + r halo, FP64
-    for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
-        const int br = e / bw, bc = e % bw;
-        const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
-        double v = 0.0;
-        if (gr % dec == 0 && gc % dec == 0) {
-            double bx = 0.0;
-            for (int a = -rh; a <= rh; ++a) {
-                const float* prow = sp + (br + rh - a) * PW + bc + rw;
-                const double* krow = psf64 + (a + rh) * op.kw + rw;
-                for (int b = -rw; b <= rw; ++b) bx += krow[b] * (double)prow[-b];
+    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+        int r0, c0;
+        tile_origin(t, W, r0, c0);
+        for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
+            const int pr = e / pw, pc = e % pw;
+            sp[pr * PW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
+        }
+        __syncthreads();
+        if (op.separable) {
+            for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
+                const int pr = e / bw, bc = e % bw;
+                const float* prow = sp + pr * PW + bc + 2 * rw;
+                double a = 0.0;
+                for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * (double)prow[-b];
+                sh[pr * PW + bc] = a;
             }
-            v = (double)y[(size_t)(gr / dec) * wy + gc / dec] - bx;
+            __syncthreads();
         }
-        se[br * PW + bc] = v;
-    }
-    __syncthreads();
-    const double is2 = op.inv_s2_d;
-    double acc[1] = {0.0};
+        // e = S^T (y - S B x) on the tile + r halo, FP64
+        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+            const int br = e / bw, bc = e % bw;
+            const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
+            double v = 0.0;
+            if (gr % dec == 0 && gc % dec == 0) {
+                double bx = 0.0;
+                if (op.separable) {
+                    const double* hcol = sh + (br + 2 * rh) * PW + bc;
+                    for (int a = 0; a < op.kh; ++a) bx += op.col_d[a] * hcol[-a * PW];
+                } else {
+                    for (int a = -rh; a <= rh; ++a) {
+                        const float* prow = sp + (br + rh - a) * PW + bc + rw;
+                        const double* krow = op.psf64 + (a + rh) * op.kw + rw;
+                        for (int b = -rw; b <= rw; ++b) bx += krow[b] * (double)prow[-b];
+                    }
+                }
+                v = (double)y[(size_t)(gr / dec) * wy + gc / dec] - bx;
+            }
+            se[br * PW + bc] = v;
+        }
+        __syncthreads();
+        if (op.separable) {
+            for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
+                const int br = e / TW, tc = e % TW;
+                const double* erow = se + br * PW + tc;
+                double a = 0.0;
+                for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * erow[b];
+                sh[br * PW + tc] = a;
+            }
+            __syncthreads();
+        }
 #pragma unroll
-    for (int k = 0; k < TH * TW / kThreads; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int tr = o / TW, tc = o % TW;
-        const int gr = r0 + tr, gc = c0 + tc;
-        double bt = 0.0;
-        for (int a = -rh; a <= rh; ++a) {
-            const double* erow = se + (tr + a + rh) * PW + tc + rw;
-            const double* krow = psf64 + (a + rh) * op.kw + rw;
-            for (int b = -rw; b <= rw; ++b) bt += krow[b] * erow[b];
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int tr = o / TW, tc = o % TW;
+            const int gr = r0 + tr, gc = c0 + tc;
+            double bt = 0.0;
+            if (op.separable) {
+                const double* hcol = sh + tr * PW + tc;
+                for (int a = 0; a < op.kh; ++a) bt += op.col_d[a] * hcol[a * PW];
+            } else {
+                for (int a = -rh; a <= rh; ++a) {
+                    const double* erow = se + (tr + a + rh) * PW + tc + rw;
+                    const double* krow = op.psf64 + (a + rh) * op.kw + rw;
+                    for (int b = -rw; b <= rw; ++b) bt += krow[b] * erow[b];
+                }
+            }
+            if (gr < H && gc < W) {
+                const size_t g = (size_t)gr * W + gc;
+                double rv = op.inv_s2_d * bt;
+                if (s) rv += op.lambda_d * (double)s[g];
+                r[g] = (float)rv;
+            }
         }
-        if (gr < H && gc < W) {
-            const size_t g = (size_t)gr * W + gc;
-            double rv = is2 * bt;
-            if (s) rv += op.lambda_d * (double)s[g];
-            const float rf = (float)rv;
-            r[g] = rf;
-            p[g] = rf;
-            acc[0] += (double)rf * (double)rf;
-        }
-    }
-    block_sum<1>(acc, sred);
-    double tot[1];
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x, nblk = gridDim.x * gridDim.y;
-    if (grid_sum<1>(acc, tot, red, blk, nblk, sred) && threadIdx.x == 0) {
-        sc->rho0 = tot[0];
-        sc->beta = 0.0;
+        __syncthreads();
     }
 }
 
-// CG direction + product: p_new = r + beta p_old (on the fly, halo included), q = A p_new,
-// pq = p_new . q, alpha = rho0 / pq (0 once the residual vanished).
-__global__ __launch_bounds__(kThreads) void k_cg_q(const LinOp op, const float* __restrict__ r,
-                                                   const float* __restrict__ p_old,
-                                                   float* __restrict__ p_new,
-                                                   float* __restrict__ q, int H, int W,
-                                                   Reduction red, CgScalars* sc) {
-    __shared__ float sp[PH * PW];
-    __shared__ float sb[PH * PW];
-    __shared__ double sred[kThreads / 64];
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
-    const float beta = (float)sc->beta;
-    TileIO io;
-    tile_apply_A(op, r, p_old, beta, H, W, r0, c0, sp, sb, io);
-    double acc[1] = {0.0};
+// Second half of the CG start: w0 = A r0; publishes rho0 = r0.r0 and mu0 = w0.r0.
+template <int RS>
+__global__ __launch_bounds__(kThreads) void k_cg_w0(const LinOp op, const float* __restrict__ r,
+                                                    float* __restrict__ w, int H, int W,
+                                                    double* __restrict__ part) {
+    __shared__ TileSmem sm;
+    __shared__ double sred[2 * kThreads / 64];
+    double acc[2] = {0.0, 0.0};
+    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+        int r0, c0;
+        tile_origin(t, W, r0, c0);
+        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return r[g]; });
+        float pc[NO], q[NO];
+        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
 #pragma unroll
-    for (int k = 0; k < TH * TW / kThreads; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int gr = r0 + o / TW, gc = c0 + o % TW;
-        if (gr < H && gc < W) {
-            const size_t g = (size_t)gr * W + gc;
-            p_new[g] = io.p[k];
-            q[g] = io.q[k];
-            acc[0] += (double)io.p[k] * (double)io.q[k];
+        for (int k = 0; k < NO; ++k) {
+            const int o = threadIdx.x + k * kThreads;
+            const int gr = r0 + o / TW, gc = c0 + o % TW;
+            if (gr < H && gc < W) {
+                w[(size_t)gr * W + gc] = q[k];
+                acc[0] += (double)pc[k] * (double)pc[k];
+                acc[1] += (double)q[k] * (double)pc[k];
+            }
         }
     }
-    block_sum<1>(acc, sred);
-    double tot[1];
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x, nblk = gridDim.x * gridDim.y;
-    if (grid_sum<1>(acc, tot, red, blk, nblk, sred) && threadIdx.x == 0) {
-        const double rho0 = sc->rho0;
-        sc->pq = tot[0];
-        sc->alpha = (rho0 > 1e-300 && tot[0] > 0.0) ? rho0 / tot[0] : 0.0;
-    }
+    block_sum<2>(acc, sred);
+    publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
-// CG update on the correction: d += alpha p (d = alpha p on the first iteration),
-// r -= alpha q, rho1 = r.r, beta = rho1 / rho0, rho0 = rho1. On the last iteration the new
-// iterate x_out = x_in + d is written instead of d (one rounding of the O(|x|) quantity).
-constexpr int UPD_PER_THREAD = 4;
-__global__ __launch_bounds__(kThreads) void k_cg_update(float* __restrict__ d, float* __restrict__ r,
-                                                        const float* __restrict__ p,
-                                                        const float* __restrict__ q, int n,
-                                                        int first, const float* __restrict__ x_in,
-                                                        float* __restrict__ x_out,
-                                                        Reduction red, CgScalars* sc) {
-    __shared__ double sred[kThreads / 64];
-    const float alpha = (float)sc->alpha;
-    double acc[1] = {0.0};
-    const int base = blockIdx.x * kThreads * UPD_PER_THREAD + threadIdx.x;
+// One conjugate-gradient iteration in the single-reduction (Chronopoulos-Gear) form: with
+// r_k, w_k = A r_k, rho_k = r_k.r_k, mu_k = w_k.r_k (published by the previous kernel) and
+// alpha_{k-1}, rho_{k-1} (hist):
+//   beta = rho_k / rho_{k-1},  alpha = rho_k / (mu_k - beta rho_k / alpha_{k-1})  (k = 0:
+//   beta = 0, alpha = rho_0 / mu_0)
+//   p_k = r_k + beta p_{k-1},  s_k = w_k + beta s_{k-1}  (s = A p)
+//   d_{k+1} = d_k + alpha p_k,  r_{k+1} = r_k - alpha s_k,  w_{k+1} = A r_{k+1}
+// and publishes rho_{k+1}, mu_{k+1}. In exact arithmetic these are the Hestenes-Stiefel
+// iterates; one grid-wide reduction per iteration instead of two. r_{k+1} is formed on the
+// tile + halo from r_k, w_k and s_{k-1}, then w_{k+1} is its stencil. On the last iteration
+// only x_out = x_in + d_{k+1} is written.
+template <int RS>
+__global__ __launch_bounds__(kThreads) void k_cg_iter(
+    const LinOp op, int H, int W, int k, int last, const float* __restrict__ r_in,
+    const float* __restrict__ w_in, const float* __restrict__ s_in, float* __restrict__ r_out,
+    float* __restrict__ w_out, float* __restrict__ s_out, float* __restrict__ p,
+    float* __restrict__ d, const float* __restrict__ x_in, float* __restrict__ x_out,
+    Partials rm, const double* __restrict__ hist_prev, double* __restrict__ hist_cur,
+    double* __restrict__ part) {
+    __shared__ TileSmem sm;
+    __shared__ double sred[2 * kThreads / 64];
+    __shared__ double bc;
+    const double rho = consume(rm.p, rm.n, &bc);
+    const double mu = consume(rm.p + kMaxRedBlocks, rm.n, &bc);
+    double alpha_d = 0.0, beta_d = 0.0;
+    if (rho > 1e-300) {
+        if (k == 0) {
+            alpha_d = mu > 0.0 ? rho / mu : 0.0;
+        } else {
+            const double alpha_prev = hist_prev[0], rho_prev = hist_prev[1];
+            beta_d = rho_prev > 1e-300 ? rho / rho_prev : 0.0;
+            const double den = alpha_prev != 0.0 ? mu - beta_d * rho / alpha_prev : 0.0;
+            alpha_d = den > 0.0 ? rho / den : 0.0;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hist_cur[0] = alpha_d;
+        hist_cur[1] = rho;
+    }
+    const float alpha = (float)alpha_d, beta = (float)beta_d;
+    const int n = H * W;
+    double acc[2] = {0.0, 0.0};
+    if (last) {
+        for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+            const float pk = k ? r_in[i] + beta * p[i] : r_in[i];
+            const float dn = k ? d[i] + alpha * pk : alpha * pk;
+            x_out[i] = x_in[i] + dn;
+        }
+        return;
+    }
+    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+        int r0, c0;
+        tile_origin(t, W, r0, c0);
+        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) {
+            const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
+            return r_in[g] - alpha * sk;
+        });
+        float r1[NO], w1[NO];
+        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, r1, w1);
 #pragma unroll
-    for (int k = 0; k < UPD_PER_THREAD; ++k) {
-        const int i = base + k * kThreads;
-        if (i < n) {
-            const float dv = first ? alpha * p[i] : d[i] + alpha * p[i];
-            if (x_out)
-                x_out[i] = x_in[i] + dv;
-            else
-                d[i] = dv;
-            const float rv = r[i] - alpha * q[i];
-            r[i] = rv;
-            acc[0] += (double)rv * (double)rv;
+        for (int kk = 0; kk < NO; ++kk) {
+            const int o = threadIdx.x + kk * kThreads;
+            const int gr = r0 + o / TW, gc = c0 + o % TW;
+            if (gr < H && gc < W) {
+                const size_t g = (size_t)gr * W + gc;
+                const float rk = r_in[g];
+                const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
+                const float pk = k ? rk + beta * p[g] : rk;
+                const float dn = k ? d[g] + alpha * pk : alpha * pk;
+                s_out[g] = sk;
+                p[g] = pk;
+                d[g] = dn;
+                r_out[g] = r1[kk];
+                w_out[g] = w1[kk];
+                acc[0] += (double)r1[kk] * (double)r1[kk];
+                acc[1] += (double)w1[kk] * (double)r1[kk];
+            }
         }
     }
-    block_sum<1>(acc, sred);
-    double tot[1];
-    if (grid_sum<1>(acc, tot, red, blockIdx.x, gridDim.x, sred) && threadIdx.x == 0) {
-        const double rho0 = sc->rho0;
-        sc->beta = rho0 > 1e-300 ? tot[0] / rho0 : 0.0;
-        sc->rho0 = tot[0];
-    }
+    block_sum<2>(acc, sred);
+    publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
-// out = b0 + lambda u (right-hand side of eq. (7) when the denoiser has no stages).
-__global__ __launch_bounds__(kThreads) void k_axpb(const float* __restrict__ b0,
-                                                   const float* __restrict__ u, float lambda,
-                                                   float* __restrict__ out, int n) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) out[i] = b0[i] + lambda * u[i];
+inline int tile_blocks(int H, int W) {
+    const int nt = ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+    return nt < kMaxRedBlocks ? nt : kMaxRedBlocks;
 }
 
-inline dim3 tile_grid(int H, int W) { return dim3((W + TW - 1) / TW, (H + TH - 1) / TH); }
+inline int upd_blocks(int n) {
+    const int b = (n + kThreads - 1) / kThreads;
+    return b < kMaxRedBlocks ? (b > 0 ? b : 1) : kMaxRedBlocks;
+}
 
 }  // namespace
-
-int linop_grid(int H, int W) {
-    dim3 g = tile_grid(H, W);
-    return (int)(g.x * g.y);
-}
-
-int cg_update_grid(int n) { return (n + kThreads * UPD_PER_THREAD - 1) / (kThreads * UPD_PER_THREAD); }
 
 void launch_apply_H(const LinOp& op, const float* x, int H, int W, float* y, hipStream_t st) {
     const int n = ((H + op.decim - 1) / op.decim) * ((W + op.decim - 1) / op.decim);
@@ -344,34 +473,63 @@ void launch_apply_Ht(const LinOp& op, const float* y, int H, int W, float scale,
 }
 
 void launch_apply_A(const LinOp& op, const float* p, int H, int W, float* out, hipStream_t st) {
-    k_apply_A<<<tile_grid(H, W), kThreads, 0, st>>>(op, p, H, W, out);
+    const int g = tile_blocks(H, W);
+    const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
+    if (rr == 4)
+        k_apply_A<4><<<g, kThreads, 0, st>>>(op, p, H, W, out);
+    else if (rr == 3)
+        k_apply_A<3><<<g, kThreads, 0, st>>>(op, p, H, W, out);
+    else
+        k_apply_A<0><<<g, kThreads, 0, st>>>(op, p, H, W, out);
 }
 
-void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, float* p,
-                    int H, int W, Reduction red, CgScalars* sc, hipStream_t st) {
-    k_cg_init<<<tile_grid(H, W), kThreads, 0, st>>>(op, x_in, rhs, r, p, H, W, red, sc);
+void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, int H, int W,
+                    hipStream_t st) {
+    const int g = tile_blocks(H, W);
+    const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
+    if (rr == 4)
+        k_cg_init<4><<<g, kThreads, 0, st>>>(op, x_in, rhs, r, H, W);
+    else if (rr == 3)
+        k_cg_init<3><<<g, kThreads, 0, st>>>(op, x_in, rhs, r, H, W);
+    else
+        k_cg_init<0><<<g, kThreads, 0, st>>>(op, x_in, rhs, r, H, W);
 }
 
-void launch_cg_init_fp(const LinOp& op, const double* psf64, const float* x, const float* y,
-                       const float* s, float* r, float* p, int H, int W, Reduction red,
-                       CgScalars* sc, hipStream_t st) {
-    k_cg_init_fp<<<tile_grid(H, W), kThreads, 0, st>>>(op, psf64, x, y, s, r, p, H, W, red, sc);
+void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
+                       int H, int W, hipStream_t st) {
+    k_cg_init_fp<<<tile_blocks(H, W), kThreads, 0, st>>>(op, x, y, s, r, H, W);
 }
 
-void launch_cg_q(const LinOp& op, const float* r, const float* p_old, float* p_new, float* q,
-                 int H, int W, Reduction red, CgScalars* sc, hipStream_t st) {
-    k_cg_q<<<tile_grid(H, W), kThreads, 0, st>>>(op, r, p_old, p_new, q, H, W, red, sc);
-}
-
-void launch_cg_update(float* d, float* r, const float* p, const float* q, int n, int first,
-                      const float* x_in, float* x_out, Reduction red, CgScalars* sc,
+Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, double* part,
                       hipStream_t st) {
-    k_cg_update<<<cg_update_grid(n), kThreads, 0, st>>>(d, r, p, q, n, first, x_in, x_out, red, sc);
+    const int g = tile_blocks(H, W);
+    const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
+    if (rr == 4)
+        k_cg_w0<4><<<g, kThreads, 0, st>>>(op, r, w, H, W, part);
+    else if (rr == 3)
+        k_cg_w0<3><<<g, kThreads, 0, st>>>(op, r, w, H, W, part);
+    else
+        k_cg_w0<0><<<g, kThreads, 0, st>>>(op, r, w, H, W, part);
+    return Partials{part, g};
 }
 
-void launch_axpb(const float* b0, const float* u, float lambda, float* out, int n,
-                 hipStream_t st) {
-    k_axpb<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(b0, u, lambda, out, n);
+Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const float* r_in,
+                        const float* w_in, const float* s_in, float* r_out, float* w_out,
+                        float* s_out, float* p, float* d, const float* x_in, float* x_out,
+                        Partials rm, const double* hist_prev, double* hist_cur, double* part,
+                        hipStream_t st) {
+    const int g = last ? upd_blocks(H * W) : tile_blocks(H, W);
+    const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
+    if (rr == 4)
+        k_cg_iter<4><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
+                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
+    else if (rr == 3)
+        k_cg_iter<3><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
+                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
+    else
+        k_cg_iter<0><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
+                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
+    return Partials{part, g};
 }
 
 }  // namespace redve

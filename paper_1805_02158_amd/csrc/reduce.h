@@ -1,8 +1,12 @@
-// Deterministic FP64 workgroup and grid reductions for wave64 (gfx950).
+// Deterministic FP64 reductions for wave64 (gfx950) without atomics or fences.
 //
-// Order of summation is fixed by the data-to-thread mapping, the butterfly order inside a
-// wavefront and the wave order inside a workgroup; the grid stage sums per-workgroup partials
-// in workgroup-index order. Results are therefore bitwise reproducible run to run.
+// A grid-wide sum is split across a kernel boundary: the producing kernel writes one FP64
+// partial per workgroup (plain stores), and every workgroup of the consuming kernel re-sums
+// those partials itself, in workgroup-index order. The kernel boundary makes the partials
+// visible, so no device-scope atomic, fence or last-workgroup protocol is needed; every
+// consumer workgroup computes the bitwise-identical total. The order of summation is fixed by
+// the data-to-thread mapping, the butterfly inside a wavefront and the wave order inside a
+// workgroup, so results are reproducible run to run.
 #pragma once
 
 #include "internal.h"
@@ -37,38 +41,28 @@ __device__ inline void block_sum(double (&v)[NV], double* scratch /* NV * kThrea
     __syncthreads();
 }
 
-// Publishes this workgroup's NV partials (held by thread 0) and returns true in every thread
-// of the workgroup that completes the grid. In that workgroup, thread 0 then holds the grid
-// totals in `tot` (summed over workgroups 0..nblk-1 in order) and the counter is re-armed.
+// Writes this workgroup's NV partials (valid in thread 0) to part[k * stride + blk].
 template <int NV>
-__device__ inline bool grid_sum(const double (&v)[NV], double (&tot)[NV], Reduction red,
-                                int blk, int nblk, double* scratch) {
-    __shared__ int s_last;
+__device__ inline void publish(const double (&v)[NV], double* part, int stride, int blk) {
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) red.partials[(size_t)k * red.capacity + blk] = v[k];
-        unsigned prev = __hip_atomic_fetch_add(red.counter, 1u, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (unsigned)(nblk - 1));
+        for (int k = 0; k < NV; ++k) part[(size_t)k * stride + blk] = v[k];
+    }
+}
+
+// Total of n partials, summed by the first wave in a fixed order and broadcast to the whole
+// workgroup. Call from every thread (contains a workgroup barrier).
+__device__ inline double consume(const double* part, int n, double* bcast /* one double */) {
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += 64) s += part[i];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) *bcast = s;
     }
     __syncthreads();
-    if (!s_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double acc[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += kThreads)
-            s += red.partials[(size_t)k * red.capacity + i];
-        acc[k] = s;
-    }
-    block_sum<NV>(acc, scratch);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) tot[k] = acc[k];
-        __hip_atomic_store(red.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return true;
+    const double r = *bcast;
+    __syncthreads();
+    return r;
 }
 
 }  // namespace redve

@@ -24,18 +24,15 @@ struct Workspace {
     size_t bytes = 0;
     size_t cap_px = 0;
     int cap_L = 0;
-    int cap_blocks = 0;
-    float *xa, *xb, *xc, *rhs, *r, *p0, *p1, *q, *u0, *u1, *d, *U;
-    double* partials;
-    unsigned* counter;
-    CgScalars* sc;
-    double* G;
-    double* norms;
+    float *xa, *xb, *xc, *sres, *u0, *u1, *r[2], *w[2], *s[2], *p, *d, *U;
+    double* cg_part;  // two slots of published (rho, mu) partials
+    double* cg_hist;  // two slots of (alpha, rho) of the previous CG iteration
+    double* ve_part;  // window partials: column j at j * win_stride
+    size_t win_stride;
     VeInfo* info;
 };
 
 struct HostMirror {
-    double norms[2];
     VeInfo info;
 };
 
@@ -51,11 +48,13 @@ struct redve_ctx {
     int kh = 0, kw = 0, decim = 1;
     float* d_psf = nullptr;
     double* d_psf64 = nullptr;
+    int separable = 0;
+    double row[REDVE_MAX_PSF], col[REDVE_MAX_PSF];  // psf = col (x) row when separable
     // sigma, lambda
     double sigma = -1.0, lambda = -1.0;
     // denoiser
     bool have_den = false;
-    int T = 0, F = 0, J = 0, precision = REDVE_PREC_FP32;
+    int T = 0, F = 0, J = 0, precision = REDVE_PREC_FP32, kwin = 7;
     double mu0 = 0, dmu = 0, gamma = 1;
     std::vector<float> theta;
     float* d_filt = nullptr;
@@ -90,11 +89,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int ensure_workspace(redve_t h, int hx, int wx, int L) {
     const size_t npx = (size_t)hx * wx;
-    // capacity for the grid reductions: tiled CG kernels, CG update, difference/Gram pass
-    const int H_blocks = std::max({linop_grid(hx, wx), cg_update_grid((int)npx),
-                                   diff_grid((int)npx), 1024});
     Workspace& w = h->ws;
-    if (w.arena && w.cap_px >= npx && w.cap_L >= L && w.cap_blocks >= H_blocks) return REDVE_OK;
+    if (w.arena && w.cap_px >= npx && w.cap_L >= L) return REDVE_OK;
     if (w.arena) {
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         HIP_TRY(h, hipFree(w.arena));
@@ -102,19 +98,16 @@ int ensure_workspace(redve_t h, int hx, int wx, int L) {
     }
     const size_t cap_px = std::max(npx, w.cap_px);
     const int cap_L = std::max(std::max(L, w.cap_L), 1);
-    const int cap_blocks = std::max(H_blocks, w.cap_blocks);
     const size_t vec = align_up(cap_px * sizeof(float));
-    size_t bytes = vec * (11 + (size_t)cap_L);
-    const size_t o_part = bytes;
-    bytes += align_up((size_t)cap_blocks * 18 * sizeof(double));
-    const size_t o_cnt = bytes;
+    const size_t win_stride = (size_t)(cap_L + 1) * kMaxRedBlocks;
+    constexpr int kVecs = 14;
+    size_t bytes = vec * (kVecs + (size_t)cap_L);
+    const size_t o_cg = bytes;
+    bytes += align_up(4 * kMaxRedBlocks * sizeof(double));
+    const size_t o_hist = bytes;
     bytes += kAlign;
-    const size_t o_sc = bytes;
-    bytes += align_up(sizeof(CgScalars));
-    const size_t o_G = bytes;
-    bytes += align_up(REDVE_MAX_L * REDVE_MAX_L * sizeof(double));
-    const size_t o_norms = bytes;
-    bytes += kAlign;
+    const size_t o_ve = bytes;
+    bytes += align_up((size_t)cap_L * win_stride * sizeof(double));
     const size_t o_info = bytes;
     bytes += align_up(sizeof(VeInfo));
     void* arena = nullptr;
@@ -122,29 +115,44 @@ int ensure_workspace(redve_t h, int hx, int wx, int L) {
         return fail(h, REDVE_E_NOMEM, "device workspace allocation of " + std::to_string(bytes) +
                                           " bytes failed");
     char* base = (char*)arena;
-    float** vecs[] = {&w.xa, &w.xb, &w.xc, &w.rhs, &w.r, &w.p0, &w.p1, &w.q, &w.u0, &w.u1, &w.d};
-    for (int i = 0; i < 11; ++i) *vecs[i] = (float*)(base + vec * i);
-    w.U = (float*)(base + vec * 11);
-    w.partials = (double*)(base + o_part);
-    w.counter = (unsigned*)(base + o_cnt);
-    w.sc = (CgScalars*)(base + o_sc);
-    w.G = (double*)(base + o_G);
-    w.norms = (double*)(base + o_norms);
+    float** vecs[kVecs] = {&w.xa,   &w.xb,   &w.xc,   &w.sres, &w.u0, &w.u1, &w.r[0],
+                           &w.r[1], &w.w[0], &w.w[1], &w.s[0], &w.s[1], &w.p, &w.d};
+    for (int i = 0; i < kVecs; ++i) *vecs[i] = (float*)(base + vec * i);
+    w.U = (float*)(base + vec * kVecs);
+    w.cg_part = (double*)(base + o_cg);
+    w.cg_hist = (double*)(base + o_hist);
+    w.ve_part = (double*)(base + o_ve);
+    w.win_stride = win_stride;
     w.info = (VeInfo*)(base + o_info);
     w.arena = arena;
     w.bytes = bytes;
     w.cap_px = cap_px;
     w.cap_L = cap_L;
-    w.cap_blocks = cap_blocks;
-    HIP_TRY(h, hipMemsetAsync(arena, 0, bytes, h->stream));
     return REDVE_OK;
 }
 
-Reduction red_of(redve_t h) { return Reduction{h->ws.partials, h->ws.counter, h->ws.cap_blocks}; }
-
 LinOp linop_of(redve_t h) {
     const double is2 = 1.0 / (h->sigma * h->sigma);
-    return LinOp{h->d_psf, h->kh, h->kw, h->decim, (float)is2, (float)h->lambda, is2, h->lambda};
+    LinOp op{};
+    op.psf = h->d_psf;
+    op.psf64 = h->d_psf64;
+    op.kh = h->kh;
+    op.kw = h->kw;
+    op.decim = h->decim;
+    op.separable = h->separable;
+    op.inv_s2 = (float)is2;
+    op.lambda = (float)h->lambda;
+    op.inv_s2_d = is2;
+    op.lambda_d = h->lambda;
+    for (int i = 0; i < h->kh; ++i) {
+        op.col_d[i] = h->col[i];
+        op.col[i] = (float)h->col[i];
+    }
+    for (int j = 0; j < h->kw; ++j) {
+        op.row_d[j] = h->row[j];
+        op.row[j] = (float)h->row[j];
+    }
+    return op;
 }
 
 TnrdDev tnrd_of(redve_t h) {
@@ -160,6 +168,7 @@ TnrdDev tnrd_of(redve_t h) {
     for (int t = 0; t < h->T && t < kMaxStages; ++t) d.theta[t] = h->theta[t];
     d.filt_bf16 = h->d_filt_bf16;
     d.precision = h->precision;
+    d.kwin = h->kwin;
     return d;
 }
 
@@ -204,22 +213,20 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
     return REDVE_OK;
 }
 
-// CG iterations on the correction: d accumulates sum alpha p; the last iteration writes
-// x_out = x_in + d. Requires r, p0 and the CG scalars set up by one of the init kernels.
+// CG iterations in single-reduction form on the correction d (A d = r0 from d = 0), r0 in
+// ws.r[0]; the last iteration writes x_out = x_in + d.
 int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int iters) {
     Workspace& w = h->ws;
-    const int n = H * W;
     LinOp op = linop_of(h);
-    Reduction red = red_of(h);
-    float* pold = w.p0;
-    float* pnew = w.p1;
-    for (int it = 0; it < iters; ++it) {
-        const bool last = it == iters - 1;
-        launch_cg_q(op, w.r, pold, pnew, w.q, H, W, red, w.sc, h->stream);
-        launch_cg_update(w.d, w.r, pnew, w.q, n, it == 0 ? 1 : 0, x_in, last ? x_out : nullptr,
-                         red, w.sc, h->stream);
+    double* slot[2] = {w.cg_part, w.cg_part + 2 * kMaxRedBlocks};
+    Partials rm = launch_cg_w0(op, w.r[0], w.w[0], H, W, slot[0], h->stream);
+    LAUNCH_CHECK(h);
+    for (int k = 0; k < iters; ++k) {
+        const int a = k & 1, b = a ^ 1;
+        rm = launch_cg_iter(op, H, W, k, k == iters - 1, w.r[a], w.w[a], w.s[b], w.r[b], w.w[b],
+                            w.s[a], w.p, w.d, x_in, x_out, rm, w.cg_hist + 2 * b,
+                            w.cg_hist + 2 * a, slot[b], h->stream);
         LAUNCH_CHECK(h);
-        std::swap(pold, pnew);
     }
     return REDVE_OK;
 }
@@ -232,7 +239,7 @@ int run_cg(redve_t h, const float* rhs, const float* x_in, float* x_out, int H, 
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
     }
-    launch_cg_init(linop_of(h), x_in, rhs, w.r, w.p0, H, W, red_of(h), w.sc, h->stream);
+    launch_cg_init(linop_of(h), x_in, rhs, w.r[0], H, W, h->stream);
     LAUNCH_CHECK(h);
     return cg_iterate(h, x_in, x_out, H, W, iters);
 }
@@ -244,24 +251,20 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
     Workspace& w = h->ws;
     const int n = H * W;
     bool s_null = false;
-    int rc = run_denoiser(h, x_in, H, W, w.rhs, true, &s_null);
+    int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null);
     if (rc) return rc;
     if (h->cg_iters <= 0) {
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
     }
-    launch_cg_init_fp(linop_of(h), h->d_psf64, x_in, y, s_null ? nullptr : w.rhs, w.r, w.p0, H, W,
-                      red_of(h), w.sc, h->stream);
+    launch_cg_init_fp(linop_of(h), x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
     LAUNCH_CHECK(h);
     return cg_iterate(h, x_in, x_out, H, W, h->cg_iters);
 }
 
-int read_back(redve_t h, bool info) {
-    HIP_TRY(h, hipMemcpyAsync(h->host->norms, h->ws.norms, sizeof(double) * 2,
-                              hipMemcpyDeviceToHost, h->stream));
-    if (info)
-        HIP_TRY(h, hipMemcpyAsync(&h->host->info, h->ws.info, sizeof(VeInfo), hipMemcpyDeviceToHost,
-                                  h->stream));
+int read_back(redve_t h) {
+    HIP_TRY(h, hipMemcpyAsync(&h->host->info, h->ws.info, sizeof(VeInfo), hipMemcpyDeviceToHost,
+                              h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return REDVE_OK;
 }
@@ -336,7 +339,7 @@ const char* redve_last_error(redve_t h) { return h ? h->err.c_str() : "null hand
 size_t redve_workspace_bytes(redve_t h, int hx, int wx) {
     if (!h || hx <= 0 || wx <= 0) return 0;
     const size_t vec = align_up((size_t)hx * wx * sizeof(float));
-    return vec * (11 + (size_t)std::max(h->L, 1)) + 64 * 1024;
+    return vec * (14 + (size_t)std::max(h->L, 1)) + 64 * 1024;
 }
 
 int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) {
@@ -362,6 +365,18 @@ int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) 
     h->kh = kh;
     h->kw = kw;
     h->decim = decim;
+    // rank-1 test: psf = col (x) row with col = the column through the largest tap and
+    // row = that tap's row divided by it (exact for any rank-1 matrix)
+    int im = 0;
+    for (int i = 1; i < kh * kw; ++i)
+        if (fabs(psf[i]) > fabs(psf[im])) im = i;
+    const int ai = im / kw, bj = im % kw;
+    double amax = fabs(psf[im]), err = 0.0;
+    for (int a = 0; a < kh; ++a) h->col[a] = psf[a * kw + bj];
+    for (int b = 0; b < kw; ++b) h->row[b] = amax > 0 ? psf[ai * kw + b] / psf[im] : 0.0;
+    for (int a = 0; a < kh; ++a)
+        for (int b = 0; b < kw; ++b) err = fmax(err, fabs(psf[a * kw + b] - h->col[a] * h->row[b]));
+    h->separable = (amax > 0 && err <= 1e-12 * amax) ? 1 : 0;
     h->have_op = true;
     return REDVE_OK;
 }
@@ -388,8 +403,13 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     if (p->stages > 0) {
         if (p->nfilt < 1 || p->nfilt > REDVE_MAX_FILTERS) return fail(h, REDVE_E_ARG, "nfilt out of range");
         if (p->nrbf < 1 || p->nrbf > REDVE_MAX_RBF) return fail(h, REDVE_E_ARG, "nrbf out of range");
-        if (!(p->gamma > 0) || !std::isfinite(p->mu0) || !std::isfinite(p->dmu))
+        if (!(p->gamma > 0) || !(p->dmu > 0) || !std::isfinite(p->mu0) || !std::isfinite(p->dmu))
             return fail(h, REDVE_E_ARG, "bad RBF grid");
+        // exact window: centres farther than (K + 1/2) dmu from z add < 1e-12 of a weight,
+        // i.e. (K + 1/2) dmu / gamma >= sqrt(2 ln 1e12) = 7.43
+        const double ratio = p->gamma / p->dmu;
+        if (ratio < 1.0 / 3.0 || ratio > 2.2)
+            return fail(h, REDVE_E_ARG, "gamma / dmu must be in [1/3, 2.2]");
         if (!p->filters || !p->rbf_w || !p->react) return fail(h, REDVE_E_ARG, "null denoiser array");
         const int ks2 = 25;
         for (int f = 0; f < p->stages * p->nfilt; ++f) {
@@ -423,6 +443,7 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     h->dmu = p->dmu;
     h->gamma = p->gamma;
     h->precision = p->precision;
+    h->kwin = p->stages > 0 ? std::max(1, (int)ceil(7.4338 * p->gamma / p->dmu - 0.5)) : 1;
     h->theta.assign(h->T, 0.f);
     if (h->T > 0) {
         const size_t nf = (size_t)h->T * h->F * 25, nw = (size_t)h->T * h->F * h->J;
@@ -553,15 +574,16 @@ int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* 
     if ((rc = ensure_workspace(h, hx, wx, L))) return rc;
     const int n = hx * wx;
     Workspace& w = h->ws;
+    int nblk = 1;
     for (int j = 0; j < L; ++j) {
-        launch_diff_gram(xs + (size_t)(j + 1) * n, xs + (size_t)j * n, w.U, j, L, n, w.G, w.norms,
-                         red_of(h), h->stream);
+        nblk = launch_diff_gram(xs + (size_t)(j + 1) * n, xs + (size_t)j * n, w.U, j, n,
+                                w.ve_part + j * w.win_stride, h->stream);
         LAUNCH_CHECK(h);
     }
-    launch_ve_solve(w.G, L, L, h->method, h->rank_eps, w.info, h->stream);
+    launch_ve_solve(w.ve_part, w.win_stride, nblk, L, h->method, h->rank_eps, w.info, h->stream);
     launch_ve_combine(xs, w.U, n, w.info, out, h->stream);
     LAUNCH_CHECK(h);
-    if ((rc = read_back(h, true))) return rc;
+    if ((rc = read_back(h))) return rc;
     if (gamma)
         for (int j = 0; j < L; ++j) gamma[j] = h->host->info.gamma[j];
     if (breakdown) *breakdown = h->host->info.breakdown;
@@ -585,7 +607,6 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     const int n = hx * wx;
     const size_t bytes = sizeof(float) * n;
     LinOp op = linop_of(h);
-    Reduction red = red_of(h);
 
     // x0 (default: y, or decim^2 H^T y for SR)
     if (x0)
@@ -607,10 +628,11 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
         while (calls < h->max_fp) {
             if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
             ++calls;
-            launch_diff_gram(nxt, x_cur, nullptr, 0, 1, n, nullptr, w.norms, red, h->stream);
+            const int nb = launch_diff_gram(nxt, x_cur, nullptr, 0, n, w.ve_part, h->stream);
+            launch_delta(w.ve_part, nb, w.info, h->stream);
             LAUNCH_CHECK(h);
-            if ((rc = read_back(h, false))) return rc;
-            delta = sqrt(h->host->norms[0] / h->host->norms[1]);
+            if ((rc = read_back(h))) return rc;
+            delta = sqrt(h->host->info.uu / h->host->info.xx);
             std::swap(x_cur, nxt);
             if ((status = prog.check(delta))) break;
             if (delta < h->tol) break;
@@ -620,6 +642,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
         // U; extrapolate (Algorithm 1) and restart from x_(m,kappa).
         while (calls < h->max_fp) {
             float* base = x_cur;  // x_0 of this cycle
+            int nblk = 1;
             float* wbase = nullptr;
             float* cur = base;
             bool early = false;
@@ -633,7 +656,8 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
                 if ((rc = fp_call(h, y, cur, nxt, hx, wx))) return rc;
                 ++calls;
                 if (i >= h->m) {
-                    launch_diff_gram(nxt, cur, w.U, i - h->m, L, n, w.G, w.norms, red, h->stream);
+                    nblk = launch_diff_gram(nxt, cur, w.U, i - h->m, n,
+                                            w.ve_part + (i - h->m) * w.win_stride, h->stream);
                     LAUNCH_CHECK(h);
                 }
                 cur = nxt;
@@ -643,17 +667,18 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
                 x_cur = cur;
                 break;
             }
-            launch_ve_solve(w.G, L, L, h->method, h->rank_eps, w.info, h->stream);
+            launch_ve_solve(w.ve_part, w.win_stride, nblk, L, h->method, h->rank_eps, w.info,
+                            h->stream);
             launch_ve_combine(wbase, w.U, n, w.info, wbase, h->stream);
             LAUNCH_CHECK(h);
             x_cur = wbase;
-            if ((rc = read_back(h, true))) return rc;
+            if ((rc = read_back(h))) return rc;
             ++cycles;
             if (h->host->info.breakdown)
                 ++breakdowns;
             else
                 gl1max = std::max(gl1max, h->host->info.gamma_l1);
-            delta = sqrt(h->host->norms[0] / h->host->norms[1]);
+            delta = sqrt(h->host->info.uu / h->host->info.xx);
             if (!std::isfinite(h->host->info.gamma_l1)) {
                 status = REDVE_E_NONFINITE;
                 break;

@@ -7,11 +7,19 @@
 // f + w, the epilogue computes w_t = w_{t-1} - g - theta_t w_{t-1}, so the FP32 rounding of the
 // carried state is relative to |w|, not to |u|. The FP call then uses f(x) - x = w_T directly.
 //
-// A workgroup owns a TH x TW output tile. It stages u on the tile + 4-pixel halo in LDS
-// (2 for the forward bank, 2 for the adjoint). Every thread keeps the 5x5 window of u around
-// each of its forward positions in registers, so the 24-filter forward bank reads LDS once.
-// Per filter, v = phi(K u) on the tile + 2 halo goes to LDS and the adjoint accumulates in
-// registers. The responses z and v never reach HBM: one read of u and f, one write of u_t.
+// Work decomposition (gfx950, wave64). A workgroup owns a 16x16 output tile and stages u on
+// the tile + 4-pixel halo in LDS (2 for the forward bank, 2 for the adjoint). Its eight waves
+// split the filters (wave q takes filters q, q+8, ...), so the filter loop needs no workgroup
+// barrier. Forward bank: each lane keeps a 5x11 patch of u in registers and produces a 1x7
+// strip of responses z for every filter of its wave (no LDS reads). Influence functions: the
+// Gaussian RBF sum is evaluated exactly on the centres within 7.5 spacings of z (the rest
+// contribute < 1e-12 of a weight), with one exp for the nearest term and a two-multiply
+// recurrence for its neighbours. Adjoint: the wave's v plane goes to a wave-private LDS slab;
+// each lane accumulates a 1x4 output strip from a 5x8 window of it. The eight waves' partial
+// sums are added in fixed wave order at the end (deterministic). z and v never reach HBM:
+// one read of f and w (plus halo), one write of w_t.
+#include <math.h>
+
 #include "internal.h"
 
 namespace redve {
@@ -19,25 +27,82 @@ namespace redve {
 namespace {
 
 constexpr int TH = 16, TW = 16;
-constexpr int UH = TH + 8, UW = TW + 8;  // u region: rows r0-4 .. r0+TH+3
-constexpr int VH = TH + 4, VW = TW + 4;  // v region: rows r0-2 .. r0+TH+1
-constexpr int NPOS = (VH * VW + kThreads - 1) / kThreads;  // forward positions per thread
-constexpr int NOUT = TH * TW / kThreads;                    // outputs per thread
-constexpr float LOG2E = 1.4426950408889634f;
+constexpr int UH = TH + 8, UW = TW + 12;  // u region rows r0-4.., padded columns for the patches
+constexpr int VH = TH + 4, VW = TW + 4;   // v region: rows r0-2 .. r0+TH+1
+constexpr int NP = 7;                      // forward positions per lane (a 1x7 strip)
+constexpr int SPR = (VW + NP - 1) / NP;    // strips per v row
+constexpr int OS = 4;                      // adjoint outputs per lane (a 1x4 strip)
+constexpr int NTHR = 512;                  // 8 waves: each takes every 8th filter
+constexpr int NWAVE = NTHR / 64;
+constexpr int WPAD = kMaxRbfWindow;        // zero padding on both sides of each weight row
+static_assert(VH * SPR <= 64, "forward strips must fit one wave");
+static_assert(TH * TW == 64 * OS, "adjoint strips must cover the tile with one wave");
+static_assert((SPR - 1) * NP + NP + 4 <= UW, "patch columns must stay inside the u region");
 
 // Half-sample symmetric mirror, valid for -2 <= i <= n+1 and n >= 2.
 __device__ inline int mirror(int i, int n) { return i < 0 ? -i - 1 : (i >= n ? 2 * n - i - 1 : i); }
 
-__global__ __launch_bounds__(kThreads) void k_tnrd_stage_f32(
+struct RbfConst {
+    float mu0, dmu, inv_dmu;
+    float c;       // log2(e) / (2 gamma^2): exp(-d^2/(2 gamma^2)) = exp2(-c d^2)
+    float two_cd;  // 2 c dmu
+    float b, b2;   // exp2(-c dmu^2), its square
+    float cutoff;  // |z - nearest centre| beyond which every term is negligible
+    int J, K;      // centres, window half-width
+};
+
+// phi(z) = sum_j w_j exp2(-c (z - mu_j)^2), summed over j0-K .. j0+K (j0 the nearest centre).
+// With d0 = z - mu_{j0}: term(j0+k) = G0 A^k B^(k^2), G0 = exp2(-c d0^2), A = exp2(2 c dmu d0),
+// B = exp2(-c dmu^2), so term(k+1) = term(k) * R_k with R_{k+1} = R_k B^2 (and the same with
+// A^-1 downwards). wrow points at the (zero-padded) weights of this function. Beyond the
+// cut-off (z more than K + 1/2 spacings outside the centre range) every term is below 1e-12
+// of a weight and the result is 0; d0 is clamped there so no factor overflows.
+template <int KC>
+__device__ inline float phi_window(float z, const float* wrow, const RbfConst& p) {
+    const int K = KC > 0 ? KC : p.K;
+    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
+    j0 = min(max(j0, 0), p.J - 1);
+    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
+    const bool live = fabsf(d0r) <= p.cutoff;
+    const float d0 = live ? d0r : 0.f;
+    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
+    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
+    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
+    const float* wc = wrow + WPAD + j0;
+    float acc = wc[0] * g0;
+    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
+#pragma unroll
+    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
+        if (KC == 0 && k > K) break;
+        gu *= ru;
+        ru *= p.b2;
+        gd *= rd;
+        rd *= p.b2;
+        acc += wc[k] * gu + wc[-k] * gd;
+    }
+    return acc;
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const float* __restrict__ filt /* F*25 */, const float* __restrict__ rbfw /* F*J */,
-    int F, int J, float theta, float mu0, float dmu, float gscale /* log2(e)/(2 gamma^2) */,
-    int out_mode) {
-    __shared__ float su[UH * UW];
-    __shared__ float sv[VH * VW];
+    int F, RbfConst rc, float theta, int out_mode) {
+    extern __shared__ float smem[];
+    float* su = smem;                  // UH * UW
+    float* sg = su + UH * UW;          // NWAVE * TH * TW (partial g)
+    float* sv = sg + NWAVE * TH * TW;  // NWAVE * VH * VW
+    float* sw = sv + NWAVE * VH * VW;  // F * (J + 2 WPAD)
+    const int wstride = rc.J + 2 * WPAD;
     const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    for (int e = threadIdx.x; e < UH * UW; e += kThreads) {
+    for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
         const int er = r0 - 4 + e / UW, ec = c0 - 4 + e % UW;
         float val = 0.f;
         if (er >= -2 && er <= H + 1 && ec >= -2 && ec <= W + 1) {
@@ -46,104 +111,115 @@ __global__ __launch_bounds__(kThreads) void k_tnrd_stage_f32(
         }
         su[e] = val;
     }
+    for (int e = threadIdx.x; e < F * wstride; e += NTHR) {
+        const int i = e / wstride, j = e % wstride - WPAD;
+        sw[e] = (j >= 0 && j < rc.J) ? rbfw[i * rc.J + j] : 0.f;
+    }
     __syncthreads();
 
-    // 5x5 windows of u for this thread's forward positions (v region coordinates).
-    float win[NPOS][25];
-    bool inside[NPOS];
+    // forward strip of this lane: v row fr, columns fc .. fc+NP-1
+    const int fr = lane / SPR, fc = (lane % SPR) * NP;
+    const bool fwd_lane = fr < VH;
+    float patch[5][NP + 4];
 #pragma unroll
-    for (int k = 0; k < NPOS; ++k) {
-        const int pos = threadIdx.x + k * kThreads;
-        const int vr = pos / VW, vc = pos % VW;  // v region row/col; image row r0-2+vr
-        const int gr = r0 - 2 + vr, gc = c0 - 2 + vc;
-        inside[k] = pos < VH * VW && gr >= 0 && gr < H && gc >= 0 && gc < W;
+    for (int a = 0; a < 5; ++a)
 #pragma unroll
-        for (int t = 0; t < 25; ++t) win[k][t] = 0.f;
-        if (inside[k]) {
+        for (int b = 0; b < NP + 4; ++b) patch[a][b] = fwd_lane ? su[(fr + a) * UW + fc + b] : 0.f;
+    bool fin[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int gr = r0 - 2 + fr, gc = c0 - 2 + fc + p;
+        fin[p] = fwd_lane && fc + p < VW && gr >= 0 && gr < H && gc >= 0 && gc < W;
+    }
+    // adjoint strip of this lane: tile row ar, columns ac .. ac+OS-1
+    const int ar = lane / (TW / OS), ac = (lane % (TW / OS)) * OS;
+    float g[OS];
+#pragma unroll
+    for (int o = 0; o < OS; ++o) g[o] = 0.f;
+    const int gra = r0 + ar;
+    bool border[OS];
+#pragma unroll
+    for (int o = 0; o < OS; ++o) {
+        const int gca = c0 + ac + o;
+        border[o] = gra < H && gca < W && (gra <= 1 || gra >= H - 2 || gca <= 1 || gca >= W - 2);
+    }
+    float* my_v = sv + wave * VH * VW;
+
+    for (int i = wave; i < F; i += NWAVE) {
+        const float* kf = filt + i * 25;
+        const float* wrow = sw + i * wstride;
+        // forward bank + influence function on the strip
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            float z = 0.f;
 #pragma unroll
             for (int a = 0; a < 5; ++a)
 #pragma unroll
-                for (int b = 0; b < 5; ++b) win[k][a * 5 + b] = su[(vr + a) * UW + vc + b];
+                for (int b = 0; b < 5; ++b) z += kf[a * 5 + b] * patch[a][p + b];
+            const float v = fin[p] ? phi_window<KC>(z, wrow, rc) : 0.f;
+            if (fwd_lane && fc + p < VW) my_v[fr * VW + fc + p] = v;
         }
-    }
-
-    float g[NOUT];
+        wave_sync();
+        // adjoint: g(p) += sum_{a,b} k[a][b] v[p - (a-2, b-2)] on the strip
+        float vw[5][OS + 4];
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) g[k] = 0.f;
-
-    for (int i = 0; i < F; ++i) {
-        const float* kf = filt + i * 25;
-        const float* wi = rbfw + i * J;
+        for (int a = 0; a < 5; ++a)
 #pragma unroll
-        for (int k = 0; k < NPOS; ++k) {
-            const int pos = threadIdx.x + k * kThreads;
-            float v = 0.f;
-            if (inside[k]) {
-                float z = 0.f;
+            for (int b = 0; b < OS + 4; ++b) vw[a][b] = my_v[(ar + a) * VW + ac + b];
 #pragma unroll
-                for (int t = 0; t < 25; ++t) z += kf[t] * win[k][t];
-                float acc = 0.f;
-                for (int j = 0; j < J; ++j) {
-                    const float d = z - (mu0 + dmu * (float)j);
-                    acc += wi[j] * __builtin_amdgcn_exp2f(-(d * d) * gscale);
-                }
-                v = acc;
-            }
-            if (pos < VH * VW) sv[pos] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < NOUT; ++k) {
-            const int o = threadIdx.x + k * kThreads;
-            const int tr = o / TW, tc = o % TW;
-            const int gr = r0 + tr, gc = c0 + tc;
-            // primary: extended position == the pixel itself; v outside the image is 0 in LDS
+        for (int o = 0; o < OS; ++o) {
             float acc = 0.f;
 #pragma unroll
             for (int a = 0; a < 5; ++a)
 #pragma unroll
-                for (int b = 0; b < 5; ++b)
-                    acc += kf[a * 5 + b] * sv[(tr + 4 - a) * VW + tc + 4 - b];
-            // border pixels also receive the contributions of the extended positions that
-            // mirror onto them (the transpose of the extension)
-            if ((gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) && gr < H && gc < W) {
-                const int cr[3] = {gr, -1 - gr, 2 * H - 1 - gr};
-                const int cc[3] = {gc, -1 - gc, 2 * W - 1 - gc};
-                for (int x = 0; x < 3; ++x) {
-                    const int er = cr[x];
-                    if (er < -2 || er > H + 1) continue;
-                    for (int y = 0; y < 3; ++y) {
-                        const int ec = cc[y];
-                        if (ec < -2 || ec > W + 1) continue;
-                        if (x == 0 && y == 0) continue;
-                        for (int a = 0; a < 5; ++a) {
-                            const int vr = er - a + 2;
-                            if (vr < 0 || vr >= H) continue;
-                            for (int b = 0; b < 5; ++b) {
-                                const int vc = ec - b + 2;
-                                if (vc < 0 || vc >= W) continue;
-                                acc += kf[a * 5 + b] * sv[(vr - r0 + 2) * VW + vc - c0 + 2];
-                            }
+                for (int b = 0; b < 5; ++b) acc += kf[a * 5 + b] * vw[4 - a][o + 4 - b];
+            g[o] += acc;
+        }
+        // border pixels also receive the contributions of the extended positions that mirror
+        // onto them (the transpose of the extension)
+        for (int o = 0; o < OS; ++o) {
+            if (!border[o]) continue;
+            const int gca = c0 + ac + o;
+            const int cr[3] = {gra, -1 - gra, 2 * H - 1 - gra};
+            const int cc[3] = {gca, -1 - gca, 2 * W - 1 - gca};
+            float acc = 0.f;
+            for (int x = 0; x < 3; ++x) {
+                const int er = cr[x];
+                if (er < -2 || er > H + 1) continue;
+                for (int y = 0; y < 3; ++y) {
+                    const int ec = cc[y];
+                    if (ec < -2 || ec > W + 1 || (x == 0 && y == 0)) continue;
+                    for (int a = 0; a < 5; ++a) {
+                        const int vr = er - a + 2;
+                        if (vr < 0 || vr >= H) continue;
+                        for (int b = 0; b < 5; ++b) {
+                            const int vc = ec - b + 2;
+                            if (vc < 0 || vc >= W) continue;
+                            acc += kf[a * 5 + b] * my_v[(vr - r0 + 2) * VW + vc - c0 + 2];
                         }
                     }
                 }
             }
-            g[k] += acc;
+            g[o] += acc;
         }
-        __syncthreads();
+        wave_sync();
     }
 
 #pragma unroll
-    for (int k = 0; k < NOUT; ++k) {
-        const int o = threadIdx.x + k * kThreads;
-        const int tr = o / TW, tc = o % TW;
+    for (int o = 0; o < OS; ++o) sg[wave * TH * TW + ar * TW + ac + o] = g[o];
+    __syncthreads();
+    // fixed-order sum of the wave partials and the reaction update
+    for (int e = threadIdx.x; e < TH * TW; e += NTHR) {
+        const int tr = e / TW, tc = e % TW;
         const int gr = r0 + tr, gc = c0 + tc;
-        if (gr < H && gc < W) {
-            const size_t gi = (size_t)gr * W + gc;
-            const float wc = w ? w[gi] : 0.f;
-            const float wn = wc - g[k] - theta * wc;
-            out[gi] = out_mode ? f[gi] + wn : wn;
-        }
+        if (gr >= H || gc >= W) continue;
+        float gs = 0.f;
+#pragma unroll
+        for (int q = 0; q < NWAVE; ++q) gs += sg[q * TH * TW + e];
+        const size_t gi = (size_t)gr * W + gc;
+        const float wc = w ? w[gi] : 0.f;
+        const float wn = wc - gs - theta * wc;
+        out[gi] = out_mode ? f[gi] + wn : wn;
     }
 }
 
@@ -151,15 +227,35 @@ __global__ __launch_bounds__(kThreads) void k_tnrd_stage_f32(
 
 int tnrd_grid(int H, int W) { return ((W + TW - 1) / TW) * ((H + TH - 1) / TH); }
 
+size_t tnrd_smem_bytes(int F, int J) {
+    return sizeof(float) * ((size_t)UH * UW + NWAVE * TH * TW + NWAVE * VH * VW +
+                            (size_t)F * (J + 2 * WPAD));
+}
+
 void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    const float gscale = LOG2E / (2.f * d.gamma * d.gamma);
-    const float theta = d.theta[t];
-    k_tnrd_stage_f32<<<grid, kThreads, 0, st>>>(w_prev, f, out, H, W,
-                                                d.filters + (size_t)t * d.nfilt * 25,
-                                                d.rbf_w + (size_t)t * d.nfilt * d.nrbf, d.nfilt,
-                                                d.nrbf, theta, d.mu0, d.dmu, gscale, out_mode);
+    RbfConst rc;
+    rc.mu0 = d.mu0;
+    rc.dmu = d.dmu;
+    rc.inv_dmu = 1.0f / d.dmu;
+    const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
+    rc.c = (float)c;
+    rc.two_cd = (float)(2.0 * c * d.dmu);
+    rc.b = (float)exp2(-c * (double)d.dmu * d.dmu);
+    rc.b2 = (float)exp2(-2.0 * c * (double)d.dmu * d.dmu);
+    rc.J = d.nrbf;
+    rc.K = d.kwin;
+    rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
+    const size_t smem = tnrd_smem_bytes(d.nfilt, d.nrbf);
+    const float* kf = d.filters + (size_t)t * d.nfilt * 25;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    if (rc.K == 7)
+        k_tnrd_stage_f32<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
+                                                      d.theta[t], out_mode);
+    else
+        k_tnrd_stage_f32<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
+                                                      d.theta[t], out_mode);
 }
 
 }  // namespace redve

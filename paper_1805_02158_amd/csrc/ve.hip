@@ -18,17 +18,13 @@ namespace redve {
 
 namespace {
 
-constexpr int DIFF_MAX_BLOCKS = 1024;
-
 // One pass over two consecutive iterates: u = x_new - x_old, its inner products with the
-// NC earlier columns, ||u||^2 and ||x_old||^2.
+// NC earlier columns, ||u||^2 and ||x_old||^2, published as per-workgroup partials.
 template <int NC>
 __global__ __launch_bounds__(kThreads) void k_diff_gram(const float* __restrict__ x_new,
                                                         const float* __restrict__ x_old,
-                                                        float* __restrict__ U, int ldG, int n,
-                                                        double* __restrict__ G,
-                                                        double* __restrict__ norms,
-                                                        Reduction red) {
+                                                        float* __restrict__ U, int n,
+                                                        double* __restrict__ part) {
     constexpr int NV = NC + 2;
     __shared__ double sred[NV * kThreads / 64];
     double acc[NV];
@@ -45,19 +41,7 @@ __global__ __launch_bounds__(kThreads) void k_diff_gram(const float* __restrict_
         acc[NC + 1] += (double)xo * (double)xo;
     }
     block_sum<NV>(acc, sred);
-    double tot[NV];
-    if (grid_sum<NV>(acc, tot, red, blockIdx.x, gridDim.x, sred) && threadIdx.x == 0) {
-        if (G) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) {
-                G[NC * ldG + k] = tot[k];
-                G[k * ldG + NC] = tot[k];
-            }
-            G[NC * ldG + NC] = tot[NC];
-        }
-        norms[0] = tot[NC];
-        norms[1] = tot[NC + 1];
-    }
+    publish<NV>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
 // ---- small dense FP64 algebra, one thread ----------------------------------------------
@@ -184,9 +168,36 @@ __device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma) {
     return true;
 }
 
-__global__ void k_ve_solve(const double* __restrict__ G, int ldG, int L, int method,
-                           double rank_eps, VeInfo* __restrict__ info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sums the window's published partials into the Gram matrix (fixed order, FP64), then the
+// L x L work on one thread.
+__global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part, size_t win_stride,
+                                                 int nblk, int L, int method, double rank_eps,
+                                                 VeInfo* __restrict__ info) {
+    __shared__ double G[MAXL * MAXL];
+    __shared__ double norms[2];
+    // column j's pass published values k < j (u_j . u_k), j (u_j . u_j), j + 1 (x . x)
+    for (int j = 0; j < L; ++j) {
+        const double* pj = part + (size_t)j * win_stride;
+        for (int k = 0; k <= j + 1; ++k) {
+            double s = 0.0;
+            for (int i = threadIdx.x; i < nblk; i += 64) s += pj[(size_t)k * kMaxRedBlocks + i];
+            s = wave_sum(s);
+            if (threadIdx.x == 0) {
+                if (k <= j) {
+                    G[j * MAXL + k] = s;
+                    G[k * MAXL + j] = s;
+                } else if (j == L - 1) {
+                    norms[1] = s;
+                }
+                if (k == j && j == L - 1) norms[0] = s;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    info->uu = norms[0];
+    info->xx = norms[1];
+    const int ldG = MAXL;
     // Cholesky G = R^T R (upper R). A column whose pivot falls under the rank threshold gets
     // R_ii = 0 and a zero row, as modified Gram-Schmidt gives a zero q_i for it.
     double R[MAXL][MAXL];
@@ -257,19 +268,31 @@ __global__ __launch_bounds__(kThreads) void k_ve_combine(const float* __restrict
     out[i] = (float)acc;
 }
 
-}  // namespace
-
-int diff_grid(int n) {
-    const int b = (n + kThreads - 1) / kThreads;
-    return b < DIFF_MAX_BLOCKS ? (b > 0 ? b : 1) : DIFF_MAX_BLOCKS;
+// Relative change of one FP call: sums a single difference pass (j = 0) into uu, xx.
+__global__ __launch_bounds__(64) void k_delta(const double* __restrict__ part, int nblk,
+                                              VeInfo* __restrict__ info) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 64) {
+        s0 += part[i];
+        s1 += part[kMaxRedBlocks + i];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (threadIdx.x == 0) {
+        info->uu = s0;
+        info->xx = s1;
+    }
 }
 
-void launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, int ldG, int n,
-                      double* G, double* norms, Reduction red, hipStream_t st) {
-    const int g = diff_grid(n);
-#define REDVE_DG(J)                                                                              \
-    case J:                                                                                      \
-        k_diff_gram<J><<<g, kThreads, 0, st>>>(x_new, x_old, U, ldG, n, G, norms, red);          \
+}  // namespace
+
+int launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, int n, double* part,
+                     hipStream_t st) {
+    int g = (n + kThreads - 1) / kThreads;
+    g = g < kMaxRedBlocks ? (g > 0 ? g : 1) : kMaxRedBlocks;
+#define REDVE_DG(J)                                                                   \
+    case J:                                                                           \
+        k_diff_gram<J><<<g, kThreads, 0, st>>>(x_new, x_old, U, n, part);             \
         break;
     switch (j) {
         REDVE_DG(0) REDVE_DG(1) REDVE_DG(2) REDVE_DG(3) REDVE_DG(4) REDVE_DG(5) REDVE_DG(6)
@@ -278,11 +301,16 @@ void launch_diff_gram(const float* x_new, const float* x_old, float* U, int j, i
         default: break;
     }
 #undef REDVE_DG
+    return g;
 }
 
-void launch_ve_solve(const double* G, int ldG, int L, int method, double rank_eps, VeInfo* info,
-                     hipStream_t st) {
-    k_ve_solve<<<1, 64, 0, st>>>(G, ldG, L, method, rank_eps, info);
+void launch_delta(const double* part, int nblk, VeInfo* info, hipStream_t st) {
+    k_delta<<<1, 64, 0, st>>>(part, nblk, info);
+}
+
+void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int method,
+                     double rank_eps, VeInfo* info, hipStream_t st) {
+    k_ve_solve<<<1, 64, 0, st>>>(part, win_stride, nblk, L, method, rank_eps, info);
 }
 
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,

@@ -1,0 +1,88 @@
+"""CPU checks of the algebra the GPU kernels rely on (no GPU needed).
+
+These restate, in numpy, identities the HIP kernels use in place of the oracle's literal
+steps, and check them against the oracle's plain definitions.
+"""
+import math
+
+import numpy as np
+
+import workload as W
+
+
+def _window_recurrence(z, w, mu0, dmu, gamma, K):
+    """The denoiser kernel's influence-function evaluation, in float64: nearest centre j0, one
+    exp, then term(k+1) = term(k) R_k, R_{k+1} = R_k B^2 on both sides, |k| <= K."""
+    J = len(w)
+    c = math.log2(math.e) / (2 * gamma * gamma)
+    j0 = int(np.clip(np.rint((z - mu0) / dmu), 0, J - 1))
+    d0 = z - (mu0 + dmu * j0)
+    if abs(d0) > (K + 0.5) * dmu:
+        return 0.0
+    g0 = 2.0 ** (-c * d0 * d0)
+    a, ai, b = 2.0 ** (2 * c * dmu * d0), 2.0 ** (-2 * c * dmu * d0), 2.0 ** (-c * dmu * dmu)
+    wp = lambda j: w[j] if 0 <= j < J else 0.0  # noqa: E731
+    acc = wp(j0) * g0
+    gu, ru, gd, rd = g0, a * b, g0, ai * b
+    for k in range(1, K + 1):
+        gu *= ru
+        ru *= b * b
+        gd *= rd
+        rd *= b * b
+        acc += wp(j0 + k) * gu + wp(j0 - k) * gd
+    return acc
+
+
+def test_rbf_window_recurrence_matches_full_sum(orc):
+    """Seven centres either side (gamma = dmu) reproduce the 63-term sum to 1e-12 of the
+    largest weight, over and beyond the centre range."""
+    d = W.make_denoiser()
+    z = np.concatenate([np.linspace(-420, 420, 1201), [0.0, 5.0, -5.0, 305.0, 315.0]])
+    K = max(1, math.ceil(7.4338 * d.gamma / d.dmu - 0.5))
+    assert K == 7
+    for t, i in [(0, 0), (1, 7), (3, 19), (4, 23)]:
+        w = d.rbf_w[t, i]
+        full = orc.phi(z, w, d.mu0, d.dmu, d.gamma)
+        win = np.array([_window_recurrence(v, w, d.mu0, d.dmu, d.gamma, K) for v in z])
+        assert np.abs(win - full).max() <= 1e-12 * np.abs(w).max()
+
+
+def test_correction_form_cg_equals_warm_start(orc):
+    """CG on A d = rhs - A x0 from d = 0, then x0 + d, gives the warm-started CG iterate."""
+    psf = W.psf_uniform(9)
+    rng = np.random.default_rng(0)
+    x0 = rng.uniform(0, 255, (16, 16))
+    rhs = rng.uniform(0, 100, (16, 16))
+    r0 = rhs - orc.apply_A(x0, psf, 1, math.sqrt(2), 0.02)
+    for n in (1, 5, 15):
+        d = orc.cg(r0, np.zeros_like(x0), psf, 1, math.sqrt(2), 0.02, n)
+        x = orc.cg(rhs, x0, psf, 1, math.sqrt(2), 0.02, n)
+        assert np.allclose(x0 + d, x, rtol=0, atol=1e-9 * np.abs(x).max())
+
+
+def test_residual_form_of_fp_rhs(orc):
+    """rhs - A x = H^T (y - H x) / sigma^2 + lambda (f(x) - x) for the right-hand side of eq. (7)."""
+    prob = W.problem("tiny")
+    op = orc.OracleProblem(prob)
+    x = op.y + 3.0
+    fx = op.denoise(x)
+    lhs = (op.b0 + op.lam * fx) - orc.apply_A(x, op.psf, op.s, op.sigma, op.lam)
+    rhs = (orc.apply_Ht(op.y - orc.apply_H(x, op.psf, op.s), op.shape, op.psf, op.s)
+           / op.sigma ** 2 + op.lam * (fx - x))
+    assert np.allclose(lhs, rhs, atol=1e-10 * np.abs(op.b0).max())
+
+
+def test_gram_route_extrapolation_equals_mgs_route(orc):
+    """x_m + U_{k-1} xi (the GPU's combine, with R from chol(U^T U)) equals Algorithm 1's
+    x_m + Q_{k-1} R_{k-1} xi with Q, R from modified Gram-Schmidt."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((200, 6)).cumsum(axis=1)
+    U = X[:, 1:] - X[:, :-1]
+    Q, R = orc.mgs(U)
+    Rc = np.linalg.cholesky(U.T @ U).T
+    for gfun in (orc.mpe_gamma, orc.rre_gamma, orc.svd_mpe_gamma):
+        g = gfun(Rc)
+        k = len(g) - 1
+        xi = 1.0 - np.cumsum(g)[:k]
+        via_u = X[:, 0] + U[:, :k] @ xi
+        assert np.allclose(via_u, orc.extrapolate(X[:, 0], Q, R, gfun(R)), atol=1e-9)
