@@ -37,7 +37,8 @@ struct TnrdDev {
     const float* filters;    // T*F*25
     const float* rbf_w;      // T*F*J
     float theta[kMaxStages]; // reaction weights theta_t (kernel arguments)
-    const uint16_t* filt_bf16;  // T*F*25 bf16 bits
+    const uint16_t* frag_fwd;   // per stage: 2 x 64 lanes x 8 BF16 forward-bank MFMA operands
+    const uint16_t* frag_adj;   // per stage: 2 x 64 lanes x 8 BF16 adjoint-bank MFMA operands
     int precision;
     int kwin;                   // RBF window half-width: centres beyond it add < 1e-12 w
 };
@@ -75,6 +76,10 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
 
 int tnrd_grid(int H, int W);
 size_t tnrd_smem_bytes(int F, int J);
+// Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
+void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
+                            float* out, int H, int W, int out_mode, hipStream_t st);
+size_t tnrd_bf16_smem_bytes(int F, int J);
 // One denoiser stage in residual form: w_t = w_{t-1} - sum_i K_i^T phi_i(K_i (f + w_{t-1}))
 // - theta_t w_{t-1}, with w = u - f (w_prev null: w_0 = 0). out_mode 0 writes w_t, 1 writes
 // f + w_t (= u_t).

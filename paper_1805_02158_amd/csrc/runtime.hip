@@ -59,7 +59,7 @@ struct redve_ctx {
     std::vector<float> theta;
     float* d_filt = nullptr;
     float* d_rbfw = nullptr;
-    uint16_t* d_filt_bf16 = nullptr;
+    uint16_t* d_frag = nullptr;  // BF16 MFMA operand fragments: forward then adjoint, per stage
     // solver
     int method = REDVE_VE_NONE, L = 5, m = 0;
     int cg_iters = 15, max_fp = 500, extra_fp = 0;
@@ -166,7 +166,8 @@ TnrdDev tnrd_of(redve_t h) {
     d.filters = h->d_filt;
     d.rbf_w = h->d_rbfw;
     for (int t = 0; t < h->T && t < kMaxStages; ++t) d.theta[t] = h->theta[t];
-    d.filt_bf16 = h->d_filt_bf16;
+    d.frag_fwd = h->d_frag;
+    d.frag_adj = h->d_frag ? h->d_frag + (size_t)h->T * 2 * 64 * 8 : nullptr;
     d.precision = h->precision;
     d.kwin = h->kwin;
     return d;
@@ -206,7 +207,11 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
     for (int t = 0; t < h->T; ++t) {
         const bool last = t == h->T - 1;
         float* dst = last ? out : ((t & 1) ? w.u1 : w.u0);
-        launch_tnrd_stage(d, t, wprev, x, dst, H, W, (last && !residual) ? 1 : 0, h->stream);
+        const int mode = (last && !residual) ? 1 : 0;
+        if (h->precision == REDVE_PREC_BF16)
+            launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream);
+        else
+            launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream);
         LAUNCH_CHECK(h);
         wprev = dst;
     }
@@ -322,7 +327,7 @@ int redve_destroy(redve_t h) {
     hipFree(h->d_psf64);
     hipFree(h->d_filt);
     hipFree(h->d_rbfw);
-    hipFree(h->d_filt_bf16);
+    hipFree(h->d_frag);
     hipHostFree(h->host);
     delete h;
     return REDVE_OK;
@@ -433,9 +438,9 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     hipFree(h->d_filt);
     hipFree(h->d_rbfw);
-    hipFree(h->d_filt_bf16);
+    hipFree(h->d_frag);
     h->d_filt = h->d_rbfw = nullptr;
-    h->d_filt_bf16 = nullptr;
+    h->d_frag = nullptr;
     h->T = p->stages;
     h->F = p->stages > 0 ? p->nfilt : 0;
     h->J = p->stages > 0 ? p->nrbf : 0;
@@ -448,23 +453,38 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     if (h->T > 0) {
         const size_t nf = (size_t)h->T * h->F * 25, nw = (size_t)h->T * h->F * h->J;
         std::vector<float> f(nf), w(nw);
-        std::vector<uint16_t> fb(nf);
-        for (size_t i = 0; i < nf; ++i) {
-            f[i] = (float)p->filters[i];
-            // round-to-nearest-even FP32 -> BF16
-            uint32_t bits;
-            memcpy(&bits, &f[i], 4);
-            bits += 0x7FFFu + ((bits >> 16) & 1u);
-            fb[i] = (uint16_t)(bits >> 16);
-        }
+        for (size_t i = 0; i < nf; ++i) f[i] = (float)p->filters[i];
         for (size_t i = 0; i < nw; ++i) w[i] = (float)p->rbf_w[i];
         for (int t = 0; t < h->T; ++t) h->theta[t] = (float)p->react[t];
+        // MFMA operand fragments (v_mfma_f32_16x16x32_bf16, B operand): lane l of half hf holds
+        // column n = l % 16 + 16 hf and the K values 8 (l / 16) + j. Forward: K = tap, n = filter;
+        // adjoint: K = filter, n = tap. Round to nearest even.
+        auto bf16 = [](double x) {
+            float v = (float)x;
+            uint32_t bits;
+            memcpy(&bits, &v, 4);
+            bits += 0x7FFFu + ((bits >> 16) & 1u);
+            return (uint16_t)(bits >> 16);
+        };
+        const size_t per = 2 * 64 * 8;
+        std::vector<uint16_t> frag(2 * (size_t)h->T * per, 0);
+        for (int t = 0; t < h->T; ++t)
+            for (int hf = 0; hf < 2; ++hf)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        const int kk = 8 * (l / 16) + j, n = l % 16 + 16 * hf;
+                        const size_t o = (size_t)t * per + ((size_t)hf * 64 + l) * 8 + j;
+                        const double* ft = p->filters + (size_t)t * h->F * 25;
+                        if (kk < 25 && n < h->F) frag[o] = bf16(ft[n * 25 + kk]);
+                        if (kk < h->F && n < 25) frag[(size_t)h->T * per + o] = bf16(ft[kk * 25 + n]);
+                    }
         HIP_TRY(h, hipMalloc(&h->d_filt, nf * sizeof(float)));
         HIP_TRY(h, hipMalloc(&h->d_rbfw, nw * sizeof(float)));
-        HIP_TRY(h, hipMalloc(&h->d_filt_bf16, nf * sizeof(uint16_t)));
+        HIP_TRY(h, hipMalloc(&h->d_frag, frag.size() * sizeof(uint16_t)));
         HIP_TRY(h, hipMemcpy(h->d_filt, f.data(), nf * sizeof(float), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_rbfw, w.data(), nw * sizeof(float), hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemcpy(h->d_filt_bf16, fb.data(), nf * sizeof(uint16_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_frag, frag.data(), frag.size() * sizeof(uint16_t),
+                             hipMemcpyHostToDevice));
     }
     h->have_den = true;
     return REDVE_OK;

@@ -1,0 +1,244 @@
+// Mixed-precision denoiser stage: both 5x5 filter banks on MFMA (BF16 operands, FP32
+// accumulation), influence functions and the reaction update in FP32.
+//
+// Same stage as tnrd.hip (u_t = u_{t-1} - sum_i K_i^T phi_i(K_i u_{t-1}) - theta (u_{t-1} - f),
+// carried as the residual w = u - f), reorganised as two implicit GEMMs per 16x16 tile:
+//   forward  Z[q][i] = sum_tap A[q][tap] Kf[tap][i]   q: 400 positions (tile + 2 halo, 25 groups
+//            of 16), taps 25 -> 32, filters F -> 32; A[q][tap] = u(q + tap) - u(q) (the filters
+//            have zero mean, so subtracting the window centre is exact and keeps the BF16
+//            operand small: an image value of 100 carries a BF16 error of 0.4, a local
+//            difference of 5 one of 0.02).
+//   adjoint S[q][tap] = sum_i V[q][i] Kf[tap][i]    V = phi(Z) (FP32 phi, BF16 operand),
+//            then g(p) = sum_tap S[p - off(tap)][tap] (shift-add in LDS) plus the mirror fold at
+//            the image border.
+// v_mfma_f32_16x16x32_bf16 operand layout (checked on gfx950): lane l holds row (A) or column
+// (B) l % 16 and the eight K values of slice l / 16; the accumulator holds column l % 16, rows
+// 4 (l / 16) + 0..3. The filter fragments are prepacked on the host per stage.
+#include <math.h>
+
+#include "internal.h"
+
+namespace redve {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int TH = 16, TW = 16;
+constexpr int UH = TH + 8, UW = TW + 8;  // u region: rows r0-4 .. r0+TH+3
+constexpr int VH = TH + 4, VW = TW + 4;  // positions of z / v: rows r0-2 .. r0+TH+1
+constexpr int NPOS = VH * VW;            // 400 = 25 groups of 16
+constexpr int NGRP = NPOS / 16;
+constexpr int NTHR = 512;
+constexpr int NWAVE = NTHR / 64;
+constexpr int WPAD = kMaxRbfWindow;
+static_assert(NPOS % 16 == 0, "positions must fill MFMA groups");
+
+__device__ inline int mirror(int i, int n) { return i < 0 ? -i - 1 : (i >= n ? 2 * n - i - 1 : i); }
+
+struct RbfC {
+    float mu0, dmu, inv_dmu, c, two_cd, b, b2, cutoff;
+    int J, K;
+};
+
+template <int KC>
+__device__ inline float phi_win(float z, const float* wrow, const RbfC& p) {
+    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
+    j0 = min(max(j0, 0), p.J - 1);
+    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
+    const bool live = fabsf(d0r) <= p.cutoff;
+    const float d0 = live ? d0r : 0.f;
+    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
+    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
+    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
+    const float* wc = wrow + WPAD + j0;
+    float acc = wc[0] * g0;
+    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
+#pragma unroll
+    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
+        if (KC == 0 && k > p.K) break;
+        gu *= ru;
+        ru *= p.b2;
+        gd *= rd;
+        rd *= p.b2;
+        acc += wc[k] * gu + wc[-k] * gd;
+    }
+    return acc;
+}
+
+__device__ inline bf16x8 load_frag(const uint16_t* p) {
+    // eight packed BF16 values (16 bytes, aligned)
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, 16);
+    return r;
+}
+
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const uint16_t* __restrict__ bfwd /* 2 x 64 x 8 */, const uint16_t* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+    extern __shared__ float smem[];
+    // One row per position holds z, then v = phi(z), then the 25 per-tap adjoint sums (a wave
+    // overwrites the rows of its own MFMA group after loading them as an operand).
+    const int ZS = (F > 25 ? F : 25) | 1;
+    float* su = smem;                 // UH * UW
+    float* sz = su + UH * UW;         // NPOS * ZS
+    float* ss = sz;
+    float* sw = sz + NPOS * ZS;       // F * (J + 2 WPAD)
+    const int wstride = rc.J + 2 * WPAD;
+    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
+        const int er = r0 - 4 + e / UW, ec = c0 - 4 + e % UW;
+        float val = 0.f;
+        if (er >= -2 && er <= H + 1 && ec >= -2 && ec <= W + 1) {
+            const size_t g = (size_t)mirror(er, H) * W + mirror(ec, W);
+            val = w ? f[g] + w[g] : f[g];
+        }
+        su[e] = val;
+    }
+    for (int e = threadIdx.x; e < F * wstride; e += NTHR) {
+        const int i = e / wstride, j = e % wstride - WPAD;
+        sw[e] = (j >= 0 && j < rc.J) ? rbfw[i * rc.J + j] : 0.f;
+    }
+    __syncthreads();
+
+    const int m = lane & 15, sl = lane >> 4;  // fragment row/column, K slice
+    // ---- forward bank: Z = A Kf on MFMA, one group of 16 positions per step
+    {
+        const bf16x8 b0 = load_frag(bfwd + (0 * 64 + lane) * 8);
+        const bf16x8 b1 = load_frag(bfwd + (1 * 64 + lane) * 8);
+        for (int grp = wave; grp < NGRP; grp += NWAVE) {
+            const int q = grp * 16 + m;
+            const int vr = q / VW, vc = q % VW;
+            const float centre = su[(vr + 2) * UW + vc + 2];
+            bf16x8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int tap = sl * 8 + j;
+                float x = 0.f;
+                if (tap < 25) x = su[(vr + tap / 5) * UW + vc + tap % 5] - centre;
+                a[j] = (__bf16)x;
+            }
+            f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+            z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, z0, 0, 0, 0);
+            z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, z1, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qq = grp * 16 + sl * 4 + i;
+                sz[qq * ZS + m] = z0[i];
+                if (m + 16 < F) sz[qq * ZS + m + 16] = z1[i];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- influence functions, dense over (position, filter) pairs, FP32
+    for (int e = threadIdx.x; e < NPOS * F; e += NTHR) {
+        const int q = e / F, i = e % F;
+        const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
+        float v = 0.f;
+        if (gr >= 0 && gr < H && gc >= 0 && gc < W) v = phi_win<KC>(sz[q * ZS + i], sw + i * wstride, rc);
+        sz[q * ZS + i] = v;
+    }
+    __syncthreads();
+    // ---- adjoint bank: S = V Kf^T on MFMA
+    {
+        const bf16x8 b0 = load_frag(badj + (0 * 64 + lane) * 8);
+        const bf16x8 b1 = load_frag(badj + (1 * 64 + lane) * 8);
+        for (int grp = wave; grp < NGRP; grp += NWAVE) {
+            const int q = grp * 16 + m;
+            bf16x8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = sl * 8 + j;
+                a[j] = (__bf16)(i < F ? sz[q * ZS + i] : 0.f);
+            }
+            f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+            s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, s0, 0, 0, 0);
+            s1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, s1, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qq = grp * 16 + sl * 4 + i;
+                ss[qq * ZS + m] = s0[i];
+                if (m + 16 < 25) ss[qq * ZS + m + 16] = s1[i];
+            }
+        }
+    }
+    __syncthreads();
+    // ---- shift-add of the tap sums, mirror fold at the border, reaction update
+    for (int e = threadIdx.x; e < TH * TW; e += NTHR) {
+        const int tr = e / TW, tc = e % TW;
+        const int gr = r0 + tr, gc = c0 + tc;
+        if (gr >= H || gc >= W) continue;
+        float g = 0.f;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) g += ss[((tr + 4 - a) * VW + tc + 4 - b) * ZS + a * 5 + b];
+        if (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) {
+            const int cr[3] = {gr, -1 - gr, 2 * H - 1 - gr};
+            const int cc[3] = {gc, -1 - gc, 2 * W - 1 - gc};
+            for (int x = 0; x < 3; ++x) {
+                const int er = cr[x];
+                if (er < -2 || er > H + 1) continue;
+                for (int y = 0; y < 3; ++y) {
+                    const int ec = cc[y];
+                    if (ec < -2 || ec > W + 1 || (x == 0 && y == 0)) continue;
+                    for (int a = 0; a < 5; ++a) {
+                        const int vr = er - a + 2;
+                        if (vr < 0 || vr >= H) continue;
+                        for (int b = 0; b < 5; ++b) {
+                            const int vc = ec - b + 2;
+                            if (vc < 0 || vc >= W) continue;
+                            g += ss[((vr - r0 + 2) * VW + vc - c0 + 2) * ZS + a * 5 + b];
+                        }
+                    }
+                }
+            }
+        }
+        const size_t gi = (size_t)gr * W + gc;
+        const float wc = w ? w[gi] : 0.f;
+        const float wn = wc - g - theta * wc;
+        out[gi] = out_mode ? f[gi] + wn : wn;
+    }
+}
+
+}  // namespace
+
+size_t tnrd_bf16_smem_bytes(int F, int J) {
+    const int zs = (F > 25 ? F : 25) | 1;
+    return sizeof(float) * ((size_t)UH * UW + (size_t)NPOS * zs + (size_t)F * (J + 2 * WPAD));
+}
+
+void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
+                            float* out, int H, int W, int out_mode, hipStream_t st) {
+    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+    RbfC rc;
+    rc.mu0 = d.mu0;
+    rc.dmu = d.dmu;
+    rc.inv_dmu = 1.0f / d.dmu;
+    const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
+    rc.c = (float)c;
+    rc.two_cd = (float)(2.0 * c * d.dmu);
+    rc.b = (float)exp2(-c * (double)d.dmu * d.dmu);
+    rc.b2 = (float)exp2(-2.0 * c * (double)d.dmu * d.dmu);
+    rc.J = d.nrbf;
+    rc.K = d.kwin;
+    rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
+    const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
+    const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
+    const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    if (rc.K == 7)
+        k_tnrd_stage_bf16<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                                       rc, d.theta[t], out_mode);
+    else
+        k_tnrd_stage_bf16<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                                       rc, d.theta[t], out_mode);
+}
+
+}  // namespace redve

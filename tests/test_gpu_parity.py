@@ -393,3 +393,54 @@ def test_errors(torch):
     with pytest.raises(P.RedveError) as e:
         r.solve(torch.zeros((1, 1), device="cuda"), 1, 1)
     assert e.value.code == P.E_ARG
+
+
+# ------------------------------------------------------------------ mixed precision (BF16 banks)
+# Bar for the BF16 form: 5e-3 relative L2 and 0.05 dB PSNR against the FP64 oracle.
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (37, 53), (3, 5), (256, 256)])
+def test_denoiser_bf16(torch, orc, shape):
+    """BF16 filter banks (per-window centred operands, FP32 accumulation): the denoiser update
+    f(x) - x matches the oracle's to 2e-2 relative L2 (BF16 keeps 8 significant bits, 3.9e-3 of
+    each operand)."""
+    say("denoiser bf16", shape)
+    d = W.make_denoiser()
+    r = restorer()
+    r.set_denoiser(d, "bf16")
+    x = f32(W.make_image(*shape, 77) + 5 * W.make_noise(shape, 78))
+    g = host(r.denoise(dev(torch, x)))
+    o = orc.denoise(x, orc.Denoiser(d))
+    err = rel(g - x, o - x)
+    say(f"  update rel L2 {err:.2e}")
+    assert err <= 2e-2
+    c = np.full((24, 40), 88.0)
+    assert np.abs(host(r.denoise(dev(torch, c))) - 88.0).max() <= 1e-3
+
+
+def _converged_bf16(torch, orc, prob, method, L, tol=1e-5, calls=400):
+    y32 = f32(orc.OracleProblem(prob).y)
+    op = orc.OracleProblem(prob, y=y32)
+    r = restorer(prob, precision="bf16", method=method, L=L, tol=tol, max_fp_calls=calls)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    xg = host(x)
+    ref = orc.solve(op, method, L=L, m=0, tol=1e-8, max_calls=calls)
+    err = rel(xg, ref.x)
+    dp = orc.psnr(xg, prob.x_true) - orc.psnr(ref.x, prob.x_true)
+    say(f"  stats {st}")
+    say(f"  rel L2 vs oracle fixed point {err:.2e}, dPSNR {dp:+.4f} dB")
+    return err, dp
+
+
+def test_solve_bf16_deblur(torch, orc):
+    say("solve bf16 deblur 256")
+    err, dp = _converged_bf16(torch, orc, W.problem("c1"), "rre", 5)
+    assert err <= 5e-3 and abs(dp) <= 0.05
+
+
+def test_solve_bf16_sr_512(torch, orc):
+    """The mixed-precision workload at full size: 512x512, Gaussian 7x7 + 3x decimation,
+    sigma 5, RRE with L = 8, FP64 Gram and small solve."""
+    say("solve bf16 sr 512")
+    err, dp = _converged_bf16(torch, orc, W.problem("c2"), "rre", 8, calls=300)
+    assert err <= 5e-3 and abs(dp) <= 0.05
