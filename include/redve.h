@@ -148,6 +148,61 @@ int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, flo
 int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* out,
                       double* gamma, int* breakdown);
 
+/* ---- batched solve (many images of different sizes in one set of launches) ------------- */
+
+/* One restoration of a batch or a serving request. Device pointers are caller-owned and must
+ * stay valid until the call returns (batch) or the request is done (server). */
+typedef struct {
+    const float* y;     /* device, ceil(hx/decim) x ceil(wx/decim): observation of eq. (1)  */
+    const float* x0;    /* device, hx x wx, or NULL: y (decim 1) or decim^2 H^T y            */
+    float* x;           /* device, hx x wx: receives the result                              */
+    int hx, wx;         /* image size (>= 2 each)                                            */
+    const double* psf;  /* host, kh x kw (odd, <= 15): the blur of H = S B (copied by the call
+                           or, for the server, at submit)                                  */
+    int kh, kw;
+    int decim;          /* S: 1 deblurring, 3 super-resolution (1..4)                        */
+    double sigma;       /* noise standard deviation of eq. (1), > 0                          */
+    double lambda;      /* weight lambda of eq. (2), > 0                                     */
+} redve_item_t;
+
+/* Solves n independent problems at once (the denoiser, extrapolation and solver settings of
+ * the handle apply to all; the handle's operator, sigma and lambda are not used): every kernel
+ * of an FP call (eq. (7)) runs once over a tile list of the running images, each FP call is one
+ * replay of a captured HIP graph, and converged images drop out of the list. Reductions are per
+ * image, in a fixed order, so each image's result does not depend on the other images in the
+ * batch. Waits for the handle's stream before reading the inputs; allocates its workspace
+ * (about 4 (14 + L) bytes per pixel) for the call. st: n entries (host) or NULL; st[i].status
+ * is the item's own outcome. Returns REDVE_OK, an argument/HIP error, or the first non-OK item
+ * status. */
+int redve_solve_batch(redve_t h, int n, const redve_item_t* items, redve_stats_t* st);
+
+/* ---- serving: continuous batching of arriving requests --------------------------------- */
+
+typedef struct redve_server* redve_server_t;
+
+/* A scheduler thread with its own stream and a copy of proto's denoiser, extrapolation and
+ * solver settings (proto must have a denoiser and must outlive the server: the denoiser's
+ * device buffers are shared). The server allocates its whole workspace here, within
+ * hbm_budget bytes (4 (14 + L) bytes per pixel of capacity); requests are admitted in arrival
+ * order while their pixels fit (and at most max_active run at once). Every round advances each
+ * admitted request by one FP call (one batched launch sequence), extrapolates those that
+ * complete a window, retires the finished ones and admits queued ones. Each request's result
+ * is the same alone and in any mix. */
+int redve_server_create(redve_server_t* out, redve_t proto, size_t hbm_budget, int max_active);
+/* Queues a request (does not wait for the GPU); *ticket identifies it. The inputs are read
+ * after the work queued so far on proto's stream. The item's device buffers must live until
+ * the request is done. REDVE_E_NOMEM: the request could never fit the server's capacity. */
+int redve_server_submit(redve_server_t s, const redve_item_t* item, unsigned long long* ticket);
+/* *done = 1 once the request finished; st (host, may be NULL) then receives its statistics
+ * (st->ms = submit-to-completion latency). */
+int redve_server_poll(redve_server_t s, unsigned long long ticket, int* done, redve_stats_t* st);
+/* Blocks until the request finished. */
+int redve_server_wait(redve_server_t s, unsigned long long ticket, redve_stats_t* st);
+/* Requests queued, running, finished so far, and rounds executed. */
+int redve_server_counts(redve_server_t s, int* queued, int* active, int* finished, long long* rounds);
+/* Waits for every submitted request, stops the scheduler, frees everything. */
+int redve_server_destroy(redve_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,9 @@ EXPORTS = (
     "redve_workspace_bytes", "redve_set_operator", "redve_set_noise", "redve_set_lambda",
     "redve_set_denoiser", "redve_set_extrapolation", "redve_set_solver", "redve_solve",
     "redve_apply_H", "redve_apply_Ht", "redve_apply_A", "redve_cg", "redve_denoise",
-    "redve_fp_step", "redve_extrapolate",
+    "redve_fp_step", "redve_extrapolate", "redve_solve_batch", "redve_server_create",
+    "redve_server_submit", "redve_server_poll", "redve_server_wait", "redve_server_counts",
+    "redve_server_destroy",
 )
 
 
@@ -44,6 +46,14 @@ class _Tnrd(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("filters", ctypes.POINTER(ctypes.c_double)),
                 ("rbf_w", ctypes.POINTER(ctypes.c_double)),
                 ("react", ctypes.POINTER(ctypes.c_double)), ("precision", ctypes.c_int)]
+
+
+class Item(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("hx", ctypes.c_int), ("wx", ctypes.c_int),
+                ("psf", ctypes.POINTER(ctypes.c_double)), ("kh", ctypes.c_int),
+                ("kw", ctypes.c_int), ("decim", ctypes.c_int), ("sigma", ctypes.c_double),
+                ("lam", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -89,6 +99,14 @@ def load_library(path: str = LIB_PATH):
         "redve_denoise": ([vp, vp, i, i, vp], i),
         "redve_fp_step": ([vp, vp, vp, i, i, vp], i),
         "redve_extrapolate": ([vp, vp, i, i, i, vp, dp, ctypes.POINTER(i)], i),
+        "redve_solve_batch": ([vp, i, ctypes.POINTER(Item), ctypes.POINTER(Stats)], i),
+        "redve_server_create": ([ctypes.POINTER(vp), vp, sz, i], i),
+        "redve_server_submit": ([vp, ctypes.POINTER(Item), ctypes.POINTER(ctypes.c_ulonglong)], i),
+        "redve_server_poll": ([vp, ctypes.c_ulonglong, ctypes.POINTER(i), ctypes.POINTER(Stats)], i),
+        "redve_server_wait": ([vp, ctypes.c_ulonglong, ctypes.POINTER(Stats)], i),
+        "redve_server_counts": ([vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                 ctypes.POINTER(ctypes.c_longlong)], i),
+        "redve_server_destroy": ([vp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -260,6 +278,29 @@ class Restorer:
                                           _dev(x), hx, wx, _dev(out)))
         return out
 
+    def make_item(self, y, hx, wx, psf, decim, sigma, lam, x0=None, out=None):
+        """Describes one problem for solve_batch / Server.submit (keeps the host PSF alive)."""
+        torch = self._torch
+        if out is None:
+            out = torch.empty((hx, wx), dtype=torch.float32, device=y.device)
+        a, pp = _f64p(psf)
+        it = Item(_dev(y, lr_shape(hx, wx, decim)), _dev(x0, (hx, wx)), _dev(out, (hx, wx)),
+                  int(hx), int(wx), pp, a.shape[0], a.shape[1], int(decim), float(sigma),
+                  float(lam))
+        return it, out, a
+
+    def solve_batch(self, problems):
+        """problems: list of dicts with y, hx, wx, psf, decim, sigma, lam (and optional x0, out).
+        Returns (outputs, stats) in the same order."""
+        made = [self.make_item(**p) for p in problems]
+        arr = (Item * len(made))(*[m[0] for m in made])
+        st = (Stats * len(made))()
+        rc = self._L.redve_solve_batch(self._h, len(made), arr, st)
+        stats = [s.as_dict() for s in st]
+        if rc != OK and not any(s["status"] for s in stats):
+            self._check(rc)
+        return [m[1] for m in made], stats
+
     def extrapolate(self, xs):
         """xs: (L+1, h, w) stacked iterates -> (x_new, gamma, breakdown)."""
         n1, hx, wx = xs.shape
@@ -271,3 +312,60 @@ class Restorer:
                                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                               ctypes.byref(bd)))
         return out, g, bool(bd.value)
+
+
+class Server:
+    """Continuous-batching restoration server (include/redve.h, redve_server_*). It copies the
+    settings of a configured Restorer; requests are admitted by device-memory budget."""
+
+    def __init__(self, proto: Restorer, hbm_budget: int, max_active: int = 64):
+        self._L = proto._L
+        self._proto = proto
+        h = ctypes.c_void_p()
+        rc = self._L.redve_server_create(ctypes.byref(h), proto._h, int(hbm_budget),
+                                         int(max_active))
+        if rc != OK:
+            raise RedveError(rc, "redve_server_create failed")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, y, hx, wx, psf, decim, sigma, lam, x0=None, out=None):
+        it, out, psf_arr = self._proto.make_item(y, hx, wx, psf, decim, sigma, lam, x0, out)
+        t = ctypes.c_ulonglong()
+        rc = self._L.redve_server_submit(self._h, ctypes.byref(it), ctypes.byref(t))
+        if rc != OK:
+            raise RedveError(rc, "redve_server_submit failed")
+        self._keep[t.value] = (y, x0, out)
+        return t.value, out
+
+    def poll(self, ticket):
+        done = ctypes.c_int()
+        st = Stats()
+        self._L.redve_server_poll(self._h, ctypes.c_ulonglong(ticket), ctypes.byref(done),
+                                  ctypes.byref(st))
+        return bool(done.value), (st.as_dict() if done.value else None)
+
+    def wait(self, ticket):
+        st = Stats()
+        rc = self._L.redve_server_wait(self._h, ctypes.c_ulonglong(ticket), ctypes.byref(st))
+        if rc != OK:
+            raise RedveError(rc, "redve_server_wait failed")
+        self._keep.pop(ticket, None)
+        return st.as_dict()
+
+    def counts(self):
+        q, a, f, r = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong()
+        self._L.redve_server_counts(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(f),
+                                    ctypes.byref(r))
+        return {"queued": q.value, "active": a.value, "finished": f.value, "rounds": r.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            self._L.redve_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

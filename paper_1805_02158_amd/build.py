@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libredve.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["linear.hip", "tnrd.hip", "tnrd_mfma.hip", "ve.hip", "runtime.hip"]
+SOURCES = ["linear.hip", "tnrd.hip", "tnrd_mfma.hip", "ve.hip", "runtime.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

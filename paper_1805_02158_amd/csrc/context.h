@@ -1,0 +1,73 @@
+// Private definition of the library handle (shared by the single-image runtime and the
+// batched / serving engine).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/redve.h"
+#include "internal.h"
+
+namespace redve_detail {
+
+using redve::VeInfo;
+constexpr size_t kAlign = 256;
+
+struct Workspace {
+    void* arena = nullptr;
+    size_t bytes = 0;
+    size_t cap_px = 0;
+    int cap_L = 0;
+    float *xa, *xb, *xc, *sres, *u0, *u1, *r[2], *w[2], *s[2], *p, *d, *U;
+    double* cg_part;  // two slots of published (rho, mu) partials
+    double* cg_hist;  // two slots of (alpha, rho) of the previous CG iteration
+    double* ve_part;  // window partials: column j at j * win_stride
+    size_t win_stride;
+    VeInfo* info;
+};
+
+struct HostMirror {
+    VeInfo info;
+};
+
+}  // namespace redve_detail
+
+using redve_detail::kAlign;
+using redve_detail::Workspace;
+using redve_detail::HostMirror;
+
+struct redve_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t bstream = nullptr;  // the batched engine's own stream (created on first use)
+    std::string err;
+    // operator H = S B
+    bool have_op = false;
+    std::vector<float> psf;
+    int kh = 0, kw = 0, decim = 1;
+    float* d_psf = nullptr;
+    double* d_psf64 = nullptr;
+    int separable = 0;
+    double row[REDVE_MAX_PSF], col[REDVE_MAX_PSF];  // psf = col (x) row when separable
+    // sigma, lambda
+    double sigma = -1.0, lambda = -1.0;
+    // denoiser
+    bool have_den = false;
+    int T = 0, F = 0, J = 0, precision = REDVE_PREC_FP32, kwin = 7;
+    double mu0 = 0, dmu = 0, gamma = 1;
+    std::vector<float> theta;
+    float* d_filt = nullptr;
+    float* d_rbfw = nullptr;
+    uint16_t* d_frag = nullptr;  // BF16 MFMA operand fragments: forward then adjoint, per stage
+    // solver
+    int method = REDVE_VE_NONE, L = 5, m = 0;
+    int cg_iters = 15, max_fp = 500, extra_fp = 0;
+    double tol = 1e-5;
+    double rank_eps = 1e-7;  // R_jj <= rank_eps * R_00 counts as rank deficient (FP32 data)
+    Workspace ws;
+    HostMirror* host = nullptr;  // pinned
+};
+
+// Device view of the handle's denoiser (runtime.hip).
+redve::TnrdDev redve_tnrd_dev(redve_t h);
+

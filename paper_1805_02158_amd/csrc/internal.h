@@ -30,6 +30,60 @@ struct LinOp {
     double row_d[kMaxPsf], col_d[kMaxPsf];
 };
 
+// One image of a batch (batched kernels take a device array of these and a tile list that maps
+// every 16x16 tile of every image to its image).
+struct ImgDesc {
+    int H, W;          // image size
+    int tile0, ntiles; // this image's range in the batch tile list
+    int active;        // 0: every batched kernel skips the image
+    int wj;            // window column the difference pass of this FP call writes (-1: none)
+    int do_ve;         // 1: this round completes the image's window: extrapolate
+    int pad0;
+    size_t off;        // element offset of the image in every per-image workspace array
+    const float* y;    // observation (caller-owned device memory)
+    const float* x_in; // this FP call's input iterate
+    float* x_out;      // this FP call's output iterate
+    float* x_m;        // window base x_m (extrapolation combines into it)
+    LinOp op;
+};
+constexpr int kBatchTile = 16;  // side of the tiles of the batch tile list
+
+struct VeInfo;
+
+// Per-image results of a batched round, read back by the host.
+struct ImgStat {
+    double uu, xx;     // ||x_out - x_in||^2, ||x_in||^2 of this FP call
+    double gamma_l1;   // sum |gamma| of the extrapolation (0 if none)
+    int breakdown;     // 1 if the extrapolation did not exist
+    int pad;
+};
+// Per-image CG scalars of the batched single-reduction CG.
+struct CgImg {
+    double alpha, beta;            // this iteration's step and direction weights
+    double alpha_prev, rho_prev;   // the previous iteration's alpha and rho
+};
+
+// Batched CG (see linear.hip). Partials are per tile (value v of tile T at part[v * cap + T]).
+void launch_cg_init_fp_batch(const ImgDesc* desc, const int* tile_img, int ntiles,
+                             const float* sres /* null: f = identity */, float* r, hipStream_t st);
+void launch_cg_w0_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs,
+                        const float* r, float* w, double* part, int cap, hipStream_t st);
+void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
+                         CgImg* cg, hipStream_t st);
+void launch_cg_iter_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs, int k,
+                          int last, const CgImg* cg, const float* r_in, const float* w_in,
+                          const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
+                          float* d, double* part, int cap, hipStream_t st);
+// Batched VE (see ve.hip).
+void launch_diff_gram_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int L, float* U,
+                            size_t ustride, double* part, int cap, hipStream_t st);
+void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* part, int cap,
+                           double* G, ImgStat* stat, hipStream_t st);
+void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
+                           const double* G, VeInfo* info, ImgStat* stat, hipStream_t st);
+void launch_ve_combine_batch(const ImgDesc* desc, const int* tile_img, int ntiles, const float* U,
+                             size_t ustride, const VeInfo* info, hipStream_t st);
+
 // Denoiser parameters on the device (FP32; BF16 copies of the filters for the MFMA path).
 struct TnrdDev {
     int stages, nfilt, nrbf;
@@ -76,6 +130,14 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
 
 int tnrd_grid(int H, int W);
 size_t tnrd_smem_bytes(int F, int J);
+// Batched stage over the tile list; vectors are base pointers of per-image arrays.
+// f is each image's x_in (from its descriptor).
+void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const int* tile_img,
+                             int ntiles, const float* w_prev, float* out, int out_mode,
+                             hipStream_t st);
+void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
+                                  const int* tile_img, int ntiles, const float* w_prev, float* out,
+                                  int out_mode, hipStream_t st);
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st);

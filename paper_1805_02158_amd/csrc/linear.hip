@@ -242,6 +242,97 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const LinOp op, const floa
     }
 }
 
+struct InitFpSmem {
+    float sp[PH * PW];
+    double se[PH * PW];
+    double sh[PH * PW];
+};
+
+// r = H^T (y - H x) / sigma^2 + lambda s on the tile at (r0, c0); FP64 sums.
+__device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x,
+                                    const float* __restrict__ y, const float* __restrict__ s,
+                                    float* __restrict__ r, int H, int W, int r0, int c0,
+                                    InitFpSmem& sm) {
+    float* sp = sm.sp;
+    double* se = sm.se;
+    double* sh = sm.sh;
+    const int rh = op.kh / 2, rw = op.kw / 2, dec = op.decim;
+    const int ph = TH + 4 * rh, pw = TW + 4 * rw;
+    const int bh = TH + 2 * rh, bw = TW + 2 * rw;
+    const int wy = (W + dec - 1) / dec;
+    for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
+        const int pr = e / pw, pc = e % pw;
+        sp[pr * PW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
+    }
+    __syncthreads();
+    if (op.separable) {
+        for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
+            const int pr = e / bw, bc = e % bw;
+            const float* prow = sp + pr * PW + bc + 2 * rw;
+            double a = 0.0;
+            for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * (double)prow[-b];
+            sh[pr * PW + bc] = a;
+        }
+        __syncthreads();
+    }
+    // e = S^T (y - S B x) on the tile + r halo, FP64
+    for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+        const int br = e / bw, bc = e % bw;
+        const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
+        double v = 0.0;
+        if (gr % dec == 0 && gc % dec == 0) {
+            double bx = 0.0;
+            if (op.separable) {
+                const double* hcol = sh + (br + 2 * rh) * PW + bc;
+                for (int a = 0; a < op.kh; ++a) bx += op.col_d[a] * hcol[-a * PW];
+            } else {
+                for (int a = -rh; a <= rh; ++a) {
+                    const float* prow = sp + (br + rh - a) * PW + bc + rw;
+                    const double* krow = op.psf64 + (a + rh) * op.kw + rw;
+                    for (int b = -rw; b <= rw; ++b) bx += krow[b] * (double)prow[-b];
+                }
+            }
+            v = (double)y[(size_t)(gr / dec) * wy + gc / dec] - bx;
+        }
+        se[br * PW + bc] = v;
+    }
+    __syncthreads();
+    if (op.separable) {
+        for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
+            const int br = e / TW, tc = e % TW;
+            const double* erow = se + br * PW + tc;
+            double a = 0.0;
+            for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * erow[b];
+            sh[br * PW + tc] = a;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+        const int o = threadIdx.x + k * kThreads;
+        const int tr = o / TW, tc = o % TW;
+        const int gr = r0 + tr, gc = c0 + tc;
+        double bt = 0.0;
+        if (op.separable) {
+            const double* hcol = sh + tr * PW + tc;
+            for (int a = 0; a < op.kh; ++a) bt += op.col_d[a] * hcol[a * PW];
+        } else {
+            for (int a = -rh; a <= rh; ++a) {
+                const double* erow = se + (tr + a + rh) * PW + tc + rw;
+                const double* krow = op.psf64 + (a + rh) * op.kw + rw;
+                for (int b = -rw; b <= rw; ++b) bt += krow[b] * erow[b];
+            }
+        }
+        if (gr < H && gc < W) {
+            const size_t g = (size_t)gr * W + gc;
+            double rv = op.inv_s2_d * bt;
+            if (s) rv += op.lambda_d * (double)s[g];
+            r[g] = (float)rv;
+        }
+    }
+    __syncthreads();
+}
+
 // CG start of one FP call (eq. (7)) in residual form. With rhs = H^T y / sigma^2 + lambda f(x),
 //   r = rhs - A x = H^T (y - H x) / sigma^2 + lambda (f(x) - x),
 // both terms small near the fixed point; the data term is accumulated in FP64 from the FP32
@@ -251,87 +342,30 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const f
                                                          const float* __restrict__ y,
                                                          const float* __restrict__ s,
                                                          float* __restrict__ r, int H, int W) {
-    __shared__ float sp[PH * PW];
-    __shared__ double se[PH * PW];
-    __shared__ double sh[PH * PW];
-    const int rh = op.kh / 2, rw = op.kw / 2, dec = op.decim;
-    const int ph = TH + 4 * rh, pw = TW + 4 * rw;
-    const int bh = TH + 2 * rh, bw = TW + 2 * rw;
-    const int wy = (W + dec - 1) / dec;
+    __shared__ InitFpSmem sm;
     for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
         int r0, c0;
         tile_origin(t, W, r0, c0);
-        for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
-            const int pr = e / pw, pc = e % pw;
-            sp[pr * PW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
-        }
-        __syncthreads();
-        if (op.separable) {
-            for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
-                const int pr = e / bw, bc = e % bw;
-                const float* prow = sp + pr * PW + bc + 2 * rw;
-                double a = 0.0;
-                for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * (double)prow[-b];
-                sh[pr * PW + bc] = a;
-            }
-            __syncthreads();
-        }
-        // e = S^T (y - S B x) on the tile + r halo, FP64
-        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
-            const int br = e / bw, bc = e % bw;
-            const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
-            double v = 0.0;
-            if (gr % dec == 0 && gc % dec == 0) {
-                double bx = 0.0;
-                if (op.separable) {
-                    const double* hcol = sh + (br + 2 * rh) * PW + bc;
-                    for (int a = 0; a < op.kh; ++a) bx += op.col_d[a] * hcol[-a * PW];
-                } else {
-                    for (int a = -rh; a <= rh; ++a) {
-                        const float* prow = sp + (br + rh - a) * PW + bc + rw;
-                        const double* krow = op.psf64 + (a + rh) * op.kw + rw;
-                        for (int b = -rw; b <= rw; ++b) bx += krow[b] * (double)prow[-b];
-                    }
-                }
-                v = (double)y[(size_t)(gr / dec) * wy + gc / dec] - bx;
-            }
-            se[br * PW + bc] = v;
-        }
-        __syncthreads();
-        if (op.separable) {
-            for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
-                const int br = e / TW, tc = e % TW;
-                const double* erow = se + br * PW + tc;
-                double a = 0.0;
-                for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * erow[b];
-                sh[br * PW + tc] = a;
-            }
-            __syncthreads();
-        }
+        init_fp_tile(op, x, y, s, r, H, W, r0, c0, sm);
+    }
+}
+
+// w0 = A r0 on one tile; accumulates r0.r0 and w0.r0.
+template <int RS>
+__device__ inline void w0_tile(const LinOp& op, const float* __restrict__ r, float* __restrict__ w,
+                               int H, int W, int r0, int c0, TileSmem& sm, double (&acc)[2]) {
+    tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return r[g]; });
+    float pc[NO], q[NO];
+    tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
 #pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            const int o = threadIdx.x + k * kThreads;
-            const int tr = o / TW, tc = o % TW;
-            const int gr = r0 + tr, gc = c0 + tc;
-            double bt = 0.0;
-            if (op.separable) {
-                const double* hcol = sh + tr * PW + tc;
-                for (int a = 0; a < op.kh; ++a) bt += op.col_d[a] * hcol[a * PW];
-            } else {
-                for (int a = -rh; a <= rh; ++a) {
-                    const double* erow = se + (tr + a + rh) * PW + tc + rw;
-                    const double* krow = op.psf64 + (a + rh) * op.kw + rw;
-                    for (int b = -rw; b <= rw; ++b) bt += krow[b] * erow[b];
-                }
-            }
-            if (gr < H && gc < W) {
-                const size_t g = (size_t)gr * W + gc;
-                double rv = op.inv_s2_d * bt;
-                if (s) rv += op.lambda_d * (double)s[g];
-                r[g] = (float)rv;
-            }
+    for (int k = 0; k < NO; ++k) {
+        const int o = threadIdx.x + k * kThreads;
+        const int gr = r0 + o / TW, gc = c0 + o % TW;
+        if (gr < H && gc < W) {
+            w[(size_t)gr * W + gc] = q[k];
+            acc[0] += (double)pc[k] * (double)pc[k];
+            acc[1] += (double)q[k] * (double)pc[k];
         }
-        __syncthreads();
     }
 }
 
@@ -346,22 +380,80 @@ __global__ __launch_bounds__(kThreads) void k_cg_w0(const LinOp op, const float*
     for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
         int r0, c0;
         tile_origin(t, W, r0, c0);
-        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return r[g]; });
-        float pc[NO], q[NO];
-        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
-#pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            const int o = threadIdx.x + k * kThreads;
-            const int gr = r0 + o / TW, gc = c0 + o % TW;
-            if (gr < H && gc < W) {
-                w[(size_t)gr * W + gc] = q[k];
-                acc[0] += (double)pc[k] * (double)pc[k];
-                acc[1] += (double)q[k] * (double)pc[k];
-            }
-        }
+        w0_tile<RS>(op, r, w, H, W, r0, c0, sm, acc);
     }
     block_sum<2>(acc, sred);
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
+// Step lengths of the single-reduction CG from rho_k, mu_k and the previous iteration's
+// alpha and rho (a vanished residual gives alpha = beta = 0: the iteration stops moving).
+__device__ inline void cg_scalars(int k, double rho, double mu, double alpha_prev, double rho_prev,
+                                  double& alpha, double& beta) {
+    alpha = 0.0;
+    beta = 0.0;
+    if (rho > 1e-300) {
+        if (k == 0) {
+            alpha = mu > 0.0 ? rho / mu : 0.0;
+        } else {
+            beta = rho_prev > 1e-300 ? rho / rho_prev : 0.0;
+            const double den = alpha_prev != 0.0 ? mu - beta * rho / alpha_prev : 0.0;
+            alpha = den > 0.0 ? rho / den : 0.0;
+        }
+    }
+}
+
+// One single-reduction CG iteration on one tile (see k_cg_iter); accumulates rho_{k+1}, mu_{k+1}.
+template <int RS>
+__device__ inline void cg_iter_tile(const LinOp& op, int H, int W, int r0, int c0, int k,
+                                    float alpha, float beta, const float* __restrict__ r_in,
+                                    const float* __restrict__ w_in, const float* __restrict__ s_in,
+                                    float* __restrict__ r_out, float* __restrict__ w_out,
+                                    float* __restrict__ s_out, float* __restrict__ p,
+                                    float* __restrict__ d, TileSmem& sm, double (&acc)[2]) {
+    tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) {
+        const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
+        return r_in[g] - alpha * sk;
+    });
+    float r1[NO], w1[NO];
+    tile_A_from_lds<RS>(op, H, W, r0, c0, sm, r1, w1);
+#pragma unroll
+    for (int kk = 0; kk < NO; ++kk) {
+        const int o = threadIdx.x + kk * kThreads;
+        const int gr = r0 + o / TW, gc = c0 + o % TW;
+        if (gr < H && gc < W) {
+            const size_t g = (size_t)gr * W + gc;
+            const float rk = r_in[g];
+            const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
+            const float pk = k ? rk + beta * p[g] : rk;
+            const float dn = k ? d[g] + alpha * pk : alpha * pk;
+            s_out[g] = sk;
+            p[g] = pk;
+            d[g] = dn;
+            r_out[g] = r1[kk];
+            w_out[g] = w1[kk];
+            acc[0] += (double)r1[kk] * (double)r1[kk];
+            acc[1] += (double)w1[kk] * (double)r1[kk];
+        }
+    }
+}
+
+// The last iteration on one tile: only x_out = x_in + d_k + alpha p_k.
+__device__ inline void cg_last_tile(int H, int W, int r0, int c0, int k, float alpha, float beta,
+                                    const float* __restrict__ r_in, const float* __restrict__ p,
+                                    const float* __restrict__ d, const float* __restrict__ x_in,
+                                    float* __restrict__ x_out) {
+#pragma unroll
+    for (int kk = 0; kk < NO; ++kk) {
+        const int o = threadIdx.x + kk * kThreads;
+        const int gr = r0 + o / TW, gc = c0 + o % TW;
+        if (gr < H && gc < W) {
+            const size_t g = (size_t)gr * W + gc;
+            const float pk = k ? r_in[g] + beta * p[g] : r_in[g];
+            const float dn = k ? d[g] + alpha * pk : alpha * pk;
+            x_out[g] = x_in[g] + dn;
+        }
+    }
 }
 
 // One conjugate-gradient iteration in the single-reduction (Chronopoulos-Gear) form: with
@@ -388,63 +480,121 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
     __shared__ double bc;
     const double rho = consume(rm.p, rm.n, &bc);
     const double mu = consume(rm.p + kMaxRedBlocks, rm.n, &bc);
-    double alpha_d = 0.0, beta_d = 0.0;
-    if (rho > 1e-300) {
-        if (k == 0) {
-            alpha_d = mu > 0.0 ? rho / mu : 0.0;
-        } else {
-            const double alpha_prev = hist_prev[0], rho_prev = hist_prev[1];
-            beta_d = rho_prev > 1e-300 ? rho / rho_prev : 0.0;
-            const double den = alpha_prev != 0.0 ? mu - beta_d * rho / alpha_prev : 0.0;
-            alpha_d = den > 0.0 ? rho / den : 0.0;
-        }
-    }
+    double alpha_d, beta_d;
+    cg_scalars(k, rho, mu, k ? hist_prev[0] : 0.0, k ? hist_prev[1] : 0.0, alpha_d, beta_d);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hist_cur[0] = alpha_d;
         hist_cur[1] = rho;
     }
     const float alpha = (float)alpha_d, beta = (float)beta_d;
-    const int n = H * W;
     double acc[2] = {0.0, 0.0};
-    if (last) {
-        for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
-            const float pk = k ? r_in[i] + beta * p[i] : r_in[i];
-            const float dn = k ? d[i] + alpha * pk : alpha * pk;
-            x_out[i] = x_in[i] + dn;
-        }
-        return;
-    }
     for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
         int r0, c0;
         tile_origin(t, W, r0, c0);
-        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) {
-            const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
-            return r_in[g] - alpha * sk;
-        });
-        float r1[NO], w1[NO];
-        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, r1, w1);
-#pragma unroll
-        for (int kk = 0; kk < NO; ++kk) {
-            const int o = threadIdx.x + kk * kThreads;
-            const int gr = r0 + o / TW, gc = c0 + o % TW;
-            if (gr < H && gc < W) {
-                const size_t g = (size_t)gr * W + gc;
-                const float rk = r_in[g];
-                const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
-                const float pk = k ? rk + beta * p[g] : rk;
-                const float dn = k ? d[g] + alpha * pk : alpha * pk;
-                s_out[g] = sk;
-                p[g] = pk;
-                d[g] = dn;
-                r_out[g] = r1[kk];
-                w_out[g] = w1[kk];
-                acc[0] += (double)r1[kk] * (double)r1[kk];
-                acc[1] += (double)w1[kk] * (double)r1[kk];
-            }
-        }
+        if (last)
+            cg_last_tile(H, W, r0, c0, k, alpha, beta, r_in, p, d, x_in, x_out);
+        else
+            cg_iter_tile<RS>(op, H, W, r0, c0, k, alpha, beta, r_in, w_in, s_in, r_out, w_out,
+                             s_out, p, d, sm, acc);
     }
+    if (last) return;
     block_sum<2>(acc, sred);
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
+// ---- batched kernels: one workgroup per tile of the batch tile list ----------------------
+
+// The image of this workgroup's tile and the tile's origin; null for an inactive image.
+__device__ inline const ImgDesc* batch_tile(const ImgDesc* desc, const int* tile_img, int& r0,
+                                            int& c0) {
+    const ImgDesc* d = desc + tile_img[blockIdx.x];
+    if (!d->active) return nullptr;
+    const int t = blockIdx.x - d->tile0, ntx = (d->W + TW - 1) / TW;
+    r0 = (t / ntx) * TH;
+    c0 = (t % ntx) * TW;
+    return d;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __restrict__ desc,
+                                                               const int* __restrict__ tile_img,
+                                                               const float* __restrict__ sres,
+                                                               float* __restrict__ r) {
+    __shared__ InitFpSmem sm;
+    int r0, c0;
+    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    if (!d) return;
+    init_fp_tile(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr, r + d->off, d->H, d->W, r0,
+                 c0, sm);
+}
+
+template <int RS>
+__global__ __launch_bounds__(kThreads) void k_cg_w0_batch(const ImgDesc* __restrict__ desc,
+                                                          const int* __restrict__ tile_img,
+                                                          const float* __restrict__ r,
+                                                          float* __restrict__ w,
+                                                          double* __restrict__ part, int cap) {
+    __shared__ TileSmem sm;
+    __shared__ double sred[2 * kThreads / 64];
+    int r0, c0;
+    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    if (!d) return;
+    double acc[2] = {0.0, 0.0};
+    w0_tile<RS>(d->op, r + d->off, w + d->off, d->H, d->W, r0, c0, sm, acc);
+    block_sum<2>(acc, sred);
+    publish<2>(acc, part, cap, blockIdx.x);
+}
+
+// Per-image CG scalars: sums the image's tile partials in tile order (deterministic and
+// independent of the other images of the batch), then alpha_k, beta_k.
+__global__ __launch_bounds__(64) void k_cg_fin_batch(const ImgDesc* __restrict__ desc, int k,
+                                                     const double* __restrict__ part, int cap,
+                                                     CgImg* __restrict__ cg) {
+    const ImgDesc& d = desc[blockIdx.x];
+    if (!d.active) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < d.ntiles; i += 64) {
+        s0 += part[d.tile0 + i];
+        s1 += part[(size_t)cap + d.tile0 + i];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (threadIdx.x == 0) {
+        CgImg c = cg[blockIdx.x];
+        double alpha, beta;
+        cg_scalars(k, s0, s1, c.alpha_prev, c.rho_prev, alpha, beta);
+        c.alpha = alpha;
+        c.beta = beta;
+        c.alpha_prev = alpha;
+        c.rho_prev = s0;
+        cg[blockIdx.x] = c;
+    }
+}
+
+template <int RS>
+__global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
+    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img, int k, int last,
+    const CgImg* __restrict__ cg, const float* __restrict__ r_in, const float* __restrict__ w_in,
+    const float* __restrict__ s_in, float* __restrict__ r_out, float* __restrict__ w_out,
+    float* __restrict__ s_out, float* __restrict__ p, float* __restrict__ dd,
+    double* __restrict__ part, int cap) {
+    __shared__ TileSmem sm;
+    __shared__ double sred[2 * kThreads / 64];
+    int r0, c0;
+    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    if (!d) return;
+    const CgImg c = cg[d - desc];
+    const float alpha = (float)c.alpha, beta = (float)c.beta;
+    const size_t o = d->off;
+    if (last) {
+        cg_last_tile(d->H, d->W, r0, c0, k, alpha, beta, r_in + o, p + o, dd + o, d->x_in,
+                     d->x_out);
+        return;
+    }
+    double acc[2] = {0.0, 0.0};
+    cg_iter_tile<RS>(d->op, d->H, d->W, r0, c0, k, alpha, beta, r_in + o, w_in + o, s_in + o,
+                     r_out + o, w_out + o, s_out + o, p + o, dd + o, sm, acc);
+    block_sum<2>(acc, sred);
+    publish<2>(acc, part, cap, blockIdx.x);
 }
 
 inline int tile_blocks(int H, int W) {
@@ -530,6 +680,41 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
         k_cg_iter<0><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
                                              s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
     return Partials{part, g};
+}
+
+void launch_cg_init_fp_batch(const ImgDesc* desc, const int* tile_img, int ntiles,
+                             const float* sres, float* r, hipStream_t st) {
+    k_cg_init_fp_batch<<<ntiles, kThreads, 0, st>>>(desc, tile_img, sres, r);
+}
+
+void launch_cg_w0_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs,
+                        const float* r, float* w, double* part, int cap, hipStream_t st) {
+    if (rs == 4)
+        k_cg_w0_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+    else if (rs == 3)
+        k_cg_w0_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+    else
+        k_cg_w0_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+}
+
+void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
+                         CgImg* cg, hipStream_t st) {
+    k_cg_fin_batch<<<nimg, 64, 0, st>>>(desc, k, part, cap, cg);
+}
+
+void launch_cg_iter_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs, int k,
+                          int last, const CgImg* cg, const float* r_in, const float* w_in,
+                          const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
+                          float* d, double* part, int cap, hipStream_t st) {
+    if (rs == 4)
+        k_cg_iter_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+                                                        s_in, r_out, w_out, s_out, p, d, part, cap);
+    else if (rs == 3)
+        k_cg_iter_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+                                                        s_in, r_out, w_out, s_out, p, d, part, cap);
+    else
+        k_cg_iter_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+                                                        s_in, r_out, w_out, s_out, p, d, part, cap);
 }
 
 }  // namespace redve

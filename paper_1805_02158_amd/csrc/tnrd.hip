@@ -88,18 +88,18 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// The stage on the 16x16 output tile at (r0, c0) of one image.
 template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
-    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
-    int W, const float* __restrict__ filt /* F*25 */, const float* __restrict__ rbfw /* F*J */,
-    int F, RbfConst rc, float theta, int out_mode) {
+__device__ inline void stage_tile(const float* __restrict__ w, const float* __restrict__ f,
+                                  float* __restrict__ out, int H, int W, int r0, int c0,
+                                  const float* __restrict__ filt, const float* __restrict__ rbfw,
+                                  int F, const RbfConst& rc, float theta, int out_mode) {
     extern __shared__ float smem[];
     float* su = smem;                  // UH * UW
     float* sg = su + UH * UW;          // NWAVE * TH * TW (partial g)
     float* sv = sg + NWAVE * TH * TW;  // NWAVE * VH * VW
     float* sw = sv + NWAVE * VH * VW;  // F * (J + 2 WPAD)
     const int wstride = rc.J + 2 * WPAD;
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
@@ -223,6 +223,31 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
     }
 }
 
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
+    float theta, int out_mode) {
+    stage_tile<KC>(w, f, out, H, W, blockIdx.y * TH, blockIdx.x * TW, filt, rbfw, F, rc, theta,
+                   out_mode);
+}
+
+// Batched: one workgroup per tile of the batch's tile list. Vector v of image i lives at
+// base_v + desc[i].off; w_base null means w = 0 (first stage).
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_batch(
+    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img,
+    const float* __restrict__ w_base, float* __restrict__ out_base,
+    const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
+    float theta, int out_mode) {
+    const int img = tile_img[blockIdx.x];
+    const ImgDesc& d = desc[img];
+    if (!d.active) return;
+    const int t = blockIdx.x - d.tile0, ntx = (d.W + TW - 1) / TW;
+    stage_tile<KC>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H, d.W,
+                   (t / ntx) * TH, (t % ntx) * TW, filt, rbfw, F, rc, theta, out_mode);
+}
+
 }  // namespace
 
 int tnrd_grid(int H, int W) { return ((W + TW - 1) / TW) * ((H + TH - 1) / TH); }
@@ -232,9 +257,7 @@ size_t tnrd_smem_bytes(int F, int J) {
                             (size_t)F * (J + 2 * WPAD));
 }
 
-void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
-                       int H, int W, int out_mode, hipStream_t st) {
-    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+static RbfConst rbf_const(const TnrdDev& d) {
     RbfConst rc;
     rc.mu0 = d.mu0;
     rc.dmu = d.dmu;
@@ -247,6 +270,13 @@ void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float
     rc.J = d.nrbf;
     rc.K = d.kwin;
     rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
+    return rc;
+}
+
+void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+                       int H, int W, int out_mode, hipStream_t st) {
+    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+    const RbfConst rc = rbf_const(d);
     const size_t smem = tnrd_smem_bytes(d.nfilt, d.nrbf);
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
@@ -256,6 +286,21 @@ void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float
     else
         k_tnrd_stage_f32<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
                                                       d.theta[t], out_mode);
+}
+
+void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const int* tile_img,
+                             int ntiles, const float* w_prev, float* out, int out_mode,
+                             hipStream_t st) {
+    const RbfConst rc = rbf_const(d);
+    const size_t smem = tnrd_smem_bytes(d.nfilt, d.nrbf);
+    const float* kf = d.filters + (size_t)t * d.nfilt * 25;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    if (rc.K == 7)
+        k_tnrd_stage_f32_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, kf,
+                                                               wf, d.nfilt, rc, d.theta[t], out_mode);
+    else
+        k_tnrd_stage_f32_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, kf,
+                                                               wf, d.nfilt, rc, d.theta[t], out_mode);
 }
 
 }  // namespace redve

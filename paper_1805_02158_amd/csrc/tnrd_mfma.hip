@@ -76,10 +76,12 @@ __device__ inline bf16x8 load_frag(const uint16_t* p) {
 }
 
 template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
-    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
-    int W, const uint16_t* __restrict__ bfwd /* 2 x 64 x 8 */, const uint16_t* __restrict__ badj,
-    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+__device__ inline void stage_tile_bf16(const float* __restrict__ w, const float* __restrict__ f,
+                                       float* __restrict__ out, int H, int W, int r0, int c0,
+                                       const uint16_t* __restrict__ bfwd,
+                                       const uint16_t* __restrict__ badj,
+                                       const float* __restrict__ rbfw, int F, const RbfC& rc,
+                                       float theta, int out_mode) {
     extern __shared__ float smem[];
     // One row per position holds z, then v = phi(z), then the 25 per-tap adjoint sums (a wave
     // overwrites the rows of its own MFMA group after loading them as an operand).
@@ -89,7 +91,6 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
     float* ss = sz;
     float* sw = sz + NPOS * ZS;       // F * (J + 2 WPAD)
     const int wstride = rc.J + 2 * WPAD;
-    const int r0 = blockIdx.y * TH, c0 = blockIdx.x * TW;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
@@ -207,6 +208,30 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
     }
 }
 
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+    stage_tile_bf16<KC>(w, f, out, H, W, blockIdx.y * TH, blockIdx.x * TW, bfwd, badj, rbfw, F,
+                        rc, theta, out_mode);
+}
+
+template <int KC>
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16_batch(
+    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img,
+    const float* __restrict__ w_base, float* __restrict__ out_base,
+    const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+    const int img = tile_img[blockIdx.x];
+    const ImgDesc& d = desc[img];
+    if (!d.active) return;
+    const int t = blockIdx.x - d.tile0, ntx = (d.W + TW - 1) / TW;
+    stage_tile_bf16<KC>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H,
+                        d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta,
+                        out_mode);
+}
+
 }  // namespace
 
 size_t tnrd_bf16_smem_bytes(int F, int J) {
@@ -214,9 +239,7 @@ size_t tnrd_bf16_smem_bytes(int F, int J) {
     return sizeof(float) * ((size_t)UH * UW + (size_t)NPOS * zs + (size_t)F * (J + 2 * WPAD));
 }
 
-void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
-                            float* out, int H, int W, int out_mode, hipStream_t st) {
-    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+static RbfC rbf_c(const TnrdDev& d) {
     RbfC rc;
     rc.mu0 = d.mu0;
     rc.dmu = d.dmu;
@@ -229,6 +252,13 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
     rc.J = d.nrbf;
     rc.K = d.kwin;
     rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
+    return rc;
+}
+
+void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
+                            float* out, int H, int W, int out_mode, hipStream_t st) {
+    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+    const RbfC rc = rbf_c(d);
     const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
     const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
@@ -239,6 +269,24 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
     else
         k_tnrd_stage_bf16<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
                                                        rc, d.theta[t], out_mode);
+}
+
+void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
+                                  const int* tile_img, int ntiles, const float* w_prev, float* out,
+                                  int out_mode, hipStream_t st) {
+    const RbfC rc = rbf_c(d);
+    const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
+    const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
+    const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    if (rc.K == 7)
+        k_tnrd_stage_bf16_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, bf,
+                                                                ba, wf, d.nfilt, rc, d.theta[t],
+                                                                out_mode);
+    else
+        k_tnrd_stage_bf16_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, bf,
+                                                                ba, wf, d.nfilt, rc, d.theta[t],
+                                                                out_mode);
 }
 
 }  // namespace redve

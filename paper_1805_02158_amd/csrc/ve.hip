@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kThreads) void k_diff_gram(const float* __restrict_
 
 // ---- small dense FP64 algebra, one thread ----------------------------------------------
 
-constexpr int MAXL = 32;
+constexpr int MAXL = 16;  // REDVE_MAX_L
 
 __device__ void back_sub(const double (*R)[MAXL], int k, const double* b, double* x) {
     for (int i = k - 1; i >= 0; --i) {
@@ -168,36 +168,10 @@ __device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma) {
     return true;
 }
 
-// Sums the window's published partials into the Gram matrix (fixed order, FP64), then the
-// L x L work on one thread.
-__global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part, size_t win_stride,
-                                                 int nblk, int L, int method, double rank_eps,
-                                                 VeInfo* __restrict__ info) {
-    __shared__ double G[MAXL * MAXL];
-    __shared__ double norms[2];
-    // column j's pass published values k < j (u_j . u_k), j (u_j . u_j), j + 1 (x . x)
-    for (int j = 0; j < L; ++j) {
-        const double* pj = part + (size_t)j * win_stride;
-        for (int k = 0; k <= j + 1; ++k) {
-            double s = 0.0;
-            for (int i = threadIdx.x; i < nblk; i += 64) s += pj[(size_t)k * kMaxRedBlocks + i];
-            s = wave_sum(s);
-            if (threadIdx.x == 0) {
-                if (k <= j) {
-                    G[j * MAXL + k] = s;
-                    G[k * MAXL + j] = s;
-                } else if (j == L - 1) {
-                    norms[1] = s;
-                }
-                if (k == j && j == L - 1) norms[0] = s;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    info->uu = norms[0];
-    info->xx = norms[1];
-    const int ldG = MAXL;
+// The L x L work of Algorithm 1 on one thread: Cholesky of the Gram matrix (= the R of
+// Algorithm 2), MPE / RRE / SVD-MPE coefficients, xi; writes gamma, xi, ncols, breakdown.
+__device__ void small_solve(const double* G, int ldG, int L, int method, double rank_eps,
+                            VeInfo* __restrict__ info) {
     // Cholesky G = R^T R (upper R). A column whose pivot falls under the rank threshold gets
     // R_ii = 0 and a zero row, as modified Gram-Schmidt gives a zero q_i for it.
     double R[MAXL][MAXL];
@@ -255,6 +229,38 @@ __global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part
     info->gamma_l1 = l1;
 }
 
+// Sums the window's published partials into the Gram matrix (fixed order, FP64), then the
+// L x L work on one thread.
+__global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part, size_t win_stride,
+                                                 int nblk, int L, int method, double rank_eps,
+                                                 VeInfo* __restrict__ info) {
+    __shared__ double G[MAXL * MAXL];
+    __shared__ double norms[2];
+    // column j's pass published values k < j (u_j . u_k), j (u_j . u_j), j + 1 (x . x)
+    for (int j = 0; j < L; ++j) {
+        const double* pj = part + (size_t)j * win_stride;
+        for (int k = 0; k <= j + 1; ++k) {
+            double s = 0.0;
+            for (int i = threadIdx.x; i < nblk; i += 64) s += pj[(size_t)k * kMaxRedBlocks + i];
+            s = wave_sum(s);
+            if (threadIdx.x == 0) {
+                if (k <= j) {
+                    G[j * MAXL + k] = s;
+                    G[k * MAXL + j] = s;
+                } else if (j == L - 1) {
+                    norms[1] = s;
+                }
+                if (k == j && j == L - 1) norms[0] = s;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    info->uu = norms[0];
+    info->xx = norms[1];
+    small_solve(G, MAXL, L, method, rank_eps, info);
+}
+
 // Algorithm 1, step 4: x_(m,kappa) = x_m + U_{kappa-1} xi (= x_m + Q_{kappa-1} eta).
 __global__ __launch_bounds__(kThreads) void k_ve_combine(const float* __restrict__ x_m,
                                                          const float* __restrict__ U, int n,
@@ -282,6 +288,106 @@ __global__ __launch_bounds__(64) void k_delta(const double* __restrict__ part, i
         info->uu = s0;
         info->xx = s1;
     }
+}
+
+// ---- batched kernels ----------------------------------------------------------------------
+
+// One tile of one image: u = x_out - x_in (stored as window column wj when wj >= 0), its inner
+// products with window columns 0..wj, ||u||^2, ||x_in||^2; NL + 2 per-tile partials.
+template <int NL>
+__global__ __launch_bounds__(kThreads) void k_diff_gram_batch(const ImgDesc* __restrict__ desc,
+                                                              const int* __restrict__ tile_img,
+                                                              float* __restrict__ U,
+                                                              size_t ustride,
+                                                              double* __restrict__ part, int cap) {
+    constexpr int NV = NL + 2;
+    __shared__ double sred[NV * kThreads / 64];
+    const ImgDesc& d = desc[tile_img[blockIdx.x]];
+    if (!d.active) return;
+    const int t = blockIdx.x - d.tile0, ntx = (d.W + kBatchTile - 1) / kBatchTile;
+    const int gr = (t / ntx) * kBatchTile + threadIdx.x / kBatchTile;
+    const int gc = (t % ntx) * kBatchTile + threadIdx.x % kBatchTile;
+    const int j = d.wj;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    if (gr < d.H && gc < d.W) {
+        const size_t g = (size_t)gr * d.W + gc;
+        const float xo = d.x_in[g];
+        const float uv = d.x_out[g] - xo;
+        float* Ui = U + d.off + g;
+        if (j >= 0) Ui[(size_t)j * ustride] = uv;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            if (k < j) acc[k] = (double)uv * (double)Ui[(size_t)k * ustride];
+            else if (k == j) acc[k] = (double)uv * (double)uv;
+        }
+        acc[NL] = (double)uv * (double)uv;
+        acc[NL + 1] = (double)xo * (double)xo;
+    }
+    block_sum<NV>(acc, sred);
+    publish<NV>(acc, part, cap, blockIdx.x);
+}
+
+// Per image: sums the tile partials in tile order into Gram row wj and the norms.
+__global__ __launch_bounds__(64) void k_diff_fin_batch(const ImgDesc* __restrict__ desc, int L,
+                                                       const double* __restrict__ part, int cap,
+                                                       double* __restrict__ G,
+                                                       ImgStat* __restrict__ stat) {
+    const ImgDesc& d = desc[blockIdx.x];
+    if (!d.active) return;
+    double* Gi = G + (size_t)blockIdx.x * MAXL * MAXL;
+    for (int v = 0; v < L + 2; ++v) {
+        const bool gram = v < L && v <= d.wj;
+        if (v < L && !gram) continue;
+        double sum = 0.0;
+        for (int i = threadIdx.x; i < d.ntiles; i += 64) sum += part[(size_t)v * cap + d.tile0 + i];
+        sum = wave_sum(sum);
+        if (threadIdx.x == 0) {
+            if (gram) {
+                Gi[d.wj * MAXL + v] = sum;
+                Gi[v * MAXL + d.wj] = sum;
+            } else if (v == L) {
+                stat[blockIdx.x].uu = sum;
+            } else {
+                stat[blockIdx.x].xx = sum;
+            }
+        }
+    }
+}
+
+// Per image that completes its window this round: the L x L solve.
+__global__ __launch_bounds__(64) void k_ve_solve_batch(const ImgDesc* __restrict__ desc, int L,
+                                                       int method, double rank_eps,
+                                                       const double* __restrict__ G,
+                                                       VeInfo* __restrict__ info,
+                                                       ImgStat* __restrict__ stat) {
+    const ImgDesc& d = desc[blockIdx.x];
+    if (!d.active || !d.do_ve || threadIdx.x != 0) return;
+    VeInfo* in = info + blockIdx.x;
+    small_solve(G + (size_t)blockIdx.x * MAXL * MAXL, MAXL, L, method, rank_eps, in);
+    stat[blockIdx.x].gamma_l1 = in->gamma_l1;
+    stat[blockIdx.x].breakdown = in->breakdown;
+}
+
+// x_m = x_m + U_{kappa-1} xi on one tile of an image that extrapolates this round.
+__global__ __launch_bounds__(kThreads) void k_ve_combine_batch(const ImgDesc* __restrict__ desc,
+                                                               const int* __restrict__ tile_img,
+                                                               const float* __restrict__ U,
+                                                               size_t ustride,
+                                                               const VeInfo* __restrict__ info) {
+    const int img = tile_img[blockIdx.x];
+    const ImgDesc& d = desc[img];
+    if (!d.active || !d.do_ve) return;
+    const int t = blockIdx.x - d.tile0, ntx = (d.W + kBatchTile - 1) / kBatchTile;
+    const int gr = (t / ntx) * kBatchTile + threadIdx.x / kBatchTile;
+    const int gc = (t % ntx) * kBatchTile + threadIdx.x % kBatchTile;
+    if (gr >= d.H || gc >= d.W) return;
+    const size_t g = (size_t)gr * d.W + gc;
+    const VeInfo& in = info[img];
+    double acc = (double)d.x_m[g];
+    for (int j = 0; j < in.ncols; ++j) acc += in.xi[j] * (double)U[(size_t)j * ustride + d.off + g];
+    d.x_m[g] = (float)acc;
 }
 
 }  // namespace
@@ -316,6 +422,36 @@ void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,
                        hipStream_t st) {
     k_ve_combine<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(x_m, U, n, info, out);
+}
+
+void launch_diff_gram_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int L, float* U,
+                            size_t ustride, double* part, int cap, hipStream_t st) {
+#define REDVE_DGB(N)                                                                       \
+    case N:                                                                                \
+        k_diff_gram_batch<N><<<ntiles, kThreads, 0, st>>>(desc, tile_img, U, ustride, part, cap); \
+        break;
+    switch (L) {
+        REDVE_DGB(1) REDVE_DGB(2) REDVE_DGB(3) REDVE_DGB(4) REDVE_DGB(5) REDVE_DGB(6) REDVE_DGB(7)
+        REDVE_DGB(8) REDVE_DGB(9) REDVE_DGB(10) REDVE_DGB(11) REDVE_DGB(12) REDVE_DGB(13)
+        REDVE_DGB(14) REDVE_DGB(15) REDVE_DGB(16)
+        default: break;
+    }
+#undef REDVE_DGB
+}
+
+void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* part, int cap,
+                           double* G, ImgStat* stat, hipStream_t st) {
+    k_diff_fin_batch<<<nimg, 64, 0, st>>>(desc, L, part, cap, G, stat);
+}
+
+void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
+                           const double* G, VeInfo* info, ImgStat* stat, hipStream_t st) {
+    k_ve_solve_batch<<<nimg, 64, 0, st>>>(desc, L, method, rank_eps, G, info, stat);
+}
+
+void launch_ve_combine_batch(const ImgDesc* desc, const int* tile_img, int ntiles, const float* U,
+                             size_t ustride, const VeInfo* info, hipStream_t st) {
+    k_ve_combine_batch<<<ntiles, kThreads, 0, st>>>(desc, tile_img, U, ustride, info);
 }
 
 }  // namespace redve
