@@ -1,11 +1,12 @@
 #!/usr/bin/env python3
-"""Benchmark: restored MPix/s to the oracle-converged PSNR, VE (RRE) vs plain FP, on one MI355X.
+"""Benchmark: restored MPix/s to the oracle-converged PSNR, VE vs plain FP, on one MI355X; batched
+throughput; serving throughput with p50/p99 latency.
 
-Workload (the 256x256 deblurring configuration): a seeded 256x256 piecewise-smooth image,
-uniform 9x9 blur, noise sigma sqrt(2), lambda 0.02, 15 CG iterations per FP call, seeded
+Headline workload (the 256x256 deblurring configuration): a seeded 256x256 piecewise-smooth
+image, uniform 9x9 blur, noise sigma sqrt(2), lambda 0.02, 15 CG iterations per FP call, seeded
 TNRD-style denoiser (5 stages x 24 filters 5x5, 63-RBF influence functions), RRE with L = 5.
 
-Protocol
+Protocol (headline)
   1. target PSNR* = PSNR of the FP64 oracle's plain FP run to a relative change < 1e-6
      (tests/golden/bench_target_c1.json, written by a script that calls only the oracle);
   2. instrumented, untimed: solves with max_fp_calls = n = 1, 2, ... find n*, the FP-call
@@ -13,8 +14,17 @@ Protocol
   3. timed: `steps` solves with max_fp_calls = n* (after `warmup` untimed ones). A step is one
      whole solve y -> x through the C ABI, inputs resident in HBM. value = pixels * steps /
      time; p50/p99 are per-solve latencies.
-The same protocol runs plain FP for comparison. The roofline object covers the dominant
-kernel (the fused denoiser stage), timed with HIP events on the library's stream.
+Forms: plain FP (FP32), VE (RRE) with FP32 filter banks, VE (RRE) with BF16 filter banks on
+MFMA. `value` is the VE + BF16 form. The roofline object covers the dominant kernel (the fused
+denoiser stage of that form), timed with HIP events on the library's stream; the same kernel
+on a 2048 x 2048 image (16384 tiles, every CU busy) is reported beside it.
+
+Batched (64 images, sides log-uniform 128..1024, uniform 9x9 or Gaussian 7x7 blur, sigma sqrt(2)
+or 5): one redve_solve_batch to a relative change < 1e-5 per image; each image's PSNR is
+checked against its own plain-FP fixed point (GPU FP32, relative change < 1e-6).
+Serving (Poisson arrivals, sides log-uniform 128..2048, deblurring 9x9 or 3x super-resolution):
+saturation throughput with every request queued at once, then a Poisson trace at 0.7 x that
+request rate; latency = completion - submission.
 """
 import argparse
 import json
@@ -36,9 +46,19 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nmax", type=int, default=40, help="longest instrumented solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-calls", type=int, default=5,
-                    help="FP calls of the oracle timed for the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="least host time the oracle baseline is sampled for")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-images", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-max-active", type=int, default=64)
     return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def main():
@@ -70,22 +90,27 @@ def main():
     y = R.apply_H(x_true) + float(prob.sigma) * noise  # observation, eq. (1)
     torch.cuda.synchronize()
 
-    def psnr(x):
-        mse = torch.mean((x.double() - x_true.double()) ** 2).item()
+    def psnr(x, ref=x_true):
+        mse = torch.mean((x.double() - ref.double()) ** 2).item()
         return 10.0 * math.log10(255.0 ** 2 / mse)
 
     out = torch.empty((H, Wd), dtype=torch.float32, device=dev)
 
-    def solve(method, calls):
+    state = {"prec": "fp32"}  # configure() above loaded the FP32 banks
+
+    def solve(method, prec, calls):
+        if state["prec"] != prec:
+            R.set_denoiser(prob.denoiser, prec)
+            state["prec"] = prec
         R.set_extrapolation(method, prob.L, 0)
         R.set_solver(prob.cg_iters, calls, 0.0, 0)
         _, st = R.solve(y, H, Wd, out=out)
         return st
 
-    def n_star(method):
+    def n_star(method, prec):
         trace = []
         for n in range(1, args.nmax + 1):
-            solve(method, n)
+            solve(method, prec, n)
             trace.append((n, psnr(out)))
         ns = None
         for n, p in trace:
@@ -95,47 +120,47 @@ def main():
                 ns = None
         return ns, trace
 
-    def timed(method, calls):
+    def timed(method, prec, calls):
         for _ in range(args.warmup):
-            solve(method, calls)
+            solve(method, prec, calls)
         torch.cuda.synchronize()
         lat = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
-            st = solve(method, calls)
+            st = solve(method, prec, calls)
             lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
         lat = np.array(lat) * 1e3
         return {"mpix_s": npx * args.steps / total / 1e6, "ms_per_step": total / args.steps * 1e3,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "fp_calls": st["fp_calls"], "cycles": st["cycles"], "psnr_db": psnr(out)}
+                "fp_calls_to_target": calls, "cycles": st["cycles"], "psnr_db": psnr(out)}
 
-    ns_ve, tr_ve = n_star("rre")
-    ns_fp, tr_fp = n_star("none")
-    if ns_ve is None or ns_fp is None:
-        print(json.dumps({"error": "target PSNR not reached", "trace_ve": tr_ve,
-                          "trace_fp": tr_fp}))
-        sys.exit(1)
-    ve = timed("rre", ns_ve)
-    fp = timed("none", ns_fp)
+    forms = {"plain_fp32": ("none", "fp32"), "ve_fp32": ("rre", "fp32"), "ve_bf16": ("rre", "bf16")}
+    res_forms = {}
+    for name, (method, prec) in forms.items():
+        ns, tr = n_star(method, prec)
+        if ns is None:
+            print(json.dumps({"error": f"target PSNR not reached by {name}", "trace": tr}))
+            sys.exit(1)
+        res_forms[name] = timed(method, prec, ns)
+        log(name, res_forms[name])
+    ve = res_forms["ve_bf16"]
+    fp = res_forms["plain_fp32"]
 
-    # ---- roofline of the dominant kernel: the fused denoiser stage (timed with HIP events on
-    # the library's stream, which is torch's current stream)
-    reps = 20
-    xin = y.clone()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    dout = R.denoise(xin)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        dout = R.denoise(xin)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    stage_us = e0.elapsed_time(e1) * 1e3 / (reps * prob.denoiser.stages)
-    roof = roofline_stage(npx, stage_us)
+    # ---- roofline of the dominant kernel: the fused denoiser stage of the headline form,
+    # timed with HIP events on the library's stream (torch's current stream)
+    R.set_denoiser(prob.denoiser, "bf16")
+    stage_us = time_stage(torch, R, y, prob.denoiser.stages)
+    roof = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16")
+    big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device=dev)
+    stage_big_us = time_stage(torch, R, big, prob.denoiser.stages)
+    roof_big = roofline_stage(big.numel(), stage_big_us, "k_tnrd_stage_bf16")
+    R.set_denoiser(prob.denoiser, "fp32")
+    stage32_big_us = time_stage(torch, R, big, prob.denoiser.stages)
+    roof32_big = roofline_stage(big.numel(), stage32_big_us, "k_tnrd_stage_f32")
+    del big
 
     res = {
         "metric": "restored MPix/s to oracle-converged PSNR (VE vs plain FP); p50/p99 solve latency",
@@ -148,24 +173,45 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic (seeded piecewise-smooth image, seeded TNRD-style denoiser)",
         "config": {"workload": "deblur 256x256, uniform 9x9 blur, sigma sqrt(2), lambda 0.02, "
                                "15 CG/FP call, TNRD-style D 5x24x(5x5), RRE L=5 m=0",
-                   "method": "FP + RRE (L=5)", "fp_calls_to_target": ns_ve,
+                   "method": "FP + RRE (L=5)",
+                   "precision": "BF16 filter-bank operands on MFMA with FP32 accumulation; "
+                                "RBF influence, update and CG in FP32; VE Gram/solve in FP64",
+                   "fp_calls_to_target": ve["fp_calls_to_target"],
                    "psnr_target_db": psnr_star, "band_db": BAND_DB},
         "p50_ms": ve["p50_ms"],
         "p99_ms": ve["p99_ms"],
         "psnr_db": ve["psnr_db"],
-        "plain_fp": {"mpix_s": fp["mpix_s"], "ms_per_step": fp["ms_per_step"],
-                     "fp_calls_to_target": ns_fp, "p50_ms": fp["p50_ms"], "p99_ms": fp["p99_ms"],
-                     "psnr_db": fp["psnr_db"]},
-        "ve_speedup_vs_plain_fp": fp["ms_per_step"] / ve["ms_per_step"],
+        "forms": res_forms,
+        "ve_bf16_speedup_vs_plain_fp32": fp["ms_per_step"] / ve["ms_per_step"],
         "roofline": roof,
+        "roofline_stage_2048x2048": {"bf16": roof_big, "fp32": roof32_big},
     }
+    if not args.no_batch:
+        res["batched"] = bench_batch(args, torch, np, W, Restorer, psnr)
+    if not args.no_serve:
+        res["serving"] = bench_serve(args, torch, np, W, Restorer)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(prob, ns_ve, args.cpu_sample_calls)
+        res["cpu_baseline"] = cpu_baseline(prob, ve["fp_calls_to_target"], args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def time_stage(torch, R, x, stages, reps=20):
+    """Average duration of one denoiser stage launch: HIP events around `reps` denoiser calls
+    (each `stages` launches back to back) on the library's stream."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    R.denoise(x)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        R.denoise(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / (reps * stages)
 
 
 # Algorithmic work of one denoiser stage per output pixel, as the method defines it:
@@ -177,32 +223,148 @@ STAGE_FLOP_PER_PX = 2 * 24 * 25 * 2 + 24 * 63 * 6
 FP32_PEAK_TFLOPS = 157.3
 
 
-def roofline_stage(npx, stage_us):
-    """The fused denoiser stage is bound by plain ALU arithmetic (its data stays in LDS and
-    registers; HBM traffic is 12 B per pixel). achieved = algorithmic FLOP per launch / time."""
+def roofline_stage(npx, stage_us, kernel):
+    """The fused denoiser stage is bound by plain ALU arithmetic: its data stays in LDS and
+    registers (HBM traffic about 12 B per pixel) and 79% of its defined work is the RBF sum,
+    which runs on the vector ALUs in either precision. achieved = algorithmic FLOP per launch
+    / average launch time, against the FP32 vector peak."""
     work = npx * STAGE_FLOP_PER_PX
     achieved = work / (stage_us * 1e-6) / 1e12
-    return {"kernel": "k_tnrd_stage_f32", "bound": "alu", "achieved": achieved,
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
             "traffic": None, "avg_launch_us": stage_us, "flop_per_launch": work,
-            "flop_per_px": STAGE_FLOP_PER_PX}
+            "flop_per_px": STAGE_FLOP_PER_PX, "pixels_per_launch": npx}
 
 
-def cpu_baseline(prob, calls, sample_calls):
-    """The FP64 oracle (plain C, OpenMP over rows/filters) on the host: the same solve
-    (RRE, L = 5) for a bounded number of FP calls, scaled to the GPU's FP-call count."""
+def observe(torch, R, probs):
+    """y = H x_true + sigma n on the GPU (each problem's own operator)."""
+    ys = []
+    for p in probs:
+        R.set_operator(p.psf, p.decim)
+        xt = torch.tensor(p.x_true, dtype=torch.float32, device="cuda")
+        n = torch.tensor(p.noise, dtype=torch.float32, device="cuda")
+        ys.append(R.apply_H(xt) + float(p.sigma) * n)
+    torch.cuda.synchronize()
+    return ys
+
+
+def bench_batch(args, torch, np, W, Restorer, psnr):
+    probs = W.batch_items(args.batch_images)
+    R = Restorer(0)
+    ys = observe(torch, R, probs)
+    xts = [torch.tensor(p.x_true, dtype=torch.float32, device="cuda") for p in probs]
+    items = [dict(y=y, hx=p.hr_shape[0], wx=p.hr_shape[1], psf=p.psf, decim=p.decim,
+                  sigma=p.sigma, lam=p.lam) for p, y in zip(probs, ys)]
+    mpix = sum(p.x_true.size for p in probs) / 1e6
+    d = W.make_denoiser()
+
+    def run(method, prec, tol, max_calls):
+        R.set_denoiser(d, prec).set_extrapolation(method, 5, 0).set_solver(15, max_calls, tol, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, st = R.solve_batch(items)
+        return time.perf_counter() - t0, outs, st
+
+    # each image's own converged PSNR: plain FP (FP32) to a relative change < 1e-6
+    _, ref, ref_st = run("none", "fp32", 1e-6, 2000)
+    ref_psnr = [psnr(o, xt) for o, xt in zip(ref, xts)]
+    log("batched reference: calls", max(s["fp_calls"] for s in ref_st))
+    out = {"workload": f"{len(probs)} images, sides log-uniform 128..1024, {mpix:.2f} MPix, "
+                       "uniform 9x9 or Gaussian 7x7 blur, sigma sqrt(2) or 5, lambda 0.02, 15 CG",
+           "stop": "per image: relative change < 1e-5",
+           "reference": "per image: plain FP (FP32) to relative change < 1e-6",
+           "mpix": mpix}
+    for name, method, prec, reps in (("ve_bf16", "rre", "bf16", 3), ("ve_fp32", "rre", "fp32", 1),
+                                     ("plain_fp32", "none", "fp32", 1)):
+        run(method, prec, 1e-5, 500)  # warm-up: workspace and graphs
+        times = []
+        for _ in range(reps):
+            dt, outs, st = run(method, prec, 1e-5, 500)
+            times.append(dt)
+        dt = float(np.median(times))
+        dps = [psnr(o, xt) - rp for o, xt, rp in zip(outs, xts, ref_psnr)]
+        calls = [s["fp_calls"] for s in st]
+        out[name] = {"mpix_s": mpix / dt, "s_per_batch": dt,
+                     "fp_calls_mean": float(np.mean(calls)), "fp_calls_max": int(max(calls)),
+                     "mpix_fp_calls_per_s": sum(c * p.x_true.size for c, p in zip(calls, probs))
+                     / dt / 1e6,
+                     "images_within_band": int(sum(abs(v) <= BAND_DB for v in dps)),
+                     "worst_dpsnr_db": float(min(dps))}
+        log("batched", name, out[name])
+    out["ve_bf16_speedup_vs_plain_fp32"] = out["plain_fp32"]["s_per_batch"] / out["ve_bf16"]["s_per_batch"]
+    R.close()
+    return out
+
+
+def bench_serve(args, torch, np, W, Restorer):
+    from paper_1805_02158_amd import Server
+    trace = W.serve_trace(args.serve_requests, 1.0)
+    probs = [p for _, p in trace]
+    R = Restorer(0)
+    ys = observe(torch, R, probs)
+    reqs = [dict(y=y, hx=p.hr_shape[0], wx=p.hr_shape[1], psf=p.psf, decim=p.decim,
+                 sigma=p.sigma, lam=p.lam) for p, y in zip(probs, ys)]
+    mpix = sum(p.x_true.size for p in probs) / 1e6
+    R.set_denoiser(W.make_denoiser(), "bf16").set_extrapolation("rre", 5, 0).set_solver(15, 500, 1e-5, 0)
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    srv = Server(R, budget, args.serve_max_active)
+
+    def serve(arrivals):
+        rounds0 = srv.counts()["rounds"]
+        t0 = time.perf_counter()
+        tickets = []
+        for a, d in zip(arrivals, reqs):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            tickets.append(srv.submit(**d)[0])
+        st = [srv.wait(t) for t in tickets]
+        makespan = time.perf_counter() - t0
+        lat = np.array([s["ms"] for s in st])
+        bad = sum(s["status"] != 0 for s in st)
+        return makespan, lat, srv.counts()["rounds"] - rounds0, bad
+
+    serve([0.0] * 16)  # warm-up: the graphs of the first tile-list lengths
+    mk, lat_sat, rounds_sat, bad = serve([0.0] * len(reqs))
+    rate_sat = len(reqs) / mk
+    rate = 0.7 * rate_sat
+    arrivals = [a / rate for a, _ in trace]  # the trace's arrivals (drawn at rate 1) at `rate`
+    mk2, lat, rounds2, bad2 = serve(arrivals)
+    srv.close()
+    res = {"workload": f"{len(reqs)} requests, sides log-uniform 128..2048 ({mpix:.1f} MPix), "
+                       "deblur 9x9 uniform or 3x SR Gaussian 7x7, sigma sqrt(2) or 5, RRE L=5, "
+                       "BF16 banks, stop at relative change < 1e-5",
+           "hbm_budget_gb": args.serve_budget_gb, "max_active": args.serve_max_active,
+           "saturation": {"req_s": rate_sat, "mpix_s": mpix / mk, "rounds": rounds_sat,
+                          "p50_ms": float(np.percentile(lat_sat, 50)),
+                          "p99_ms": float(np.percentile(lat_sat, 99)), "failed": bad},
+           "poisson": {"rate_req_s": rate, "mpix_s": mpix / mk2, "rounds": rounds2,
+                       "p50_ms": float(np.percentile(lat, 50)),
+                       "p99_ms": float(np.percentile(lat, 99)), "failed": bad2}}
+    log("serving", res)
+    R.close()
+    return res
+
+
+def cpu_baseline(prob, calls, min_seconds):
+    """The FP64 oracle (plain C, OpenMP over rows/filters) on the host: whole RRE solves
+    (L = 5, the GPU's FP-call count to the target) of the same image, repeated until at least
+    `min_seconds` have passed (at most 50 solves)."""
     import oracle
     op = oracle.OracleProblem(prob)
-    n = max(1, min(sample_calls, calls))
-    t0 = time.perf_counter()
-    oracle.solve(op, "rre", L=prob.L, m=0, tol=0.0, max_calls=n)
-    dt = time.perf_counter() - t0
-    per_solve = dt / n * calls
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.solve(op, "rre", L=prob.L, m=0, tol=0.0, max_calls=calls)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or n >= 50:
+            break
     npx = prob.x_true.size
-    return {"value": npx / per_solve / 1e6, "unit": "MPix/s", "cores": oracle.num_threads(),
+    return {"value": npx * n / dt / 1e6, "unit": "MPix/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} FP calls of the RRE solve of the same 256x256 image "
-                      f"({dt:.1f} s), scaled to {calls} FP calls per solve"}
+            "sample": f"{n} whole RRE solves ({calls} FP calls each, FP64) of the same 256x256 "
+                      f"image, {dt:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -170,10 +170,12 @@ typedef struct {
  * of an FP call (eq. (7)) runs once over a tile list of the running images, each FP call is one
  * replay of a captured HIP graph, and converged images drop out of the list. Reductions are per
  * image, in a fixed order, so each image's result does not depend on the other images in the
- * batch. Waits for the handle's stream before reading the inputs; allocates its workspace
- * (about 4 (14 + L) bytes per pixel) for the call. st: n entries (host) or NULL; st[i].status
- * is the item's own outcome. Returns REDVE_OK, an argument/HIP error, or the first non-OK item
- * status. */
+ * batch. Waits for the handle's stream before reading the inputs and runs on a stream of the
+ * handle's own. The workspace (about 4 (14 + L) bytes per pixel) and the captured graphs are
+ * kept in the handle for later calls that fit them with unchanged denoiser, extrapolation and
+ * CG settings; otherwise they are rebuilt; redve_destroy frees them. st: n entries (host) or
+ * NULL; st[i].status is the item's own outcome. Returns REDVE_OK, an argument/HIP error, or the
+ * first non-OK item status. */
 int redve_solve_batch(redve_t h, int n, const redve_item_t* items, redve_stats_t* st);
 
 /* ---- serving: continuous batching of arriving requests --------------------------------- */
@@ -181,8 +183,8 @@ int redve_solve_batch(redve_t h, int n, const redve_item_t* items, redve_stats_t
 typedef struct redve_server* redve_server_t;
 
 /* A scheduler thread with its own stream and a copy of proto's denoiser, extrapolation and
- * solver settings (proto must have a denoiser and must outlive the server: the denoiser's
- * device buffers are shared). The server allocates its whole workspace here, within
+ * solver settings (proto must have a denoiser, must outlive the server and must keep its
+ * denoiser while the server exists: the denoiser's device buffers are shared). The server allocates its whole workspace here, within
  * hbm_budget bytes (4 (14 + L) bytes per pixel of capacity); requests are admitted in arrival
  * order while their pixels fit (and at most max_active run at once). Every round advances each
  * admitted request by one FP call (one batched launch sequence), extrapolates those that

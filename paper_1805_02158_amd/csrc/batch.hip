@@ -90,6 +90,7 @@ struct Slot {
 
 struct Engine {
     redve_t h = nullptr;      // settings (denoiser, method, solver)
+    unsigned long long gen = 0;  // the settings generation the graphs were recorded for
     hipStream_t st = nullptr; // the engine's own stream (capturable; never the null stream)
     int cap_img = 0, cap_tiles = 0, L = 1;
     size_t cap_px = 0;
@@ -203,6 +204,14 @@ struct Engine {
         slots.assign(cap_img, Slot{});
         tiles_dirty = true;
         return REDVE_OK;
+    }
+
+    // Forgets every image (keeps buffers and graphs) for the next batch.
+    void reset() {
+        slots.assign(cap_img, Slot{});
+        px_alloc.used.clear();
+        tiles_used = 0;
+        tiles_dirty = true;
     }
 
     static bool valid_item(const redve_item_t& it) {
@@ -601,36 +610,58 @@ extern "C" int redve_solve_batch(redve_t h, int n, const redve_item_t* items, re
         ntiles += tiles_of(items[i].hx, items[i].wx);
     }
     if (hipSetDevice(h->device) != hipSuccess) return REDVE_E_HIP;
-    if (!h->bstream && hipStreamCreate(&h->bstream) != hipSuccess) return REDVE_E_HIP;
+    // non-blocking: work on the legacy null stream (any thread) must not implicitly join a
+    // stream while a round is being captured on it; ordering is explicit (synchronisations)
+    if (!h->bstream && hipStreamCreateWithFlags(&h->bstream, hipStreamNonBlocking) != hipSuccess)
+        return REDVE_E_HIP;
     // inputs were produced on the caller's stream
     if (hipStreamSynchronize(h->stream) != hipSuccess) return REDVE_E_HIP;
     const auto t0 = Clock::now();
-    Engine eng;
-    if ((rc = eng.init(h, h->bstream, n, npx, ntiles))) {
-        h->err = "batch workspace allocation failed";
-        return rc;
+    // the engine (workspace + captured graphs) is kept in the handle while the settings stay
+    // the same and the batch fits its capacity
+    Engine* eng = (Engine*)h->batch;
+    if (eng && !(eng->gen == h->gen && eng->cap_img >= n && eng->cap_px >= npx &&
+                 eng->cap_tiles >= ntiles)) {
+        delete eng;
+        eng = nullptr;
+        h->batch = nullptr;
     }
-    for (int i = 0; i < n; ++i) {
-        int slot;
-        if (!eng.admit(items[i], (unsigned long long)i, t0, slot)) {
-            h->err = "internal: batch item did not fit its own capacity";
-            return REDVE_E_STATE;
-        }
-    }
-    while (eng.any_running()) {
-        if ((rc = eng.round())) {
-            h->err = rc == REDVE_E_STATE ? "internal: inconsistent batched round (not launched)"
-                                         : "HIP failure in a batched round";
+    if (eng) {
+        eng->reset();
+    } else {
+        eng = new Engine();
+        if ((rc = eng->init(h, h->bstream, n, npx, ntiles))) {
+            delete eng;
+            h->err = "batch workspace allocation failed";
             return rc;
         }
+        eng->gen = h->gen;
+        h->batch = eng;
+        h->batch_free = [](void* p) { delete (Engine*)p; };
     }
-    if (hipStreamSynchronize(h->bstream) != hipSuccess) return REDVE_E_HIP;
+    auto drop = [&](int code, const char* msg) {
+        delete eng;
+        h->batch = nullptr;
+        h->err = msg;
+        return code;
+    };
+    for (int i = 0; i < n; ++i) {
+        int slot;
+        if (!eng->admit(items[i], (unsigned long long)i, t0, slot) || slot != i)
+            return drop(REDVE_E_STATE, "internal: batch item did not fit its own capacity");
+    }
+    while (eng->any_running()) {
+        if ((rc = eng->round()))
+            return drop(rc, rc == REDVE_E_STATE ? "internal: inconsistent batched round (not launched)"
+                                                : "HIP failure in a batched round");
+    }
+    if (hipStreamSynchronize(h->bstream) != hipSuccess) return drop(REDVE_E_HIP, "HIP failure");
     const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     int worst = REDVE_OK;
     for (int i = 0; i < n; ++i) {
-        eng.slots[i].ms = ms;
-        if (st) eng.fill_stats(eng.slots[i], st + i);
-        if (eng.slots[i].status && !worst) worst = eng.slots[i].status;
+        eng->slots[i].ms = ms;
+        if (st) eng->fill_stats(eng->slots[i], st + i);
+        if (eng->slots[i].status && !worst) worst = eng->slots[i].status;
     }
     if (worst) h->err = "at least one batch item did not converge (see its status)";
     return worst;
@@ -753,7 +784,8 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.tol = proto->tol;
     c.rank_eps = proto->rank_eps;
     if (hipSetDevice(c.device) != hipSuccess) return REDVE_E_HIP;
-    if (hipStreamCreate(&c.stream) != hipSuccess) return REDVE_E_HIP;
+    // non-blocking (see redve_solve_batch); inputs are ordered by an event per request
+    if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return REDVE_E_HIP;
     s->caller = proto->stream;
     const int L = c.method == REDVE_VE_NONE ? 1 : c.L;
     const size_t per_px = Engine::bytes_per_px(L);

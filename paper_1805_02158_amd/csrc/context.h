@@ -66,6 +66,13 @@ struct redve_ctx {
     double rank_eps = 1e-7;  // R_jj <= rank_eps * R_00 counts as rank deficient (FP32 data)
     Workspace ws;
     HostMirror* host = nullptr;  // pinned
+    // Settings generation: bumped by every setter that changes what a captured batched round
+    // records (denoiser buffers and stages, precision, extrapolation method and window, CG
+    // iterations). The batched engine kept between redve_solve_batch calls is rebuilt when it
+    // was made for another generation.
+    unsigned long long gen = 0;
+    void* batch = nullptr;                 // the kept batched engine (batch.hip)
+    void (*batch_free)(void*) = nullptr;   // its destructor
 };
 
 // Device view of the handle's denoiser (runtime.hip).

@@ -276,6 +276,8 @@ int redve_destroy(redve_t h) {
     if (!h) return REDVE_E_ARG;
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
+    if (h->batch && h->batch_free) h->batch_free(h->batch);
+    h->batch = nullptr;
     if (h->ws.arena) hipFree(h->ws.arena);
     hipFree(h->d_psf);
     hipFree(h->d_psf64);
@@ -357,6 +359,7 @@ int redve_set_lambda(redve_t h, double lambda) {
 
 int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     if (!h) return REDVE_E_ARG;
+    ++h->gen;
     if (!p) return fail(h, REDVE_E_ARG, "null denoiser");
     if (p->stages < 0 || p->stages > kMaxStages) return fail(h, REDVE_E_ARG, "stages must be 0..16");
     if (p->ksize != 5) return fail(h, REDVE_E_ARG, "ksize must be 5");
@@ -450,6 +453,7 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m) {
     if (method < REDVE_VE_NONE || method > REDVE_VE_SVD_MPE) return fail(h, REDVE_E_ARG, "bad method");
     if (L < 2 || L > REDVE_MAX_L) return fail(h, REDVE_E_ARG, "L must be 2..16");
     if (m < 0) return fail(h, REDVE_E_ARG, "m must be >= 0");
+    if (method != h->method || L != h->L) ++h->gen;
     h->method = method;
     h->L = L;
     h->m = m;
@@ -460,6 +464,7 @@ int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int 
     if (!h) return REDVE_E_ARG;
     if (cg_iters < 0 || max_fp_calls < 0 || extra_fp < 0 || !(tol >= 0) || !std::isfinite(tol))
         return fail(h, REDVE_E_ARG, "solver settings out of range");
+    if (cg_iters != h->cg_iters) ++h->gen;
     h->cg_iters = cg_iters;
     h->max_fp = max_fp_calls;
     h->tol = tol;

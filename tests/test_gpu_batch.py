@@ -146,6 +146,52 @@ def test_batch_result_independent_of_the_batch(torch, orc):
     assert torch.equal(alone[0], rev[3])
 
 
+def test_batch_engine_reuse(torch, orc):
+    """The handle keeps the batched engine between calls: a repeated batch is bitwise the
+    same; after a settings change (CG count, extrapolation method) the result is bitwise that
+    of a fresh handle with the new settings; switching back restores the first result."""
+    say("batch reuse")
+    probs = mixed_problems(orc, 5, seed=4)
+    r = restorer("rre", 5, 0.0, 10)
+    a, _ = r.solve_batch(as_dicts(torch, probs))
+    b, _ = r.solve_batch(as_dicts(torch, probs))
+    r.set_solver(10, 10, 0.0, 0)
+    c, _ = r.solve_batch(as_dicts(torch, probs))
+    fc = restorer("rre", 5, 0.0, 10).set_solver(10, 10, 0.0, 0).solve_batch(as_dicts(torch, probs))[0]
+    r.set_solver(15, 10, 0.0, 0).set_extrapolation("mpe", 5, 0)
+    e, _ = r.solve_batch(as_dicts(torch, probs))
+    fe = restorer("mpe", 5, 0.0, 10).solve_batch(as_dicts(torch, probs))[0]
+    r.set_extrapolation("rre", 5, 0)
+    d, _ = r.solve_batch(as_dicts(torch, probs))
+    fresh, _ = restorer("rre", 5, 0.0, 10).solve_batch(as_dicts(torch, probs))
+    for i in range(len(probs)):
+        say(f"  image {i}: cg 10 vs 15 max|diff| {float((c[i] - a[i]).abs().max()):.3e}, "
+            f"mpe vs rre {float((e[i] - a[i]).abs().max()):.3e}")
+        assert torch.equal(a[i], b[i]) and torch.equal(a[i], d[i]) and torch.equal(a[i], fresh[i])
+        assert torch.equal(c[i], fc[i]) and torch.equal(e[i], fe[i])
+        assert not torch.equal(a[i], e[i])
+
+
+def test_single_cg_count_matters(torch, orc):
+    """Diagnostic companion of the reuse test: the single-image path with 10 and 15 CG
+    iterations per FP call, fixed schedule of 10 calls (differences printed)."""
+    prob, y32 = mixed_problems(orc, 1, seed=4)[0]
+    out = []
+    for cg in (10, 15):
+        r = restorer("rre", 5, 0.0, 10).set_solver(cg, 10, 0.0, 0)
+        xs, st = single(torch, r, prob, y32)
+        out.append(xs)
+    say(f"  single path: cg 10 vs 15 rel diff {rel(out[0], out[1]):.3e}")
+    one = []
+    for cg in (10, 15):
+        r = restorer("none", 5, 0.0, 1).set_solver(cg, 1, 0.0, 0)
+        xs, st = single(torch, r, prob, y32)
+        one.append(xs)
+    d1 = rel(one[0], one[1])
+    say(f"  one FP call: cg 10 vs 15 rel diff {d1:.3e}")
+    assert d1 > 0
+
+
 def test_batch_converged_and_m(torch, orc):
     """Tolerance-driven RRE with m = 1: every image reaches the oracle's fixed point."""
     say("batch converged")
