@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only a calibration copy and the dominant kernels (for rocprofv3 "
+                         "--pmc FETCH_SIZE / WRITE_SIZE runs), print nothing")
     return ap.parse_args()
 
 
@@ -89,6 +92,9 @@ def main():
     R.configure(prob, method="rre", L=prob.L, m=0, tol=0.0)
     y = R.apply_H(x_true) + float(prob.sigma) * noise  # observation, eq. (1)
     torch.cuda.synchronize()
+    if args.pmc_probe:
+        pmc_probe(torch, R, prob, y)
+        return
 
     def psnr(x, ref=x_true):
         mse = torch.mean((x.double() - ref.double()) ** 2).item()
@@ -149,14 +155,24 @@ def main():
     ve = res_forms["ve_bf16"]
     fp = res_forms["plain_fp32"]
 
-    # ---- roofline of the dominant kernel: the fused denoiser stage of the headline form,
-    # timed with HIP events on the library's stream (torch's current stream)
+    # ---- rooflines of the two kernels of an FP call, timed with HIP events on the library's
+    # stream (torch's current stream): the fused denoiser stage of the headline form (BF16
+    # banks) and the CG iteration; `roofline` is the one with the larger share of an FP call
+    # (5 stages, 15 CG iterations) at the headline size.
     R.set_denoiser(prob.denoiser, "bf16")
     stage_us = time_stage(torch, R, y, prob.denoiser.stages)
-    roof = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16")
+    cg_us = time_cg_iter(torch, R, y)
+    roof_stage = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16")
+    roof_cg = roofline_cg(npx, cg_us, "k_cg_iter<4>")
+    share = {"k_tnrd_stage_bf16": prob.denoiser.stages * stage_us,
+             "k_cg_iter<4>": prob.cg_iters * cg_us}
+    roof = roof_cg if share["k_cg_iter<4>"] >= share["k_tnrd_stage_bf16"] else roof_stage
+    roof["share_of_fp_call_us"] = share
     big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device=dev)
     stage_big_us = time_stage(torch, R, big, prob.denoiser.stages)
     roof_big = roofline_stage(big.numel(), stage_big_us, "k_tnrd_stage_bf16")
+    cg_big_us = time_cg_iter(torch, R, big)
+    roof_cg_big = roofline_cg(big.numel(), cg_big_us, "k_cg_iter<4>")
     R.set_denoiser(prob.denoiser, "fp32")
     stage32_big_us = time_stage(torch, R, big, prob.denoiser.stages)
     roof32_big = roofline_stage(big.numel(), stage32_big_us, "k_tnrd_stage_f32")
@@ -188,7 +204,9 @@ def main():
         "forms": res_forms,
         "ve_bf16_speedup_vs_plain_fp32": fp["ms_per_step"] / ve["ms_per_step"],
         "roofline": roof,
-        "roofline_stage_2048x2048": {"bf16": roof_big, "fp32": roof32_big},
+        "roofline_kernels": {"k_tnrd_stage_bf16": roof_stage, "k_cg_iter<4>": roof_cg},
+        "roofline_2048x2048": {"k_tnrd_stage_bf16": roof_big, "k_tnrd_stage_f32": roof32_big,
+                               "k_cg_iter<4>": roof_cg_big},
     }
     if not args.no_batch:
         res["batched"] = bench_batch(args, torch, np, W, Restorer, psnr)
@@ -214,6 +232,78 @@ def time_stage(torch, R, x, stages, reps=20):
     return e0.elapsed_time(e1) * 1e3 / (reps * stages)
 
 
+def time_cg_iter(torch, R, x, reps=10):
+    """Average duration of one CG iteration launch: HIP events around `reps` CG runs of 45 and
+    of 15 iterations (the same set-up launches); the difference over 30 * reps iterations."""
+    stream = torch.cuda.current_stream()
+
+    def run(iters):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            R.cg(x, x, iters)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    run(15)
+    return (run(45) - run(15)) * 1e3 / (30 * reps)
+
+
+# Algorithmic HBM traffic of one CG iteration per pixel (x, r, p each read and written once,
+# A p never stored), and the published MI355X HBM3E bandwidth.
+CG_BYTES_PER_PX = 24
+HBM_PEAK_GBS = 8000.0
+
+
+def roofline_cg(npx, iter_us, kernel):
+    """The CG iteration is bound by HBM bandwidth (its stencil work is 84 FLOP per pixel).
+    achieved = algorithmic bytes per launch / average launch time. traffic: the bytes the
+    FETCH_SIZE and WRITE_SIZE counters saw per launch at this size (profiles/traffic.json),
+    null if the kernel's source changed since."""
+    work = npx * CG_BYTES_PER_PX
+    achieved = work / (iter_us * 1e-6) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_of(kernel, npx),
+            "avg_launch_us": iter_us, "bytes_per_launch": work, "bytes_per_px": CG_BYTES_PER_PX,
+            "pixels_per_launch": npx}
+
+
+def traffic_of(kernel, npx):
+    """HBM bytes per launch measured by the counters for this kernel at this size, if the
+    source it was measured on is the current one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    for e in json.load(open(path)):
+        if e["kernel"] != kernel or e["pixels_per_launch"] != npx:
+            continue
+        src = os.path.join(ROOT, e["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != e["source_sha256"]:
+            return None
+        return e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+    return None
+
+
+def pmc_probe(torch, R, prob, y):
+    """Launches for the counter runs: 5 plain copies of 256 MiB (calibration: each moves
+    exactly 256 MiB in and 256 MiB out), then at the headline size 5 CG runs of 15 iterations
+    (FP32) and 5 denoiser calls with BF16 banks."""
+    src = torch.rand(64 << 20, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    for _ in range(5):
+        R.cg(y, y, prob.cg_iters)
+    R.set_denoiser(prob.denoiser, "bf16")
+    for _ in range(5):
+        R.denoise(y)
+    torch.cuda.synchronize()
+
+
 # Algorithmic work of one denoiser stage per output pixel, as the method defines it:
 # two 24-filter 5x5 banks (forward and adjoint, 2 x 24 x 25 multiply-adds = 2400 FLOP) and
 # 24 influence functions of 63 Gaussian RBF terms, each term counted as 6 FLOP (difference,
@@ -232,7 +322,8 @@ def roofline_stage(npx, stage_us, kernel):
     achieved = work / (stage_us * 1e-6) / 1e12
     return {"kernel": kernel, "bound": "alu", "achieved": achieved,
             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-            "traffic": None, "avg_launch_us": stage_us, "flop_per_launch": work,
+            "traffic": traffic_of(kernel, npx), "avg_launch_us": stage_us,
+            "flop_per_launch": work,
             "flop_per_px": STAGE_FLOP_PER_PX, "pixels_per_launch": npx}
 
 

@@ -2,9 +2,12 @@
 // (eq. (7)) per round, each with its own full-cycling state (Algorithm 3).
 //
 // Every kernel of a round runs once over a tile list covering the running images (16x16
-// tiles, packed in slot order and padded to a power-of-two length with entries that point at
-// an always-inactive image), so a round is a fixed launch sequence per (stencil class, list
-// length): it is captured once as a HIP graph and replayed. What changes between rounds (which
+// tiles, padded to a power-of-two length with entries that point at an always-inactive image),
+// so a round is a fixed launch sequence per (stencil class, list length): it is captured once
+// as a HIP graph and replayed. The list is in dispatch order: workgroups go round-robin over
+// the 8 XCDs, and the workgroups of each XCD take a contiguous run of the live tiles (image by
+// image, row-major) and then an equal share of the padding, so neighbouring tiles share an L2
+// and every XCD gets the same amount of work. What changes between rounds (which
 // buffers hold x_in / x_out / x_m, the window column, whether to extrapolate, which images are
 // active, where an image's tiles start in the list) lives in the per-image descriptors,
 // uploaded before each replay. Per-image reductions sum per-tile partials in tile order, so an
@@ -101,7 +104,7 @@ struct Engine {
     float* vec[kVecs] = {};
     float* U = nullptr;
     ImgDesc* d_desc = nullptr;
-    int* d_tile = nullptr;
+    TileRef* d_tile = nullptr;
     CgImg* d_cg = nullptr;
     double* d_part = nullptr;
     double* d_G = nullptr;
@@ -111,7 +114,8 @@ struct Engine {
     double* d_psf64 = nullptr;  // per slot: 15 x 15 doubles
     ImgDesc* h_desc = nullptr;  // pinned
     ImgStat* h_stat = nullptr;  // pinned
-    int* h_tile = nullptr;      // pinned
+    TileRef* h_tile = nullptr;  // pinned
+    std::vector<TileRef> live;  // live tiles in partial-index order (repack scratch)
     bool tiles_dirty = true;
     std::vector<Slot> slots;
     // graphs keyed by (stencil radius class, tile list length)
@@ -152,7 +156,7 @@ struct Engine {
         L = h->method == REDVE_VE_NONE ? 1 : h->L;
         cap_img = nimg;
         cap_px = align64(npx);
-        cap_tiles = std::max(ntiles, 1);
+        cap_tiles = (std::max(ntiles, 1) + kXcds - 1) / kXcds * kXcds;
         part_vals = std::max(L + 2, 2);
         px_alloc.cap = cap_px;
         tiles_used = 0;
@@ -167,7 +171,7 @@ struct Engine {
         for (int i = 0; i < kVecs; ++i) o_vec[i] = take(vbytes);
         const size_t o_U = take(vbytes * L);
         const size_t o_desc = take(sizeof(ImgDesc) * (cap_img + 1));
-        const size_t o_tile = take(sizeof(int) * cap_tiles);
+        const size_t o_tile = take(sizeof(TileRef) * cap_tiles);
         const size_t o_cg = take(sizeof(CgImg) * (cap_img + 1));
         const size_t o_part = take(sizeof(double) * (size_t)part_vals * cap_tiles);
         const size_t o_G = take(sizeof(double) * 256 * (cap_img + 1));
@@ -183,7 +187,7 @@ struct Engine {
         for (int i = 0; i < kVecs; ++i) vec[i] = (float*)(b + o_vec[i]);
         U = (float*)(b + o_U);
         d_desc = (ImgDesc*)(b + o_desc);
-        d_tile = (int*)(b + o_tile);
+        d_tile = (TileRef*)(b + o_tile);
         d_cg = (CgImg*)(b + o_cg);
         d_part = (double*)(b + o_part);
         d_G = (double*)(b + o_G);
@@ -195,7 +199,8 @@ struct Engine {
                 hipSuccess ||
             hipHostMalloc((void**)&h_stat, sizeof(ImgStat) * (cap_img + 1), hipHostMallocDefault) !=
                 hipSuccess ||
-            hipHostMalloc((void**)&h_tile, sizeof(int) * cap_tiles, hipHostMallocDefault) != hipSuccess)
+            hipHostMalloc((void**)&h_tile, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
+                hipSuccess)
             return REDVE_E_NOMEM;
         memset(h_desc, 0, sizeof(ImgDesc) * (cap_img + 1));
         memset(h_stat, 0, sizeof(ImgStat) * (cap_img + 1));
@@ -356,22 +361,30 @@ struct Engine {
         return 0;
     }
 
-    // Packs the running images' tiles in slot order and pads the list to a power of two (at
-    // least 64, at most the capacity) with the always-inactive image cap_img.
+    // Builds the tile list: the running images' tiles in slot order get partial indices
+    // 0..pos-1 (each image a contiguous range from its tile0); the list length B is a power of
+    // two (at least 64, at most the capacity; both multiples of 8). Workgroup b runs on XCD
+    // b mod 8; XCD x's workgroups take the x-th contiguous chunk of the live tiles, then padding.
     int repack() {
-        int pos = 0;
+        live.clear();
         for (int i = 0; i < cap_img; ++i) {
             Slot& sl = slots[i];
             if (!sl.running) continue;
-            sl.tile0 = pos;
-            for (int t = 0; t < sl.ntiles; ++t) h_tile[pos++] = i;
+            sl.tile0 = (int)live.size();
+            for (int t = 0; t < sl.ntiles; ++t) live.push_back(TileRef{i, t});
         }
-        int b = 64;
-        while (b < pos) b *= 2;
-        b = std::min(b, cap_tiles);
-        for (int k = pos; k < b; ++k) h_tile[k] = cap_img;
-        launch_tiles = b;
-        return hipMemcpyAsync(d_tile, h_tile, sizeof(int) * b, hipMemcpyHostToDevice, st) ==
+        const int pos = (int)live.size();
+        int B = 64;
+        while (B < pos) B *= 2;
+        B = std::min(B, cap_tiles);
+        const int nb = B / kXcds, q = pos / kXcds, r = pos % kXcds;
+        for (int x = 0; x < kXcds; ++x) {
+            const int start = x * q + std::min(x, r), len = q + (x < r ? 1 : 0);
+            for (int i = 0; i < nb; ++i)
+                h_tile[x + kXcds * i] = i < len ? live[start + i] : TileRef{cap_img, 0};
+        }
+        launch_tiles = B;
+        return hipMemcpyAsync(d_tile, h_tile, sizeof(TileRef) * B, hipMemcpyHostToDevice, st) ==
                        hipSuccess
                    ? REDVE_OK
                    : REDVE_E_HIP;
@@ -449,13 +462,23 @@ struct Engine {
                 o.decim > REDVE_MAX_DECIM || o.kh < 1 || o.kw < 1 || !(o.kh & 1) || !(o.kw & 1) ||
                 o.kh > REDVE_MAX_PSF || o.kw > REDVE_MAX_PSF)
                 return false;
-            for (int t = 0; t < d.ntiles; ++t)
-                if (h_tile[pos + t] != i) return false;
             pos += d.ntiles;
         }
-        if (pos > launch_tiles || launch_tiles > cap_tiles) return false;
-        for (int k = pos; k < launch_tiles; ++k)
-            if (h_tile[k] != cap_img) return false;
+        if (pos > launch_tiles || launch_tiles > cap_tiles || launch_tiles % kXcds) return false;
+        // every live tile exactly once, every other entry the inactive image
+        std::vector<char> seen(pos, 0);
+        for (int b = 0; b < launch_tiles; ++b) {
+            const TileRef e = h_tile[b];
+            if (e.img == cap_img) continue;
+            if (e.img < 0 || e.img > cap_img || !slots[e.img].running || e.t < 0 ||
+                e.t >= h_desc[e.img].ntiles)
+                return false;
+            const int pi = h_desc[e.img].tile0 + e.t;
+            if (seen[pi]) return false;
+            seen[pi] = 1;
+        }
+        for (char c : seen)
+            if (!c) return false;
         return !h_desc[cap_img].active;
     }
 

@@ -30,8 +30,8 @@ struct LinOp {
     double row_d[kMaxPsf], col_d[kMaxPsf];
 };
 
-// One image of a batch (batched kernels take a device array of these and a tile list that maps
-// every 16x16 tile of every image to its image).
+// One image of a batch (batched kernels take a device array of these and a tile list that gives
+// each workgroup a 16x16 tile of an image).
 struct ImgDesc {
     int H, W;          // image size
     int tile0, ntiles; // this image's range in the batch tile list
@@ -47,6 +47,23 @@ struct ImgDesc {
     LinOp op;
 };
 constexpr int kBatchTile = 16;  // side of the tiles of the batch tile list
+
+// Entry of the batch tile list: image img, its row-major tile t (of ceil(W/16) per row). The
+// host orders the list for dispatch (see the batched engine); per-tile partial sums go to index
+// desc[img].tile0 + t, contiguous per image.
+struct TileRef {
+    int img, t;
+};
+
+constexpr int kXcds = 8;  // accelerator dies of the MI355X, each with its own L2
+// The tile workgroup b processes, out of n. Workgroups are dispatched round-robin over the
+// XCDs (b on XCD b mod 8); XCD x gets the contiguous x-th chunk of the tiles, so tiles that
+// share halo rows and columns are fetched through the same L2. A bijection of [0, n).
+__device__ inline int xcd_tile(int b, int n) {
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
 
 struct VeInfo;
 
@@ -64,24 +81,24 @@ struct CgImg {
 };
 
 // Batched CG (see linear.hip). Partials are per tile (value v of tile T at part[v * cap + T]).
-void launch_cg_init_fp_batch(const ImgDesc* desc, const int* tile_img, int ntiles,
+void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
                              const float* sres /* null: f = identity */, float* r, hipStream_t st);
-void launch_cg_w0_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs,
+void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                         const float* r, float* w, double* part, int cap, hipStream_t st);
 void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
                          CgImg* cg, hipStream_t st);
-void launch_cg_iter_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs, int k,
+void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs, int k,
                           int last, const CgImg* cg, const float* r_in, const float* w_in,
                           const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
                           float* d, double* part, int cap, hipStream_t st);
 // Batched VE (see ve.hip).
-void launch_diff_gram_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int L, float* U,
+void launch_diff_gram_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int L, float* U,
                             size_t ustride, double* part, int cap, hipStream_t st);
 void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* part, int cap,
                            double* G, ImgStat* stat, hipStream_t st);
 void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
                            const double* G, VeInfo* info, ImgStat* stat, hipStream_t st);
-void launch_ve_combine_batch(const ImgDesc* desc, const int* tile_img, int ntiles, const float* U,
+void launch_ve_combine_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, const float* U,
                              size_t ustride, const VeInfo* info, hipStream_t st);
 
 // Denoiser parameters on the device (FP32; BF16 copies of the filters for the MFMA path).
@@ -132,11 +149,11 @@ int tnrd_grid(int H, int W);
 size_t tnrd_smem_bytes(int F, int J);
 // Batched stage over the tile list; vectors are base pointers of per-image arrays.
 // f is each image's x_in (from its descriptor).
-void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const int* tile_img,
+void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
                              int ntiles, const float* w_prev, float* out, int out_mode,
                              hipStream_t st);
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
-                                  const int* tile_img, int ntiles, const float* w_prev, float* out,
+                                  const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st);
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,

@@ -20,9 +20,15 @@ constexpr int MAXR = (kMaxPsf - 1) / 2;
 constexpr int PH = TH + 4 * MAXR, PW = TW + 4 * MAXR;
 constexpr int NO = TH * TW / kThreads;  // outputs per thread
 
+// i mod n in [0, n). Stencil indexes are at most one period outside [0, n) unless the image
+// is smaller than the halo; only then is the division needed.
 __device__ inline int wrapi(int i, int n) {
-    int r = i % n;
-    return r < 0 ? r + n : r;
+    int r = i < 0 ? i + n : (i >= n ? i - n : i);
+    if ((unsigned)r >= (unsigned)n) {
+        r = i % n;
+        r = r < 0 ? r + n : r;
+    }
+    return r;
 }
 
 // y[i,j] = sum_{a,b} psf[a+rh][b+rw] x[(s i - a) mod H][(s j - b) mod W]
@@ -65,11 +71,16 @@ __global__ __launch_bounds__(kThreads) void k_apply_Ht(const float* __restrict__
     out[idx] = scale * acc;
 }
 
-// LDS scratch of one tile product: three regions of PH x PW.
+// LDS of one tile product, sized for stencil radius RS (RS = 0: any radius up to MAXR): the P
+// region (tile + 2r halo), the row-pass results, and B P masked by S^T S on the tile + r halo.
+template <int RS>
 struct TileSmem {
-    float p[PH * PW];  // P region: tile + 2r halo
-    float h[PH * PW];  // row-pass results
-    float t[PH * PW];  // masked B P on tile + r halo
+    static constexpr int S = RS ? TW + 4 * RS : PW;   // row stride of every region
+    static constexpr int RP = RS ? TH + 4 * RS : PH;  // rows of the P and row-pass regions
+    static constexpr int RT = RS ? TH + 2 * RS : PH;  // rows of the B P region
+    float p[RP * S];
+    float h[RP * S];
+    float t[RT * S];
 };
 
 // q = A P on the tile at (r0, c0). P must already be in sm.p on the tile + 2r halo (region
@@ -78,7 +89,8 @@ struct TileSmem {
 // general 2-D).
 template <int RS>
 __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, int c0,
-                                       TileSmem& sm, float (&pc)[NO], float (&q)[NO]) {
+                                       TileSmem<RS>& sm, float (&pc)[NO], float (&q)[NO]) {
+    constexpr int SW = TileSmem<RS>::S;
     const int rh = RS ? RS : op.kh / 2, rw = RS ? RS : op.kw / 2;
     const int kh = 2 * rh + 1, kw = 2 * rw + 1;
     const int ph = TH + 4 * rh;                    // P region rows
@@ -88,14 +100,14 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
         // row pass over all P rows, B columns: h[pr][bc] = sum_b row[b] P[pr][bc + 2rw - b]
         for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
             const int pr = e / bw, bc = e % bw;
-            const float* prow = sm.p + pr * PW + bc + 2 * rw;
+            const float* prow = sm.p + pr * SW + bc + 2 * rw;
             float acc = 0.f;
 #pragma unroll
             for (int b = 0; b < (RS ? 2 * RS + 1 : kMaxPsf); ++b) {
                 if (!RS && b >= kw) break;
                 acc += op.row[b] * prow[-b];
             }
-            sm.h[pr * PW + bc] = acc;
+            sm.h[pr * SW + bc] = acc;
         }
         __syncthreads();
         // column pass + decimation mask: t[br][bc] = m * sum_a col[a] h[br + 2rh - a][bc]
@@ -108,41 +120,41 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
                 keep = gr % s == 0 && gc % s == 0;
             }
             if (keep) {
-                const float* hcol = sm.h + (br + 2 * rh) * PW + bc;
+                const float* hcol = sm.h + (br + 2 * rh) * SW + bc;
 #pragma unroll
                 for (int a = 0; a < (RS ? 2 * RS + 1 : kMaxPsf); ++a) {
                     if (!RS && a >= kh) break;
-                    acc += op.col[a] * hcol[-a * PW];
+                    acc += op.col[a] * hcol[-a * SW];
                 }
             }
-            sm.t[br * PW + bc] = acc;
+            sm.t[br * SW + bc] = acc;
         }
         __syncthreads();
         // B^T row pass: h[br][tc] = sum_b row[b] t[br][tc + b]
         for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
             const int br = e / TW, tc = e % TW;
-            const float* trow = sm.t + br * PW + tc;
+            const float* trow = sm.t + br * SW + tc;
             float acc = 0.f;
 #pragma unroll
             for (int b = 0; b < (RS ? 2 * RS + 1 : kMaxPsf); ++b) {
                 if (!RS && b >= kw) break;
                 acc += op.row[b] * trow[b];
             }
-            sm.h[br * PW + tc] = acc;
+            sm.h[br * SW + tc] = acc;
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int o = threadIdx.x + k * kThreads;
             const int tr = o / TW, tc = o % TW;
-            const float* hcol = sm.h + tr * PW + tc;
+            const float* hcol = sm.h + tr * SW + tc;
             float acc = 0.f;
 #pragma unroll
             for (int a = 0; a < (RS ? 2 * RS + 1 : kMaxPsf); ++a) {
                 if (!RS && a >= kh) break;
-                acc += op.col[a] * hcol[a * PW];
+                acc += op.col[a] * hcol[a * SW];
             }
-            pc[k] = sm.p[(tr + 2 * rh) * PW + tc + 2 * rw];
+            pc[k] = sm.p[(tr + 2 * rh) * SW + tc + 2 * rw];
             q[k] = op.inv_s2 * acc + op.lambda * pc[k];
         }
     } else {
@@ -152,12 +164,12 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
             float acc = 0.f;
             if (gr % s == 0 && gc % s == 0) {
                 for (int a = -rh; a <= rh; ++a) {
-                    const float* prow = sm.p + (br + rh - a) * PW + bc + rw;
+                    const float* prow = sm.p + (br + rh - a) * SW + bc + rw;
                     const float* krow = op.psf + (a + rh) * op.kw + rw;
                     for (int b = -rw; b <= rw; ++b) acc += krow[b] * prow[-b];
                 }
             }
-            sm.t[br * PW + bc] = acc;
+            sm.t[br * SW + bc] = acc;
         }
         __syncthreads();
 #pragma unroll
@@ -166,11 +178,11 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
             const int tr = o / TW, tc = o % TW;
             float acc = 0.f;
             for (int a = -rh; a <= rh; ++a) {
-                const float* trow = sm.t + (tr + a + rh) * PW + tc + rw;
+                const float* trow = sm.t + (tr + a + rh) * SW + tc + rw;
                 const float* krow = op.psf + (a + rh) * op.kw + rw;
                 for (int b = -rw; b <= rw; ++b) acc += krow[b] * trow[b];
             }
-            pc[k] = sm.p[(tr + 2 * rh) * PW + tc + 2 * rw];
+            pc[k] = sm.p[(tr + 2 * rh) * SW + tc + 2 * rw];
             q[k] = op.inv_s2 * acc + op.lambda * pc[k];
         }
     }
@@ -179,14 +191,15 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
 
 // Loads f(g) for every position of the P region of the tile at (r0, c0) into sm.p.
 template <int RS, typename F>
-__device__ inline void tile_load(const LinOp& op, int H, int W, int r0, int c0, TileSmem& sm,
+__device__ inline void tile_load(const LinOp& op, int H, int W, int r0, int c0, TileSmem<RS>& sm,
                                  F f) {
+    constexpr int SW = TileSmem<RS>::S;
     const int rh = RS ? RS : op.kh / 2, rw = RS ? RS : op.kw / 2;
     const int ph = TH + 4 * rh, pw = TW + 4 * rw;
     for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
         const int pr = e / pw, pcol = e % pw;
         const size_t g = (size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pcol, W);
-        sm.p[pr * PW + pcol] = f(g);
+        sm.p[pr * SW + pcol] = f(g);
     }
     __syncthreads();
 }
@@ -202,10 +215,11 @@ __device__ inline int ntiles(int H, int W) { return ((H + TH - 1) / TH) * ((W + 
 template <int RS>
 __global__ __launch_bounds__(kThreads) void k_apply_A(const LinOp op, const float* __restrict__ p,
                                                       int H, int W, float* __restrict__ out) {
-    __shared__ TileSmem sm;
-    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+    __shared__ TileSmem<RS> sm;
+    const int nt = ntiles(H, W);
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
-        tile_origin(t, W, r0, c0);
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
         tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return p[g]; });
         float pc[NO], q[NO];
         tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
@@ -223,10 +237,11 @@ template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init(const LinOp op, const float* __restrict__ x_in,
                                                       const float* __restrict__ rhs,
                                                       float* __restrict__ r, int H, int W) {
-    __shared__ TileSmem sm;
-    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+    __shared__ TileSmem<RS> sm;
+    const int nt = ntiles(H, W);
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
-        tile_origin(t, W, r0, c0);
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
         tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return x_in[g]; });
         float pc[NO], q[NO];
         tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
@@ -343,9 +358,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const f
                                                          const float* __restrict__ s,
                                                          float* __restrict__ r, int H, int W) {
     __shared__ InitFpSmem sm;
-    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+    const int nt = ntiles(H, W);
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
-        tile_origin(t, W, r0, c0);
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
         init_fp_tile(op, x, y, s, r, H, W, r0, c0, sm);
     }
 }
@@ -353,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const f
 // w0 = A r0 on one tile; accumulates r0.r0 and w0.r0.
 template <int RS>
 __device__ inline void w0_tile(const LinOp& op, const float* __restrict__ r, float* __restrict__ w,
-                               int H, int W, int r0, int c0, TileSmem& sm, double (&acc)[2]) {
+                               int H, int W, int r0, int c0, TileSmem<RS>& sm, double (&acc)[2]) {
     tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return r[g]; });
     float pc[NO], q[NO];
     tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
@@ -374,12 +390,13 @@ template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_w0(const LinOp op, const float* __restrict__ r,
                                                     float* __restrict__ w, int H, int W,
                                                     double* __restrict__ part) {
-    __shared__ TileSmem sm;
+    __shared__ TileSmem<RS> sm;
     __shared__ double sred[2 * kThreads / 64];
     double acc[2] = {0.0, 0.0};
-    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
+    const int nt = ntiles(H, W);
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
-        tile_origin(t, W, r0, c0);
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
         w0_tile<RS>(op, r, w, H, W, r0, c0, sm, acc);
     }
     block_sum<2>(acc, sred);
@@ -410,7 +427,7 @@ __device__ inline void cg_iter_tile(const LinOp& op, int H, int W, int r0, int c
                                     const float* __restrict__ w_in, const float* __restrict__ s_in,
                                     float* __restrict__ r_out, float* __restrict__ w_out,
                                     float* __restrict__ s_out, float* __restrict__ p,
-                                    float* __restrict__ d, TileSmem& sm, double (&acc)[2]) {
+                                    float* __restrict__ d, TileSmem<RS>& sm, double (&acc)[2]) {
     tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) {
         const float sk = k ? w_in[g] + beta * s_in[g] : w_in[g];
         return r_in[g] - alpha * sk;
@@ -456,6 +473,88 @@ __device__ inline void cg_last_tile(int H, int W, int r0, int c0, int k, float a
     }
 }
 
+// Raw inputs of one CG iteration on one tile, loaded before the step lengths are known so that
+// these loads overlap the reduction that produces alpha and beta: r_k, w_k, s_{k-1} on the P
+// region (tile + 2r halo) and r_k, w_k, s_{k-1}, p_{k-1}, d_k at the thread's output pixel.
+template <int RS>
+struct CgIn {
+    static constexpr int PHr = TH + 4 * RS, PWr = TW + 4 * RS;
+    static constexpr int NE = (PHr * PWr + kThreads - 1) / kThreads;
+    float r[NE], w[NE], s[NE];
+    float ro, wo, so, po, dn;
+};
+static_assert(NO == 1, "one output pixel per thread");
+
+template <int RS>
+__device__ inline void cg_fetch(int H, int W, int r0, int c0, int k, const float* __restrict__ r_in,
+                                const float* __restrict__ w_in, const float* __restrict__ s_in,
+                                const float* __restrict__ p, const float* __restrict__ d,
+                                CgIn<RS>& f) {
+    using C = CgIn<RS>;
+#pragma unroll
+    for (int i = 0; i < C::NE; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        f.r[i] = f.w[i] = f.s[i] = 0.f;
+        if (e < C::PHr * C::PWr) {
+            const int pr = e / C::PWr, pc = e % C::PWr;
+            const size_t g =
+                (size_t)wrapi(r0 - 2 * RS + pr, H) * W + wrapi(c0 - 2 * RS + pc, W);
+            f.r[i] = r_in[g];
+            f.w[i] = w_in[g];
+            if (k) f.s[i] = s_in[g];
+        }
+    }
+    f.ro = f.wo = f.so = f.po = f.dn = 0.f;
+    const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
+    if (gr < H && gc < W) {
+        const size_t g = (size_t)gr * W + gc;
+        f.ro = r_in[g];
+        f.wo = w_in[g];
+        if (k) {
+            f.so = s_in[g];
+            f.po = p[g];
+            f.dn = d[g];
+        }
+    }
+}
+
+// cg_iter_tile on prefetched inputs (the same arithmetic).
+template <int RS>
+__device__ inline void cg_iter_fetched(const LinOp& op, int H, int W, int r0, int c0, int k,
+                                       float alpha, float beta, const CgIn<RS>& f,
+                                       float* __restrict__ r_out, float* __restrict__ w_out,
+                                       float* __restrict__ s_out, float* __restrict__ p,
+                                       float* __restrict__ d, TileSmem<RS>& sm,
+                                       double (&acc)[2]) {
+    using C = CgIn<RS>;
+    constexpr int SW = TileSmem<RS>::S;
+#pragma unroll
+    for (int i = 0; i < C::NE; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < C::PHr * C::PWr) {
+            const float sk = k ? f.w[i] + beta * f.s[i] : f.w[i];
+            sm.p[(e / C::PWr) * SW + e % C::PWr] = f.r[i] - alpha * sk;
+        }
+    }
+    __syncthreads();
+    float r1[NO], w1[NO];
+    tile_A_from_lds<RS>(op, H, W, r0, c0, sm, r1, w1);
+    const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
+    if (gr < H && gc < W) {
+        const size_t g = (size_t)gr * W + gc;
+        const float sk = k ? f.wo + beta * f.so : f.wo;
+        const float pk = k ? f.ro + beta * f.po : f.ro;
+        const float dn = k ? f.dn + alpha * pk : alpha * pk;
+        s_out[g] = sk;
+        p[g] = pk;
+        d[g] = dn;
+        r_out[g] = r1[0];
+        w_out[g] = w1[0];
+        acc[0] += (double)r1[0] * (double)r1[0];
+        acc[1] += (double)w1[0] * (double)r1[0];
+    }
+}
+
 // One conjugate-gradient iteration in the single-reduction (Chronopoulos-Gear) form: with
 // r_k, w_k = A r_k, rho_k = r_k.r_k, mu_k = w_k.r_k (published by the previous kernel) and
 // alpha_{k-1}, rho_{k-1} (hist):
@@ -475,11 +574,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
     float* __restrict__ d, const float* __restrict__ x_in, float* __restrict__ x_out,
     Partials rm, const double* __restrict__ hist_prev, double* __restrict__ hist_cur,
     double* __restrict__ part) {
-    __shared__ TileSmem sm;
+    __shared__ TileSmem<RS> sm;
     __shared__ double sred[2 * kThreads / 64];
-    __shared__ double bc;
-    const double rho = consume(rm.p, rm.n, &bc);
-    const double mu = consume(rm.p + kMaxRedBlocks, rm.n, &bc);
+    __shared__ double bc[2];
+    const int nt = ntiles(H, W);
+    int r0 = 0, c0 = 0;
+    CgIn<RS> f;
+    if constexpr (RS > 0) {
+        if (!last && (int)blockIdx.x < nt) {
+            tile_origin(xcd_tile(blockIdx.x, nt), W, r0, c0);
+            cg_fetch<RS>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
+        }
+    }
+    double rho, mu;
+    consume2(rm.p, kMaxRedBlocks, rm.n, bc, rho, mu);
     double alpha_d, beta_d;
     cg_scalars(k, rho, mu, k ? hist_prev[0] : 0.0, k ? hist_prev[1] : 0.0, alpha_d, beta_d);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -488,14 +596,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
     }
     const float alpha = (float)alpha_d, beta = (float)beta_d;
     double acc[2] = {0.0, 0.0};
-    for (int t = blockIdx.x; t < ntiles(H, W); t += gridDim.x) {
-        int r0, c0;
-        tile_origin(t, W, r0, c0);
-        if (last)
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
+        if (last) {
             cg_last_tile(H, W, r0, c0, k, alpha, beta, r_in, p, d, x_in, x_out);
-        else
+        } else if constexpr (RS > 0) {
+            if (t != (int)blockIdx.x) cg_fetch<RS>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
+            cg_iter_fetched<RS>(op, H, W, r0, c0, k, alpha, beta, f, r_out, w_out, s_out, p, d,
+                                sm, acc);
+        } else {
             cg_iter_tile<RS>(op, H, W, r0, c0, k, alpha, beta, r_in, w_in, s_in, r_out, w_out,
                              s_out, p, d, sm, acc);
+        }
     }
     if (last) return;
     block_sum<2>(acc, sred);
@@ -504,24 +616,27 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
 
 // ---- batched kernels: one workgroup per tile of the batch tile list ----------------------
 
-// The image of this workgroup's tile and the tile's origin; null for an inactive image.
-__device__ inline const ImgDesc* batch_tile(const ImgDesc* desc, const int* tile_img, int& r0,
-                                            int& c0) {
-    const ImgDesc* d = desc + tile_img[blockIdx.x];
+// This workgroup's list entry: its image, the tile's origin, and bt, the index its per-tile
+// partials are published at; null for an inactive image.
+__device__ inline const ImgDesc* batch_tile(const ImgDesc* desc, const TileRef* tiles, int& bt,
+                                            int& r0, int& c0) {
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc* d = desc + e.img;
     if (!d->active) return nullptr;
-    const int t = blockIdx.x - d->tile0, ntx = (d->W + TW - 1) / TW;
+    const int t = e.t, ntx = (d->W + TW - 1) / TW;
+    bt = d->tile0 + t;
     r0 = (t / ntx) * TH;
     c0 = (t % ntx) * TW;
     return d;
 }
 
 __global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __restrict__ desc,
-                                                               const int* __restrict__ tile_img,
+                                                               const TileRef* __restrict__ tiles,
                                                                const float* __restrict__ sres,
                                                                float* __restrict__ r) {
     __shared__ InitFpSmem sm;
-    int r0, c0;
-    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    int bt, r0, c0;
+    const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
     init_fp_tile(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr, r + d->off, d->H, d->W, r0,
                  c0, sm);
@@ -529,72 +644,83 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __
 
 template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_w0_batch(const ImgDesc* __restrict__ desc,
-                                                          const int* __restrict__ tile_img,
+                                                          const TileRef* __restrict__ tiles,
                                                           const float* __restrict__ r,
                                                           float* __restrict__ w,
                                                           double* __restrict__ part, int cap) {
-    __shared__ TileSmem sm;
+    __shared__ TileSmem<RS> sm;
     __shared__ double sred[2 * kThreads / 64];
-    int r0, c0;
-    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    int bt, r0, c0;
+    const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
     double acc[2] = {0.0, 0.0};
     w0_tile<RS>(d->op, r + d->off, w + d->off, d->H, d->W, r0, c0, sm, acc);
     block_sum<2>(acc, sred);
-    publish<2>(acc, part, cap, blockIdx.x);
+    publish<2>(acc, part, cap, bt);
 }
 
 // Per-image CG scalars: sums the image's tile partials in tile order (deterministic and
-// independent of the other images of the batch), then alpha_k, beta_k.
-__global__ __launch_bounds__(64) void k_cg_fin_batch(const ImgDesc* __restrict__ desc, int k,
-                                                     const double* __restrict__ part, int cap,
-                                                     CgImg* __restrict__ cg) {
+// independent of the other images of the batch; rho on wave 0, mu on wave 1), then alpha_k,
+// beta_k.
+__global__ __launch_bounds__(128) void k_cg_fin_batch(const ImgDesc* __restrict__ desc, int k,
+                                                      const double* __restrict__ part, int cap,
+                                                      CgImg* __restrict__ cg) {
+    __shared__ double sums[2];
     const ImgDesc& d = desc[blockIdx.x];
     if (!d.active) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = threadIdx.x; i < d.ntiles; i += 64) {
-        s0 += part[d.tile0 + i];
-        s1 += part[(size_t)cap + d.tile0 + i];
-    }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
+    const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const double* pv = part + (size_t)v * cap + d.tile0;
+    double s = 0.0;
+    for (int i = lane; i < d.ntiles; i += 64) s += pv[i];
+    s = wave_sum(s);
+    if (lane == 0) sums[v] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
         CgImg c = cg[blockIdx.x];
         double alpha, beta;
-        cg_scalars(k, s0, s1, c.alpha_prev, c.rho_prev, alpha, beta);
+        cg_scalars(k, sums[0], sums[1], c.alpha_prev, c.rho_prev, alpha, beta);
         c.alpha = alpha;
         c.beta = beta;
         c.alpha_prev = alpha;
-        c.rho_prev = s0;
+        c.rho_prev = sums[0];
         cg[blockIdx.x] = c;
     }
 }
 
 template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
-    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img, int k, int last,
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles, int k, int last,
     const CgImg* __restrict__ cg, const float* __restrict__ r_in, const float* __restrict__ w_in,
     const float* __restrict__ s_in, float* __restrict__ r_out, float* __restrict__ w_out,
     float* __restrict__ s_out, float* __restrict__ p, float* __restrict__ dd,
     double* __restrict__ part, int cap) {
-    __shared__ TileSmem sm;
+    __shared__ TileSmem<RS> sm;
     __shared__ double sred[2 * kThreads / 64];
-    int r0, c0;
-    const ImgDesc* d = batch_tile(desc, tile_img, r0, c0);
+    int bt, r0, c0;
+    const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
-    const CgImg c = cg[d - desc];
-    const float alpha = (float)c.alpha, beta = (float)c.beta;
     const size_t o = d->off;
     if (last) {
-        cg_last_tile(d->H, d->W, r0, c0, k, alpha, beta, r_in + o, p + o, dd + o, d->x_in,
-                     d->x_out);
+        const CgImg c = cg[d - desc];
+        cg_last_tile(d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, r_in + o, p + o,
+                     dd + o, d->x_in, d->x_out);
         return;
     }
     double acc[2] = {0.0, 0.0};
-    cg_iter_tile<RS>(d->op, d->H, d->W, r0, c0, k, alpha, beta, r_in + o, w_in + o, s_in + o,
-                     r_out + o, w_out + o, s_out + o, p + o, dd + o, sm, acc);
+    if constexpr (RS > 0) {
+        CgIn<RS> f;
+        cg_fetch<RS>(d->H, d->W, r0, c0, k, r_in + o, w_in + o, s_in + o, p + o, dd + o, f);
+        const CgImg c = cg[d - desc];
+        cg_iter_fetched<RS>(d->op, d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, f,
+                            r_out + o, w_out + o, s_out + o, p + o, dd + o, sm, acc);
+    } else {
+        const CgImg c = cg[d - desc];
+        cg_iter_tile<RS>(d->op, d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, r_in + o,
+                         w_in + o, s_in + o, r_out + o, w_out + o, s_out + o, p + o, dd + o, sm,
+                         acc);
+    }
     block_sum<2>(acc, sred);
-    publish<2>(acc, part, cap, blockIdx.x);
+    publish<2>(acc, part, cap, bt);
 }
 
 inline int tile_blocks(int H, int W) {
@@ -682,38 +808,38 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
     return Partials{part, g};
 }
 
-void launch_cg_init_fp_batch(const ImgDesc* desc, const int* tile_img, int ntiles,
+void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
                              const float* sres, float* r, hipStream_t st) {
-    k_cg_init_fp_batch<<<ntiles, kThreads, 0, st>>>(desc, tile_img, sres, r);
+    k_cg_init_fp_batch<<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
 }
 
-void launch_cg_w0_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs,
+void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                         const float* r, float* w, double* part, int cap, hipStream_t st) {
     if (rs == 4)
-        k_cg_w0_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+        k_cg_w0_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tiles, r, w, part, cap);
     else if (rs == 3)
-        k_cg_w0_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+        k_cg_w0_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tiles, r, w, part, cap);
     else
-        k_cg_w0_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tile_img, r, w, part, cap);
+        k_cg_w0_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, r, w, part, cap);
 }
 
 void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
                          CgImg* cg, hipStream_t st) {
-    k_cg_fin_batch<<<nimg, 64, 0, st>>>(desc, k, part, cap, cg);
+    k_cg_fin_batch<<<nimg, 128, 0, st>>>(desc, k, part, cap, cg);
 }
 
-void launch_cg_iter_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int rs, int k,
+void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs, int k,
                           int last, const CgImg* cg, const float* r_in, const float* w_in,
                           const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
                           float* d, double* part, int cap, hipStream_t st) {
     if (rs == 4)
-        k_cg_iter_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+        k_cg_iter_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tiles, k, last, cg, r_in, w_in,
                                                         s_in, r_out, w_out, s_out, p, d, part, cap);
     else if (rs == 3)
-        k_cg_iter_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+        k_cg_iter_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tiles, k, last, cg, r_in, w_in,
                                                         s_in, r_out, w_out, s_out, p, d, part, cap);
     else
-        k_cg_iter_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tile_img, k, last, cg, r_in, w_in,
+        k_cg_iter_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, k, last, cg, r_in, w_in,
                                                         s_in, r_out, w_out, s_out, p, d, part, cap);
 }
 

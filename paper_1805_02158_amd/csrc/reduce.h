@@ -65,4 +65,27 @@ __device__ inline double consume(const double* part, int n, double* bcast /* one
     return r;
 }
 
+// Totals of two partial arrays (part[i] and part[stride + i]) in one pass: the same sums, in
+// the same order, as two calls of consume, with one memory latency instead of two.
+__device__ inline void consume2(const double* part, int stride, int n, double* bcast /* two */,
+                                double& a, double& b) {
+    if (threadIdx.x < 64) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = threadIdx.x; i < n; i += 64) {
+            s0 += part[i];
+            s1 += part[stride + i];
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        if (threadIdx.x == 0) {
+            bcast[0] = s0;
+            bcast[1] = s1;
+        }
+    }
+    __syncthreads();
+    a = bcast[0];
+    b = bcast[1];
+    __syncthreads();
+}
+
 }  // namespace redve

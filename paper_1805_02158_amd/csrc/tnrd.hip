@@ -228,7 +228,8 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
     float theta, int out_mode) {
-    stage_tile<KC>(w, f, out, H, W, blockIdx.y * TH, blockIdx.x * TW, filt, rbfw, F, rc, theta,
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    stage_tile<KC>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, filt, rbfw, F, rc, theta,
                    out_mode);
 }
 
@@ -236,14 +237,14 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
 // base_v + desc[i].off; w_base null means w = 0 (first stage).
 template <int KC>
 __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_batch(
-    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img,
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
     const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
     float theta, int out_mode) {
-    const int img = tile_img[blockIdx.x];
-    const ImgDesc& d = desc[img];
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc& d = desc[e.img];
     if (!d.active) return;
-    const int t = blockIdx.x - d.tile0, ntx = (d.W + TW - 1) / TW;
+    const int t = e.t, ntx = (d.W + TW - 1) / TW;
     stage_tile<KC>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H, d.W,
                    (t / ntx) * TH, (t % ntx) * TW, filt, rbfw, F, rc, theta, out_mode);
 }
@@ -288,7 +289,7 @@ void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float
                                                       d.theta[t], out_mode);
 }
 
-void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const int* tile_img,
+void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
                              int ntiles, const float* w_prev, float* out, int out_mode,
                              hipStream_t st) {
     const RbfConst rc = rbf_const(d);
@@ -296,10 +297,10 @@ void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
     if (rc.K == 7)
-        k_tnrd_stage_f32_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, kf,
+        k_tnrd_stage_f32_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
                                                                wf, d.nfilt, rc, d.theta[t], out_mode);
     else
-        k_tnrd_stage_f32_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, kf,
+        k_tnrd_stage_f32_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
                                                                wf, d.nfilt, rc, d.theta[t], out_mode);
 }
 

@@ -213,20 +213,21 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
     const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
-    stage_tile_bf16<KC>(w, f, out, H, W, blockIdx.y * TH, blockIdx.x * TW, bfwd, badj, rbfw, F,
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    stage_tile_bf16<KC>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, bfwd, badj, rbfw, F,
                         rc, theta, out_mode);
 }
 
 template <int KC>
 __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16_batch(
-    const ImgDesc* __restrict__ desc, const int* __restrict__ tile_img,
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
     const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
     const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
-    const int img = tile_img[blockIdx.x];
-    const ImgDesc& d = desc[img];
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc& d = desc[e.img];
     if (!d.active) return;
-    const int t = blockIdx.x - d.tile0, ntx = (d.W + TW - 1) / TW;
+    const int t = e.t, ntx = (d.W + TW - 1) / TW;
     stage_tile_bf16<KC>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H,
                         d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta,
                         out_mode);
@@ -272,7 +273,7 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
 }
 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
-                                  const int* tile_img, int ntiles, const float* w_prev, float* out,
+                                  const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st) {
     const RbfC rc = rbf_c(d);
     const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
@@ -280,11 +281,11 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
     if (rc.K == 7)
-        k_tnrd_stage_bf16_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, bf,
+        k_tnrd_stage_bf16_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, bf,
                                                                 ba, wf, d.nfilt, rc, d.theta[t],
                                                                 out_mode);
     else
-        k_tnrd_stage_bf16_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tile_img, w_prev, out, bf,
+        k_tnrd_stage_bf16_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, bf,
                                                                 ba, wf, d.nfilt, rc, d.theta[t],
                                                                 out_mode);
 }

@@ -48,6 +48,15 @@ __global__ __launch_bounds__(kThreads) void k_diff_gram(const float* __restrict_
 
 constexpr int MAXL = 16;  // REDVE_MAX_L
 
+// Work area of the one-thread L x L solver, in LDS (private arrays indexed at run time would
+// live in scratch memory).
+struct SolveWork {
+    double R[MAXL][MAXL];
+    double A[MAXL][MAXL], V[MAXL][MAXL];  // SVD-MPE
+    double t0[MAXL], t1[MAXL], t2[MAXL];  // vectors of the triangular solves
+    double gamma[MAXL];
+};
+
 __device__ void back_sub(const double (*R)[MAXL], int k, const double* b, double* x) {
     for (int i = k - 1; i >= 0; --i) {
         double s = b[i];
@@ -73,9 +82,10 @@ __device__ bool full_rank(const double (*R)[MAXL], int k, double eps) {
 }
 
 // MPE (Algorithm 1, step 2): R_{k-1} c' = -r_{k+1}, c = (c', 1), gamma = c / sum(c).
-__device__ bool mpe(const double (*R)[MAXL], int k, double eps, double* gamma) {
+__device__ bool mpe(const double (*R)[MAXL], int k, double eps, double* gamma, SolveWork& ws) {
     if (!full_rank(R, k, eps)) return false;
-    double c[MAXL], rhs[MAXL];
+    double* c = ws.t0;
+    double* rhs = ws.t1;
     for (int i = 0; i < k; ++i) rhs[i] = -R[i][k];
     back_sub(R, k, rhs, c);
     c[k] = 1.0;
@@ -91,10 +101,12 @@ __device__ bool mpe(const double (*R)[MAXL], int k, double eps, double* gamma) {
 
 // RRE (eq. (19)): R^T R d = 1, gamma = d / sum(d). A dependent last column: MPE's null vector
 // attains ||U gamma|| = 0; if MPE does not exist either, RRE_k = RRE_{k-1} (Sec. III-B).
-__device__ int rre(const double (*R)[MAXL], int k, double eps, double* gamma) {
+__device__ int rre(const double (*R)[MAXL], int k, double eps, double* gamma, SolveWork& ws) {
     while (true) {
         if (full_rank(R, k + 1, eps)) {
-            double ones[MAXL], w[MAXL], d[MAXL];
+            double* ones = ws.t0;
+            double* w = ws.t1;
+            double* d = ws.t2;
             for (int i = 0; i <= k; ++i) ones[i] = 1.0;
             fwd_sub_t(R, k + 1, ones, w);
             back_sub(R, k + 1, w, d);
@@ -107,16 +119,17 @@ __device__ int rre(const double (*R)[MAXL], int k, double eps, double* gamma) {
             gamma[0] = 1.0;
             return 0;
         }
-        if (mpe(R, k, eps, gamma)) return k;
+        if (mpe(R, k, eps, gamma, ws)) return k;
         --k;
     }
 }
 
 // SVD-MPE (Sec. III-B): gamma = v / sum(v), v the right singular vector of the smallest
 // singular value of R, by one-sided Jacobi rotations on the columns of R.
-__device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma) {
+__device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma, SolveWork& ws) {
     const int n = k + 1;
-    double A[MAXL][MAXL], V[MAXL][MAXL];
+    double(*A)[MAXL] = ws.A;
+    double(*V)[MAXL] = ws.V;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             A[i][j] = (j >= i) ? R[i][j] : 0.0;
@@ -171,10 +184,10 @@ __device__ bool svd_mpe(const double (*R)[MAXL], int k, double* gamma) {
 // The L x L work of Algorithm 1 on one thread: Cholesky of the Gram matrix (= the R of
 // Algorithm 2), MPE / RRE / SVD-MPE coefficients, xi; writes gamma, xi, ncols, breakdown.
 __device__ void small_solve(const double* G, int ldG, int L, int method, double rank_eps,
-                            VeInfo* __restrict__ info) {
+                            VeInfo* __restrict__ info, SolveWork& ws) {
     // Cholesky G = R^T R (upper R). A column whose pivot falls under the rank threshold gets
     // R_ii = 0 and a zero row, as modified Gram-Schmidt gives a zero q_i for it.
-    double R[MAXL][MAXL];
+    double(*R)[MAXL] = ws.R;
     for (int i = 0; i < L; ++i)
         for (int j = 0; j < L; ++j) R[i][j] = 0.0;
     for (int i = 0; i < L; ++i) {
@@ -189,16 +202,16 @@ __device__ void small_solve(const double* G, int ldG, int L, int method, double 
             R[i][j] = rii > 0.0 ? s / rii : 0.0;
         }
     }
-    double gamma[MAXL];
+    double* gamma = ws.gamma;
     int k = L - 1;
     bool ok;
     if (method == 1) {
-        ok = mpe(R, k, rank_eps, gamma);
+        ok = mpe(R, k, rank_eps, gamma, ws);
     } else if (method == 2) {
-        k = rre(R, k, rank_eps, gamma);
+        k = rre(R, k, rank_eps, gamma, ws);
         ok = true;
     } else {
-        ok = svd_mpe(R, k, gamma);
+        ok = svd_mpe(R, k, gamma, ws);
     }
     for (int i = 0; i < MAXL; ++i) {
         info->xi[i] = 0.0;
@@ -229,28 +242,38 @@ __device__ void small_solve(const double* G, int ldG, int L, int method, double 
     info->gamma_l1 = l1;
 }
 
-// Sums the window's published partials into the Gram matrix (fixed order, FP64), then the
-// L x L work on one thread.
-__global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part, size_t win_stride,
-                                                 int nblk, int L, int method, double rank_eps,
-                                                 VeInfo* __restrict__ info) {
+// Sums the window's published partials into the Gram matrix (fixed order, FP64; one wave per
+// entry, 16 waves), then the L x L work on one thread.
+constexpr int kSolveThreads = 1024;
+
+__global__ __launch_bounds__(kSolveThreads) void k_ve_solve(const double* __restrict__ part,
+                                                            size_t win_stride, int nblk, int L,
+                                                            int method, double rank_eps,
+                                                            VeInfo* __restrict__ info) {
     __shared__ double G[MAXL * MAXL];
     __shared__ double norms[2];
+    __shared__ SolveWork ws;
     // column j's pass published values k < j (u_j . u_k), j (u_j . u_j), j + 1 (x . x)
-    for (int j = 0; j < L; ++j) {
-        const double* pj = part + (size_t)j * win_stride;
-        for (int k = 0; k <= j + 1; ++k) {
-            double s = 0.0;
-            for (int i = threadIdx.x; i < nblk; i += 64) s += pj[(size_t)k * kMaxRedBlocks + i];
-            s = wave_sum(s);
-            if (threadIdx.x == 0) {
-                if (k <= j) {
-                    G[j * MAXL + k] = s;
-                    G[k * MAXL + j] = s;
-                } else if (j == L - 1) {
-                    norms[1] = s;
-                }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int npairs = L * (L + 3) / 2;  // sum over j of (j + 2)
+    for (int q = wave; q < npairs; q += kSolveThreads / 64) {
+        int j = 0, base = 0;
+        while (base + j + 2 <= q) {
+            base += j + 2;
+            ++j;
+        }
+        const int k = q - base;
+        const double* pj = part + (size_t)j * win_stride + (size_t)k * kMaxRedBlocks;
+        double s = 0.0;
+        for (int i = lane; i < nblk; i += 64) s += pj[i];
+        s = wave_sum(s);
+        if (lane == 0) {
+            if (k <= j) {
+                G[j * MAXL + k] = s;
+                G[k * MAXL + j] = s;
                 if (k == j && j == L - 1) norms[0] = s;
+            } else if (j == L - 1) {
+                norms[1] = s;
             }
         }
     }
@@ -258,7 +281,7 @@ __global__ __launch_bounds__(64) void k_ve_solve(const double* __restrict__ part
     if (threadIdx.x != 0) return;
     info->uu = norms[0];
     info->xx = norms[1];
-    small_solve(G, MAXL, L, method, rank_eps, info);
+    small_solve(G, MAXL, L, method, rank_eps, info, ws);
 }
 
 // Algorithm 1, step 4: x_(m,kappa) = x_m + U_{kappa-1} xi (= x_m + Q_{kappa-1} eta).
@@ -296,15 +319,16 @@ __global__ __launch_bounds__(64) void k_delta(const double* __restrict__ part, i
 // products with window columns 0..wj, ||u||^2, ||x_in||^2; NL + 2 per-tile partials.
 template <int NL>
 __global__ __launch_bounds__(kThreads) void k_diff_gram_batch(const ImgDesc* __restrict__ desc,
-                                                              const int* __restrict__ tile_img,
+                                                              const TileRef* __restrict__ tiles,
                                                               float* __restrict__ U,
                                                               size_t ustride,
                                                               double* __restrict__ part, int cap) {
     constexpr int NV = NL + 2;
     __shared__ double sred[NV * kThreads / 64];
-    const ImgDesc& d = desc[tile_img[blockIdx.x]];
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc& d = desc[e.img];
     if (!d.active) return;
-    const int t = blockIdx.x - d.tile0, ntx = (d.W + kBatchTile - 1) / kBatchTile;
+    const int t = e.t, ntx = (d.W + kBatchTile - 1) / kBatchTile, bt = d.tile0 + t;
     const int gr = (t / ntx) * kBatchTile + threadIdx.x / kBatchTile;
     const int gc = (t % ntx) * kBatchTile + threadIdx.x % kBatchTile;
     const int j = d.wj;
@@ -326,24 +350,26 @@ __global__ __launch_bounds__(kThreads) void k_diff_gram_batch(const ImgDesc* __r
         acc[NL + 1] = (double)xo * (double)xo;
     }
     block_sum<NV>(acc, sred);
-    publish<NV>(acc, part, cap, blockIdx.x);
+    publish<NV>(acc, part, cap, bt);
 }
 
-// Per image: sums the tile partials in tile order into Gram row wj and the norms.
-__global__ __launch_bounds__(64) void k_diff_fin_batch(const ImgDesc* __restrict__ desc, int L,
-                                                       const double* __restrict__ part, int cap,
-                                                       double* __restrict__ G,
-                                                       ImgStat* __restrict__ stat) {
+// Per image: sums the tile partials in tile order into Gram row wj and the norms (one wave
+// per value; each value summed in the same fixed order).
+__global__ __launch_bounds__(256) void k_diff_fin_batch(const ImgDesc* __restrict__ desc, int L,
+                                                        const double* __restrict__ part, int cap,
+                                                        double* __restrict__ G,
+                                                        ImgStat* __restrict__ stat) {
     const ImgDesc& d = desc[blockIdx.x];
     if (!d.active) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double* Gi = G + (size_t)blockIdx.x * MAXL * MAXL;
-    for (int v = 0; v < L + 2; ++v) {
+    for (int v = wave; v < L + 2; v += 4) {
         const bool gram = v < L && v <= d.wj;
         if (v < L && !gram) continue;
         double sum = 0.0;
-        for (int i = threadIdx.x; i < d.ntiles; i += 64) sum += part[(size_t)v * cap + d.tile0 + i];
+        for (int i = lane; i < d.ntiles; i += 64) sum += part[(size_t)v * cap + d.tile0 + i];
         sum = wave_sum(sum);
-        if (threadIdx.x == 0) {
+        if (lane == 0) {
             if (gram) {
                 Gi[d.wj * MAXL + v] = sum;
                 Gi[v * MAXL + d.wj] = sum;
@@ -362,24 +388,26 @@ __global__ __launch_bounds__(64) void k_ve_solve_batch(const ImgDesc* __restrict
                                                        const double* __restrict__ G,
                                                        VeInfo* __restrict__ info,
                                                        ImgStat* __restrict__ stat) {
+    __shared__ SolveWork ws;
     const ImgDesc& d = desc[blockIdx.x];
     if (!d.active || !d.do_ve || threadIdx.x != 0) return;
     VeInfo* in = info + blockIdx.x;
-    small_solve(G + (size_t)blockIdx.x * MAXL * MAXL, MAXL, L, method, rank_eps, in);
+    small_solve(G + (size_t)blockIdx.x * MAXL * MAXL, MAXL, L, method, rank_eps, in, ws);
     stat[blockIdx.x].gamma_l1 = in->gamma_l1;
     stat[blockIdx.x].breakdown = in->breakdown;
 }
 
 // x_m = x_m + U_{kappa-1} xi on one tile of an image that extrapolates this round.
 __global__ __launch_bounds__(kThreads) void k_ve_combine_batch(const ImgDesc* __restrict__ desc,
-                                                               const int* __restrict__ tile_img,
+                                                               const TileRef* __restrict__ tiles,
                                                                const float* __restrict__ U,
                                                                size_t ustride,
                                                                const VeInfo* __restrict__ info) {
-    const int img = tile_img[blockIdx.x];
+    const TileRef e = tiles[blockIdx.x];
+    const int img = e.img;
     const ImgDesc& d = desc[img];
     if (!d.active || !d.do_ve) return;
-    const int t = blockIdx.x - d.tile0, ntx = (d.W + kBatchTile - 1) / kBatchTile;
+    const int t = e.t, ntx = (d.W + kBatchTile - 1) / kBatchTile;
     const int gr = (t / ntx) * kBatchTile + threadIdx.x / kBatchTile;
     const int gc = (t % ntx) * kBatchTile + threadIdx.x % kBatchTile;
     if (gr >= d.H || gc >= d.W) return;
@@ -416,7 +444,7 @@ void launch_delta(const double* part, int nblk, VeInfo* info, hipStream_t st) {
 
 void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int method,
                      double rank_eps, VeInfo* info, hipStream_t st) {
-    k_ve_solve<<<1, 64, 0, st>>>(part, win_stride, nblk, L, method, rank_eps, info);
+    k_ve_solve<<<1, kSolveThreads, 0, st>>>(part, win_stride, nblk, L, method, rank_eps, info);
 }
 
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,
@@ -424,11 +452,11 @@ void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* in
     k_ve_combine<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(x_m, U, n, info, out);
 }
 
-void launch_diff_gram_batch(const ImgDesc* desc, const int* tile_img, int ntiles, int L, float* U,
+void launch_diff_gram_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int L, float* U,
                             size_t ustride, double* part, int cap, hipStream_t st) {
 #define REDVE_DGB(N)                                                                       \
     case N:                                                                                \
-        k_diff_gram_batch<N><<<ntiles, kThreads, 0, st>>>(desc, tile_img, U, ustride, part, cap); \
+        k_diff_gram_batch<N><<<ntiles, kThreads, 0, st>>>(desc, tiles, U, ustride, part, cap); \
         break;
     switch (L) {
         REDVE_DGB(1) REDVE_DGB(2) REDVE_DGB(3) REDVE_DGB(4) REDVE_DGB(5) REDVE_DGB(6) REDVE_DGB(7)
@@ -441,7 +469,7 @@ void launch_diff_gram_batch(const ImgDesc* desc, const int* tile_img, int ntiles
 
 void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* part, int cap,
                            double* G, ImgStat* stat, hipStream_t st) {
-    k_diff_fin_batch<<<nimg, 64, 0, st>>>(desc, L, part, cap, G, stat);
+    k_diff_fin_batch<<<nimg, 256, 0, st>>>(desc, L, part, cap, G, stat);
 }
 
 void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
@@ -449,9 +477,9 @@ void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, dou
     k_ve_solve_batch<<<nimg, 64, 0, st>>>(desc, L, method, rank_eps, G, info, stat);
 }
 
-void launch_ve_combine_batch(const ImgDesc* desc, const int* tile_img, int ntiles, const float* U,
+void launch_ve_combine_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, const float* U,
                              size_t ustride, const VeInfo* info, hipStream_t st) {
-    k_ve_combine_batch<<<ntiles, kThreads, 0, st>>>(desc, tile_img, U, ustride, info);
+    k_ve_combine_batch<<<ntiles, kThreads, 0, st>>>(desc, tiles, U, ustride, info);
 }
 
 }  // namespace redve
