@@ -8,7 +8,7 @@ TNRD-style denoiser (5 stages x 24 filters 5x5, 63-RBF influence functions), RRE
 
 Protocol (headline)
   1. target PSNR* = PSNR of the FP64 oracle's plain FP run to a relative change < 1e-6
-     (tests/golden/bench_target_c1.json, written by a script that calls only the oracle);
+     (tests/golden/bench_target_deblur256.json, written by a script that calls only the oracle);
   2. instrumented, untimed: solves with max_fp_calls = n = 1, 2, ... find n*, the FP-call
      count from which every returned vector stays within 0.05 dB of PSNR*;
   3. timed: `steps` solves with max_fp_calls = n* (after `warmup` untimed ones). A step is one
@@ -77,12 +77,12 @@ def main():
     import workload as W
     from paper_1805_02158_amd import Restorer
 
-    target = json.load(open(os.path.join(ROOT, "tests", "golden", "bench_target_c1.json")))
+    target = json.load(open(os.path.join(ROOT, "tests", "golden", "bench_target_deblur256.json")))
     psnr_star = target["psnr_star_db"]
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    prob = W.problem("c1")
+    prob = W.problem("deblur256")
     H, Wd = prob.hr_shape
     npx = H * Wd
     x_true = torch.tensor(prob.x_true, dtype=torch.float32, device=dev)

@@ -1,4 +1,4 @@
-"""Writes bench_target_c1.json: the oracle-converged PSNR of the 256x256 deblurring workload.
+"""Writes bench_target_deblur256.json: the oracle-converged PSNR of the 256x256 deblurring workload.
 
 Calls only the FP64 oracle and the seeded workload generator. The target is the PSNR of plain
 FP (eq. (7)) run until the relative change of consecutive iterates is below 1e-6 (cap 1000 FP
@@ -34,13 +34,13 @@ def stable_from(trace, target, band=BAND_DB):
 
 
 def main():
-    prob = W.problem("c1")
+    prob = W.problem("deblur256")
     op = oracle.OracleProblem(prob)
     t0 = time.time()
     ref = oracle.solve(op, "none", tol=1e-6, max_calls=1000)
     psnr_star = oracle.psnr(ref.x, prob.x_true)
     out = {
-        "workload": "c1: 256x256 synthetic image, uniform 9x9 blur, sigma sqrt(2), lambda 0.02, "
+        "workload": "deblur256: 256x256 synthetic image, uniform 9x9 blur, sigma sqrt(2), lambda 0.02, "
                     "15 CG iterations, seeded TNRD-style denoiser (5 stages x 24 filters)",
         "psnr_star_db": psnr_star,
         "psnr_input_db": oracle.psnr(op.y, prob.x_true),
@@ -54,7 +54,7 @@ def main():
                      on_vector=lambda c, v: tr.append((c, oracle.psnr(v, prob.x_true))))
         out[f"oracle_n_star_{method}"] = stable_from(tr, psnr_star)
     out["seconds"] = round(time.time() - t0, 1)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bench_target_c1.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bench_target_deblur256.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))

@@ -142,7 +142,7 @@ def test_denoiser_constant_and_identity(torch, orc):
 # ------------------------------------------------------------------ one FP call
 
 
-@pytest.mark.parametrize("name", ["tiny", "c0"])
+@pytest.mark.parametrize("name", ["tiny", "deblur64"])
 def test_fp_step(torch, orc, name):
     say("fp_step", name)
     prob = W.problem(name)
@@ -232,8 +232,8 @@ def _bound(orc, op, ref, method, L, m, calls):
     return max(1e-4, 3.0 * floor)
 
 
-@pytest.mark.parametrize("name,method,L,calls", [("c0", "none", 5, 20), ("c0", "rre", 5, 20),
-                                                 ("c0", "mpe", 5, 20), ("c0", "svd_mpe", 5, 20),
+@pytest.mark.parametrize("name,method,L,calls", [("deblur64", "none", 5, 20), ("deblur64", "rre", 5, 20),
+                                                 ("deblur64", "mpe", 5, 20), ("deblur64", "svd_mpe", 5, 20),
                                                  ("tiny", "rre", 3, 13), ("tiny", "mpe", 4, 7)])
 def test_solve_fixed_schedule(torch, orc, name, method, L, calls):
     say("solve", name, method, L, calls)
@@ -263,11 +263,11 @@ def test_solve_m_positive(torch, orc):
 
 
 @pytest.mark.parametrize("method", ["rre", "mpe"])
-def test_solve_c1_full_size(torch, orc, method):
+def test_solve_deblur256_full_size(torch, orc, method):
     """The benchmark workload (256x256, uniform 9x9, L = 5) at its launch configuration, at a
     fixed schedule of two cycles."""
-    say("solve c1", method)
-    prob = W.problem("c1")
+    say("solve deblur256", method)
+    prob = W.problem("deblur256")
     y32 = f32(orc.OracleProblem(prob).y)
     ref, op = _oracle_solve(orc, prob, y32, method, 5, 0, 0.0, 10)
     r = restorer(prob, method=method, tol=0.0, max_fp_calls=10)
@@ -312,8 +312,8 @@ def test_solve_identity_denoiser(torch, orc):
 def test_solve_converges_to_fixed_point(torch, orc):
     """Tolerance-driven RRE solve of the benchmark workload: the FP64 RED gradient at the GPU
     result has fallen by 1e3 and the result matches the oracle's fixed point."""
-    say("solve converged c1")
-    prob = W.problem("c1")
+    say("solve converged deblur256")
+    prob = W.problem("deblur256")
     op = orc.OracleProblem(prob)
     y32 = f32(op.y)
     op = orc.OracleProblem(prob, y=y32)
@@ -350,7 +350,7 @@ def test_solve_sr_converges(torch, orc):
 
 def test_solve_deterministic(torch):
     say("determinism")
-    prob = W.problem("c0")
+    prob = W.problem("deblur64")
     import oracle
     y32 = f32(oracle.OracleProblem(prob).y)
     r = restorer(prob, method="rre", tol=0.0, max_fp_calls=10)
@@ -434,7 +434,7 @@ def _converged_bf16(torch, orc, prob, method, L, tol=1e-5, calls=400):
 
 def test_solve_bf16_deblur(torch, orc):
     say("solve bf16 deblur 256")
-    err, dp = _converged_bf16(torch, orc, W.problem("c1"), "rre", 5)
+    err, dp = _converged_bf16(torch, orc, W.problem("deblur256"), "rre", 5)
     assert err <= 5e-3 and abs(dp) <= 0.05
 
 
@@ -442,5 +442,5 @@ def test_solve_bf16_sr_512(torch, orc):
     """The mixed-precision workload at full size: 512x512, Gaussian 7x7 + 3x decimation,
     sigma 5, RRE with L = 8, FP64 Gram and small solve."""
     say("solve bf16 sr 512")
-    err, dp = _converged_bf16(torch, orc, W.problem("c2"), "rre", 8, calls=300)
+    err, dp = _converged_bf16(torch, orc, W.problem("sr512"), "rre", 8, calls=300)
     assert err <= 5e-3 and abs(dp) <= 0.05

@@ -203,24 +203,24 @@ SQRT2 = math.sqrt(2.0)
 def problem(name: str) -> Problem:
     """Named workloads.
 
-    tiny   32x32 deblur, Gaussian 7x7 (CPU-test size)
-    c0     64x64, Gaussian 7x7 std 1.6, sigma sqrt(2), lambda 0.02, 10 CG, plain FP, 20 calls
-    c1     256x256, uniform 9x9, sigma sqrt(2), lambda 0.02, 15 CG, MPE/RRE L=5, tol 1e-5
-    c2     512x512, Gaussian 7x7 + 3x decimation, sigma 5, lambda 0.02, 15 CG, RRE L=8
+    tiny       32x32 deblur, Gaussian 7x7 (CPU-test size)
+    deblur64   64x64, Gaussian 7x7 std 1.6, sigma sqrt(2), lambda 0.02, 10 CG, plain FP, 20 calls
+    deblur256  256x256, uniform 9x9, sigma sqrt(2), lambda 0.02, 15 CG, MPE/RRE L=5, tol 1e-5
+    sr512      512x512, Gaussian 7x7 + 3x decimation, sigma 5, lambda 0.02, 15 CG, RRE L=8
     """
     d = make_denoiser()
     if name == "tiny":
         return Problem("tiny", make_image(32, 32, 1099), psf_gaussian(7, 1.6), 1, SQRT2, 0.02,
                        make_noise((32, 32), 2099), 10, d, "none", 5, 0, 0.0, 20)
-    if name == "c0":
-        return Problem("c0", make_image(64, 64, 1000), psf_gaussian(7, 1.6), 1, SQRT2, 0.02,
+    if name == "deblur64":
+        return Problem("deblur64", make_image(64, 64, 1000), psf_gaussian(7, 1.6), 1, SQRT2, 0.02,
                        make_noise((64, 64), 2000), 10, d, "none", 5, 0, 0.0, 20)
-    if name == "c1":
-        return Problem("c1", make_image(256, 256, 1001), psf_uniform(9), 1, SQRT2, 0.02,
+    if name == "deblur256":
+        return Problem("deblur256", make_image(256, 256, 1001), psf_uniform(9), 1, SQRT2, 0.02,
                        make_noise((256, 256), 2001), 15, d, "rre", 5, 0, 1e-5, 500)
-    if name == "c2":
+    if name == "sr512":
         x = make_image(512, 512, 1002)
-        return Problem("c2", x, psf_gaussian(7, 1.6), 3, 5.0, 0.02,
+        return Problem("sr512", x, psf_gaussian(7, 1.6), 3, 5.0, 0.02,
                        make_noise(lr_shape(512, 512, 3), 2002), 15, d, "rre", 8, 0, 1e-5, 500)
     raise KeyError(name)
 
