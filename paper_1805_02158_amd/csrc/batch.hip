@@ -409,7 +409,7 @@ struct Engine {
         }
         const int n = h->cg_iters;
         if (n > 0) {
-            launch_cg_init_fp_batch(d_desc, d_tile, nt, s_in, r(0), st);
+            launch_cg_init_fp_batch(d_desc, d_tile, nt, rs, s_in, r(0), st);
             launch_cg_w0_batch(d_desc, d_tile, nt, rs, r(0), w(0), d_part, cap_tiles, st);
             for (int k = 0; k < n; ++k) {
                 const int a = k & 1, b = a ^ 1;

@@ -10,6 +10,7 @@ namespace redve {
 constexpr int kThreads = 256;  // threads per workgroup of every tiled kernel (4 waves)
 constexpr int kMaxStages = 16; // denoiser stages
 constexpr int kMaxRbfWindow = 16;  // half-width (in centres) of the exact RBF window
+constexpr int kRbfPad = kMaxRbfWindow;  // zeros on both sides of each RBF weight row
 
 constexpr int kMaxRedBlocks = 1024;  // workgroups of any kernel that publishes partial sums
 constexpr int kMaxPsf = 15;
@@ -81,7 +82,7 @@ struct CgImg {
 };
 
 // Batched CG (see linear.hip). Partials are per tile (value v of tile T at part[v * cap + T]).
-void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
+void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                              const float* sres /* null: f = identity */, float* r, hipStream_t st);
 void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                         const float* r, float* w, double* part, int cap, hipStream_t st);
@@ -106,7 +107,7 @@ struct TnrdDev {
     int stages, nfilt, nrbf;
     float mu0, dmu, gamma;
     const float* filters;    // T*F*25
-    const float* rbf_w;      // T*F*J
+    const float* rbf_w;      // T*F rows of J + 2 kRbfPad: the weights, zero-padded both sides
     float theta[kMaxStages]; // reaction weights theta_t (kernel arguments)
     const uint16_t* frag_fwd;   // per stage: 2 x 64 lanes x 8 BF16 forward-bank MFMA operands
     const uint16_t* frag_adj;   // per stage: 2 x 64 lanes x 8 BF16 adjoint-bank MFMA operands

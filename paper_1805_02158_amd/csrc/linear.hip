@@ -257,17 +257,25 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const LinOp op, const floa
     }
 }
 
+// LDS of the FP64 residual start on one tile, sized for stencil radius RS (0: any radius up to
+// MAXR): the P region of x, e on the tile + r halo, row-pass results.
+template <int RS>
 struct InitFpSmem {
-    float sp[PH * PW];
-    double se[PH * PW];
-    double sh[PH * PW];
+    static constexpr int S = RS ? TW + 4 * RS : PW;
+    static constexpr int RP = RS ? TH + 4 * RS : PH;
+    static constexpr int RT = RS ? TH + 2 * RS : PH;
+    float sp[RP * S];
+    double se[RT * S];
+    double sh[RP * S];
 };
 
 // r = H^T (y - H x) / sigma^2 + lambda s on the tile at (r0, c0); FP64 sums.
+template <int RS>
 __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x,
                                     const float* __restrict__ y, const float* __restrict__ s,
                                     float* __restrict__ r, int H, int W, int r0, int c0,
-                                    InitFpSmem& sm) {
+                                    InitFpSmem<RS>& sm) {
+    constexpr int SW = InitFpSmem<RS>::S;
     float* sp = sm.sp;
     double* se = sm.se;
     double* sh = sm.sh;
@@ -277,16 +285,16 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
     const int wy = (W + dec - 1) / dec;
     for (int e = threadIdx.x; e < ph * pw; e += kThreads) {
         const int pr = e / pw, pc = e % pw;
-        sp[pr * PW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
+        sp[pr * SW + pc] = x[(size_t)wrapi(r0 - 2 * rh + pr, H) * W + wrapi(c0 - 2 * rw + pc, W)];
     }
     __syncthreads();
     if (op.separable) {
         for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
             const int pr = e / bw, bc = e % bw;
-            const float* prow = sp + pr * PW + bc + 2 * rw;
+            const float* prow = sp + pr * SW + bc + 2 * rw;
             double a = 0.0;
             for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * (double)prow[-b];
-            sh[pr * PW + bc] = a;
+            sh[pr * SW + bc] = a;
         }
         __syncthreads();
     }
@@ -298,27 +306,27 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
         if (gr % dec == 0 && gc % dec == 0) {
             double bx = 0.0;
             if (op.separable) {
-                const double* hcol = sh + (br + 2 * rh) * PW + bc;
-                for (int a = 0; a < op.kh; ++a) bx += op.col_d[a] * hcol[-a * PW];
+                const double* hcol = sh + (br + 2 * rh) * SW + bc;
+                for (int a = 0; a < op.kh; ++a) bx += op.col_d[a] * hcol[-a * SW];
             } else {
                 for (int a = -rh; a <= rh; ++a) {
-                    const float* prow = sp + (br + rh - a) * PW + bc + rw;
+                    const float* prow = sp + (br + rh - a) * SW + bc + rw;
                     const double* krow = op.psf64 + (a + rh) * op.kw + rw;
                     for (int b = -rw; b <= rw; ++b) bx += krow[b] * (double)prow[-b];
                 }
             }
             v = (double)y[(size_t)(gr / dec) * wy + gc / dec] - bx;
         }
-        se[br * PW + bc] = v;
+        se[br * SW + bc] = v;
     }
     __syncthreads();
     if (op.separable) {
         for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
             const int br = e / TW, tc = e % TW;
-            const double* erow = se + br * PW + tc;
+            const double* erow = se + br * SW + tc;
             double a = 0.0;
             for (int b = 0; b < op.kw; ++b) a += op.row_d[b] * erow[b];
-            sh[br * PW + tc] = a;
+            sh[br * SW + tc] = a;
         }
         __syncthreads();
     }
@@ -329,11 +337,11 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
         const int gr = r0 + tr, gc = c0 + tc;
         double bt = 0.0;
         if (op.separable) {
-            const double* hcol = sh + tr * PW + tc;
-            for (int a = 0; a < op.kh; ++a) bt += op.col_d[a] * hcol[a * PW];
+            const double* hcol = sh + tr * SW + tc;
+            for (int a = 0; a < op.kh; ++a) bt += op.col_d[a] * hcol[a * SW];
         } else {
             for (int a = -rh; a <= rh; ++a) {
-                const double* erow = se + (tr + a + rh) * PW + tc + rw;
+                const double* erow = se + (tr + a + rh) * SW + tc + rw;
                 const double* krow = op.psf64 + (a + rh) * op.kw + rw;
                 for (int b = -rw; b <= rw; ++b) bt += krow[b] * erow[b];
             }
@@ -353,16 +361,17 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
 // both terms small near the fixed point; the data term is accumulated in FP64 from the FP32
 // image, so r carries no rounding of the O(|x|) quantities rhs and A x. s = f(x) - x (null:
 // the identity denoiser, s = 0).
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const float* __restrict__ x,
                                                          const float* __restrict__ y,
                                                          const float* __restrict__ s,
                                                          float* __restrict__ r, int H, int W) {
-    __shared__ InitFpSmem sm;
+    __shared__ InitFpSmem<RS> sm;
     const int nt = ntiles(H, W);
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
         tile_origin(xcd_tile(t, nt), W, r0, c0);
-        init_fp_tile(op, x, y, s, r, H, W, r0, c0, sm);
+        init_fp_tile<RS>(op, x, y, s, r, H, W, r0, c0, sm);
     }
 }
 
@@ -630,16 +639,17 @@ __device__ inline const ImgDesc* batch_tile(const ImgDesc* desc, const TileRef* 
     return d;
 }
 
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __restrict__ desc,
                                                                const TileRef* __restrict__ tiles,
                                                                const float* __restrict__ sres,
                                                                float* __restrict__ r) {
-    __shared__ InitFpSmem sm;
+    __shared__ InitFpSmem<RS> sm;
     int bt, r0, c0;
     const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
-    init_fp_tile(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr, r + d->off, d->H, d->W, r0,
-                 c0, sm);
+    init_fp_tile<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr, r + d->off, d->H, d->W,
+                     r0, c0, sm);
 }
 
 template <int RS>
@@ -659,30 +669,41 @@ __global__ __launch_bounds__(kThreads) void k_cg_w0_batch(const ImgDesc* __restr
     publish<2>(acc, part, cap, bt);
 }
 
-// Per-image CG scalars: sums the image's tile partials in tile order (deterministic and
-// independent of the other images of the batch; rho on wave 0, mu on wave 1), then alpha_k,
+// Per-image CG scalars: sums the image's tile partials (rho on threads 0..255, mu on 256..511;
+// each thread four independent chains, so the loads of a chain overlap; the summation order
+// depends only on the image's tile count, hence on nothing else in the batch), then alpha_k,
 // beta_k.
-__global__ __launch_bounds__(128) void k_cg_fin_batch(const ImgDesc* __restrict__ desc, int k,
+__global__ __launch_bounds__(512) void k_cg_fin_batch(const ImgDesc* __restrict__ desc, int k,
                                                       const double* __restrict__ part, int cap,
                                                       CgImg* __restrict__ cg) {
-    __shared__ double sums[2];
+    __shared__ double sums[8];
     const ImgDesc& d = desc[blockIdx.x];
     if (!d.active) return;
-    const int lane = threadIdx.x & 63, v = threadIdx.x >> 6;
+    const int v = threadIdx.x >> 8, tid = threadIdx.x & 255;
     const double* pv = part + (size_t)v * cap + d.tile0;
-    double s = 0.0;
-    for (int i = lane; i < d.ntiles; i += 64) s += pv[i];
-    s = wave_sum(s);
-    if (lane == 0) sums[v] = s;
+    const int n = d.ntiles;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = tid;
+    for (; i + 768 < n; i += 1024) {
+        a0 += pv[i];
+        a1 += pv[i + 256];
+        a2 += pv[i + 512];
+        a3 += pv[i + 768];
+    }
+    for (; i < n; i += 256) a0 += pv[i];
+    const double s = wave_sum((a0 + a1) + (a2 + a3));
+    if ((threadIdx.x & 63) == 0) sums[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
+        const double rho = (sums[0] + sums[1]) + (sums[2] + sums[3]);
+        const double mu = (sums[4] + sums[5]) + (sums[6] + sums[7]);
         CgImg c = cg[blockIdx.x];
         double alpha, beta;
-        cg_scalars(k, sums[0], sums[1], c.alpha_prev, c.rho_prev, alpha, beta);
+        cg_scalars(k, rho, mu, c.alpha_prev, c.rho_prev, alpha, beta);
         c.alpha = alpha;
         c.beta = beta;
         c.alpha_prev = alpha;
-        c.rho_prev = sums[0];
+        c.rho_prev = rho;
         cg[blockIdx.x] = c;
     }
 }
@@ -773,7 +794,14 @@ void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float*
 
 void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
                        int H, int W, hipStream_t st) {
-    k_cg_init_fp<<<tile_blocks(H, W), kThreads, 0, st>>>(op, x, y, s, r, H, W);
+    const int g = tile_blocks(H, W);
+    const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
+    if (rr == 4)
+        k_cg_init_fp<4><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
+    else if (rr == 3)
+        k_cg_init_fp<3><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
+    else
+        k_cg_init_fp<0><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
 }
 
 Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, double* part,
@@ -808,9 +836,14 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
     return Partials{part, g};
 }
 
-void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
+void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                              const float* sres, float* r, hipStream_t st) {
-    k_cg_init_fp_batch<<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
+    if (rs == 4)
+        k_cg_init_fp_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
+    else if (rs == 3)
+        k_cg_init_fp_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
+    else
+        k_cg_init_fp_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
 }
 
 void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
@@ -825,7 +858,7 @@ void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, i
 
 void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
                          CgImg* cg, hipStream_t st) {
-    k_cg_fin_batch<<<nimg, 128, 0, st>>>(desc, k, part, cap, cg);
+    k_cg_fin_batch<<<nimg, 512, 0, st>>>(desc, k, part, cap, cg);
 }
 
 void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs, int k,

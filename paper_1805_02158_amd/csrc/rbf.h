@@ -1,0 +1,93 @@
+// Influence function of the TNRD-style denoiser stage (Sec. IV names TNRD):
+//   phi(z) = sum_j w_j exp(-(z - mu_j)^2 / (2 gamma^2)),  mu_j = mu0 + j dmu,
+// evaluated exactly on the 2K+1 centres nearest z. With j0 the nearest centre, d0 = z - mu_j0,
+// c = log2(e) / (2 gamma^2), A = exp2(2 c dmu d0), B = exp2(-c dmu^2), the term of centre
+// j0 + k is w_{j0+k} G0 A^k B^(k^2), G0 = exp2(-c d0^2). Centres farther than K + 1/2
+// spacings add less than 1e-12 of a weight (K = 7 for gamma = dmu).
+//
+// Inside the centre range (|d0| <= dmu / 2): phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w_{j0+m-K} A^m
+// by Horner in A, c_k = B^(k^2) precomputed, the prefactor one exp2 (two exp2 and 2K FMA +
+// 2K+1 multiplies per evaluation). Every intermediate stays below 2^(7 c dmu^2) there. Outside
+// (z beyond the first or last centre) A^2K could overflow, so the terms are built by the
+// two-sided recurrence term(k+1) = term(k) R_k, R_{k+1} = R_k B^2, which stays bounded; past
+// the cut-off (K + 1/2) dmu every term is negligible and the result is 0.
+#pragma once
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace redve {
+
+struct RbfParams {
+    float mu0, dmu, inv_dmu, half_dmu;
+    float c;       // log2(e) / (2 gamma^2)
+    float two_cd;  // 2 c dmu
+    float kpre;    // K 2 c dmu: the A^-K factor of the prefactor
+    float b, b2;   // B and B^2 (recurrence)
+    float cutoff;  // (K + 1/2) dmu
+    float ck[kMaxRbfWindow + 1];  // B^(k^2), k = 0..K
+    int J, K;
+};
+
+inline RbfParams rbf_params(const TnrdDev& d) {
+    RbfParams p{};
+    p.mu0 = d.mu0;
+    p.dmu = d.dmu;
+    p.inv_dmu = 1.0f / d.dmu;
+    p.half_dmu = 0.5f * d.dmu;
+    const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
+    const double cd2 = c * (double)d.dmu * d.dmu;
+    p.c = (float)c;
+    p.two_cd = (float)(2.0 * c * d.dmu);
+    p.kpre = (float)(d.kwin * 2.0 * c * d.dmu);
+    p.b = (float)exp2(-cd2);
+    p.b2 = (float)exp2(-2.0 * cd2);
+    p.cutoff = (float)(d.kwin + 0.5) * d.dmu;
+    for (int k = 0; k <= kMaxRbfWindow; ++k) p.ck[k] = (float)exp2(-cd2 * k * k);
+    p.J = d.nrbf;
+    p.K = d.kwin;
+    return p;
+}
+
+// wrow: the function's weights with kRbfPad zeros on each side (the layout of
+// TnrdDev::rbf_w). KC > 0: compile-time window (= p.K); KC = 0: any K <= kMaxRbfWindow,
+// recurrence only.
+template <int KC>
+__device__ inline float phi_eval(float z, const float* wrow, const RbfParams& p) {
+    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
+    j0 = min(max(j0, 0), p.J - 1);
+    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
+    const float* wc = wrow + kRbfPad + j0;
+    if (KC > 0 && fabsf(d0r) <= p.half_dmu) {
+        const float a = __builtin_amdgcn_exp2f(p.two_cd * d0r);
+        const float pre = __builtin_amdgcn_exp2f(-(p.c * d0r + p.kpre) * d0r);
+        float poly = p.ck[KC] * wc[KC];
+#pragma unroll
+        for (int m = 2 * KC - 1; m >= 0; --m) {
+            const int k = m - KC;
+            poly = fmaf(poly, a, p.ck[k < 0 ? -k : k] * wc[k]);
+        }
+        return pre * poly;
+    }
+    const int K = KC > 0 ? KC : p.K;
+    const bool live = fabsf(d0r) <= p.cutoff;
+    const float d0 = live ? d0r : 0.f;
+    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
+    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
+    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
+    float acc = wc[0] * g0;
+    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
+#pragma unroll
+    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
+        if (KC == 0 && k > K) break;
+        gu *= ru;
+        ru *= p.b2;
+        gd *= rd;
+        rd *= p.b2;
+        acc += wc[k] * gu + wc[-k] * gd;
+    }
+    return acc;
+}
+
+}  // namespace redve

@@ -409,10 +409,14 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     h->kwin = p->stages > 0 ? std::max(1, (int)ceil(7.4338 * p->gamma / p->dmu - 0.5)) : 1;
     h->theta.assign(h->T, 0.f);
     if (h->T > 0) {
-        const size_t nf = (size_t)h->T * h->F * 25, nw = (size_t)h->T * h->F * h->J;
-        std::vector<float> f(nf), w(nw);
+        // weights as rows of J + 2 kRbfPad, zero-padded both sides (the stage kernels copy
+        // them to LDS as they are)
+        const size_t ws = (size_t)h->J + 2 * kRbfPad;
+        const size_t nf = (size_t)h->T * h->F * 25, nw = (size_t)h->T * h->F * ws;
+        std::vector<float> f(nf), w(nw, 0.f);
         for (size_t i = 0; i < nf; ++i) f[i] = (float)p->filters[i];
-        for (size_t i = 0; i < nw; ++i) w[i] = (float)p->rbf_w[i];
+        for (size_t r = 0; r < (size_t)h->T * h->F; ++r)
+            for (int j = 0; j < h->J; ++j) w[r * ws + kRbfPad + j] = (float)p->rbf_w[r * h->J + j];
         for (int t = 0; t < h->T; ++t) h->theta[t] = (float)p->react[t];
         // MFMA operand fragments (v_mfma_f32_16x16x32_bf16, B operand): lane l of half hf holds
         // column n = l % 16 + 16 hf and the K values 8 (l / 16) + j. Forward: K = tap, n = filter;

@@ -21,6 +21,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "rbf.h"
 
 namespace redve {
 
@@ -34,54 +35,13 @@ constexpr int SPR = (VW + NP - 1) / NP;    // strips per v row
 constexpr int OS = 4;                      // adjoint outputs per lane (a 1x4 strip)
 constexpr int NTHR = 512;                  // 8 waves: each takes every 8th filter
 constexpr int NWAVE = NTHR / 64;
-constexpr int WPAD = kMaxRbfWindow;        // zero padding on both sides of each weight row
+constexpr int WPAD = kRbfPad;  // zero padding on both sides of each weight row
 static_assert(VH * SPR <= 64, "forward strips must fit one wave");
 static_assert(TH * TW == 64 * OS, "adjoint strips must cover the tile with one wave");
 static_assert((SPR - 1) * NP + NP + 4 <= UW, "patch columns must stay inside the u region");
 
 // Half-sample symmetric mirror, valid for -2 <= i <= n+1 and n >= 2.
 __device__ inline int mirror(int i, int n) { return i < 0 ? -i - 1 : (i >= n ? 2 * n - i - 1 : i); }
-
-struct RbfConst {
-    float mu0, dmu, inv_dmu;
-    float c;       // log2(e) / (2 gamma^2): exp(-d^2/(2 gamma^2)) = exp2(-c d^2)
-    float two_cd;  // 2 c dmu
-    float b, b2;   // exp2(-c dmu^2), its square
-    float cutoff;  // |z - nearest centre| beyond which every term is negligible
-    int J, K;      // centres, window half-width
-};
-
-// phi(z) = sum_j w_j exp2(-c (z - mu_j)^2), summed over j0-K .. j0+K (j0 the nearest centre).
-// With d0 = z - mu_{j0}: term(j0+k) = G0 A^k B^(k^2), G0 = exp2(-c d0^2), A = exp2(2 c dmu d0),
-// B = exp2(-c dmu^2), so term(k+1) = term(k) * R_k with R_{k+1} = R_k B^2 (and the same with
-// A^-1 downwards). wrow points at the (zero-padded) weights of this function. Beyond the
-// cut-off (z more than K + 1/2 spacings outside the centre range) every term is below 1e-12
-// of a weight and the result is 0; d0 is clamped there so no factor overflows.
-template <int KC>
-__device__ inline float phi_window(float z, const float* wrow, const RbfConst& p) {
-    const int K = KC > 0 ? KC : p.K;
-    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
-    j0 = min(max(j0, 0), p.J - 1);
-    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
-    const bool live = fabsf(d0r) <= p.cutoff;
-    const float d0 = live ? d0r : 0.f;
-    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
-    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
-    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
-    const float* wc = wrow + WPAD + j0;
-    float acc = wc[0] * g0;
-    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
-#pragma unroll
-    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
-        if (KC == 0 && k > K) break;
-        gu *= ru;
-        ru *= p.b2;
-        gd *= rd;
-        rd *= p.b2;
-        acc += wc[k] * gu + wc[-k] * gd;
-    }
-    return acc;
-}
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -93,13 +53,15 @@ template <int KC>
 __device__ inline void stage_tile(const float* __restrict__ w, const float* __restrict__ f,
                                   float* __restrict__ out, int H, int W, int r0, int c0,
                                   const float* __restrict__ filt, const float* __restrict__ rbfw,
-                                  int F, const RbfConst& rc, float theta, int out_mode) {
+                                  int F, const RbfParams& rc, float theta, int out_mode) {
     extern __shared__ float smem[];
-    float* su = smem;                  // UH * UW
+    // The weight rows come first, so a lane's window of weights is within the immediate
+    // offsets of one LDS address.
+    const int wstride = rc.J + 2 * WPAD;
+    float* sw = smem;                  // F * (J + 2 WPAD)
+    float* su = sw + F * wstride;      // UH * UW
     float* sg = su + UH * UW;          // NWAVE * TH * TW (partial g)
     float* sv = sg + NWAVE * TH * TW;  // NWAVE * VH * VW
-    float* sw = sv + NWAVE * VH * VW;  // F * (J + 2 WPAD)
-    const int wstride = rc.J + 2 * WPAD;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
@@ -111,10 +73,7 @@ __device__ inline void stage_tile(const float* __restrict__ w, const float* __re
         }
         su[e] = val;
     }
-    for (int e = threadIdx.x; e < F * wstride; e += NTHR) {
-        const int i = e / wstride, j = e % wstride - WPAD;
-        sw[e] = (j >= 0 && j < rc.J) ? rbfw[i * rc.J + j] : 0.f;
-    }
+    for (int e = threadIdx.x; e < F * wstride; e += NTHR) sw[e] = rbfw[e];  // padded rows
     __syncthreads();
 
     // forward strip of this lane: v row fr, columns fc .. fc+NP-1
@@ -156,7 +115,7 @@ __device__ inline void stage_tile(const float* __restrict__ w, const float* __re
             for (int a = 0; a < 5; ++a)
 #pragma unroll
                 for (int b = 0; b < 5; ++b) z += kf[a * 5 + b] * patch[a][p + b];
-            const float v = fin[p] ? phi_window<KC>(z, wrow, rc) : 0.f;
+            const float v = fin[p] ? phi_eval<KC>(z, wrow, rc) : 0.f;
             if (fwd_lane && fc + p < VW) my_v[fr * VW + fc + p] = v;
         }
         wave_sync();
@@ -226,7 +185,7 @@ __device__ inline void stage_tile(const float* __restrict__ w, const float* __re
 template <int KC>
 __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
-    int W, const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
+    int W, const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfParams rc,
     float theta, int out_mode) {
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     stage_tile<KC>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, filt, rbfw, F, rc, theta,
@@ -239,7 +198,7 @@ template <int KC>
 __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
-    const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfConst rc,
+    const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfParams rc,
     float theta, int out_mode) {
     const TileRef e = tiles[blockIdx.x];
     const ImgDesc& d = desc[e.img];
@@ -258,29 +217,14 @@ size_t tnrd_smem_bytes(int F, int J) {
                             (size_t)F * (J + 2 * WPAD));
 }
 
-static RbfConst rbf_const(const TnrdDev& d) {
-    RbfConst rc;
-    rc.mu0 = d.mu0;
-    rc.dmu = d.dmu;
-    rc.inv_dmu = 1.0f / d.dmu;
-    const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
-    rc.c = (float)c;
-    rc.two_cd = (float)(2.0 * c * d.dmu);
-    rc.b = (float)exp2(-c * (double)d.dmu * d.dmu);
-    rc.b2 = (float)exp2(-2.0 * c * (double)d.dmu * d.dmu);
-    rc.J = d.nrbf;
-    rc.K = d.kwin;
-    rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
-    return rc;
-}
 
 void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    const RbfConst rc = rbf_const(d);
+    const RbfParams rc = rbf_params(d);
     const size_t smem = tnrd_smem_bytes(d.nfilt, d.nrbf);
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
         k_tnrd_stage_f32<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
                                                       d.theta[t], out_mode);
@@ -292,10 +236,10 @@ void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float
 void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
                              int ntiles, const float* w_prev, float* out, int out_mode,
                              hipStream_t st) {
-    const RbfConst rc = rbf_const(d);
+    const RbfParams rc = rbf_params(d);
     const size_t smem = tnrd_smem_bytes(d.nfilt, d.nrbf);
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
         k_tnrd_stage_f32_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
                                                                wf, d.nfilt, rc, d.theta[t], out_mode);

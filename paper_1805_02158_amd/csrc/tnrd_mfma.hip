@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "rbf.h"
 
 namespace redve {
 
@@ -32,40 +33,10 @@ constexpr int NPOS = VH * VW;            // 400 = 25 groups of 16
 constexpr int NGRP = NPOS / 16;
 constexpr int NTHR = 512;
 constexpr int NWAVE = NTHR / 64;
-constexpr int WPAD = kMaxRbfWindow;
+constexpr int WPAD = kRbfPad;
 static_assert(NPOS % 16 == 0, "positions must fill MFMA groups");
 
 __device__ inline int mirror(int i, int n) { return i < 0 ? -i - 1 : (i >= n ? 2 * n - i - 1 : i); }
-
-struct RbfC {
-    float mu0, dmu, inv_dmu, c, two_cd, b, b2, cutoff;
-    int J, K;
-};
-
-template <int KC>
-__device__ inline float phi_win(float z, const float* wrow, const RbfC& p) {
-    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
-    j0 = min(max(j0, 0), p.J - 1);
-    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
-    const bool live = fabsf(d0r) <= p.cutoff;
-    const float d0 = live ? d0r : 0.f;
-    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
-    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
-    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
-    const float* wc = wrow + WPAD + j0;
-    float acc = wc[0] * g0;
-    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
-#pragma unroll
-    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
-        if (KC == 0 && k > p.K) break;
-        gu *= ru;
-        ru *= p.b2;
-        gd *= rd;
-        rd *= p.b2;
-        acc += wc[k] * gu + wc[-k] * gd;
-    }
-    return acc;
-}
 
 __device__ inline bf16x8 load_frag(const uint16_t* p) {
     // eight packed BF16 values (16 bytes, aligned)
@@ -80,17 +51,19 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
                                        float* __restrict__ out, int H, int W, int r0, int c0,
                                        const uint16_t* __restrict__ bfwd,
                                        const uint16_t* __restrict__ badj,
-                                       const float* __restrict__ rbfw, int F, const RbfC& rc,
+                                       const float* __restrict__ rbfw, int F, const RbfParams& rc,
                                        float theta, int out_mode) {
     extern __shared__ float smem[];
     // One row per position holds z, then v = phi(z), then the 25 per-tap adjoint sums (a wave
     // overwrites the rows of its own MFMA group after loading them as an operand).
+    // The weight rows come first, so a lane's window of weights is within the immediate
+    // offsets of one LDS address.
     const int ZS = (F > 25 ? F : 25) | 1;
-    float* su = smem;                 // UH * UW
+    const int wstride = rc.J + 2 * WPAD;
+    float* sw = smem;                 // F * (J + 2 WPAD)
+    float* su = sw + F * wstride;     // UH * UW
     float* sz = su + UH * UW;         // NPOS * ZS
     float* ss = sz;
-    float* sw = sz + NPOS * ZS;       // F * (J + 2 WPAD)
-    const int wstride = rc.J + 2 * WPAD;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
@@ -102,10 +75,7 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         }
         su[e] = val;
     }
-    for (int e = threadIdx.x; e < F * wstride; e += NTHR) {
-        const int i = e / wstride, j = e % wstride - WPAD;
-        sw[e] = (j >= 0 && j < rc.J) ? rbfw[i * rc.J + j] : 0.f;
-    }
+    for (int e = threadIdx.x; e < F * wstride; e += NTHR) sw[e] = rbfw[e];  // padded rows
     __syncthreads();
 
     const int m = lane & 15, sl = lane >> 4;  // fragment row/column, K slice
@@ -137,13 +107,34 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         }
     }
     __syncthreads();
-    // ---- influence functions, dense over (position, filter) pairs, FP32
-    for (int e = threadIdx.x; e < NPOS * F; e += NTHR) {
-        const int q = e / F, i = e % F;
-        const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
-        float v = 0.f;
-        if (gr >= 0 && gr < H && gc >= 0 && gc < W) v = phi_win<KC>(sz[q * ZS + i], sw + i * wstride, rc);
-        sz[q * ZS + i] = v;
+    // ---- influence functions, dense over (filter, position) pairs, FP32. Consecutive lanes
+    // take consecutive positions of one filter: they gather weights from the same LDS row,
+    // mostly at the same or nearby centres (broadcast instead of bank conflicts), and read z
+    // at the odd stride ZS (conflict-free). The pair index advances by NTHR = NPOS + 112 per
+    // step, so the position, the row offsets and the filter are stepped, not divided out; in a
+    // tile whose positions are all inside the image no position is tested.
+    {
+        static_assert(NTHR > NPOS && NTHR < 2 * NPOS, "one filter wrap per step");
+        const bool inner = r0 >= 2 && c0 >= 2 && r0 + TH + 2 <= H && c0 + TW + 2 <= W;
+        int i = threadIdx.x / NPOS, q = threadIdx.x - i * NPOS;
+        int zoff = q * ZS + i, woff = i * wstride;
+        const int zstep = (NTHR - NPOS) * ZS + 1, zwrap = NPOS * ZS - 1;
+        for (int e = threadIdx.x; e < NPOS * F; e += NTHR) {
+            bool in = inner;
+            if (!inner) {
+                const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
+                in = gr >= 0 && gr < H && gc >= 0 && gc < W;
+            }
+            sz[zoff] = in ? phi_eval<KC>(sz[zoff], sw + woff, rc) : 0.f;
+            q += NTHR - NPOS;
+            zoff += zstep;
+            woff += wstride;
+            if (q >= NPOS) {
+                q -= NPOS;
+                zoff -= zwrap;
+                woff += wstride;
+            }
+        }
     }
     __syncthreads();
     // ---- adjoint bank: S = V Kf^T on MFMA
@@ -212,7 +203,7 @@ template <int KC>
 __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
-    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
     stage_tile_bf16<KC>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, bfwd, badj, rbfw, F,
                         rc, theta, out_mode);
@@ -223,7 +214,7 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
     const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
-    const float* __restrict__ rbfw, int F, RbfC rc, float theta, int out_mode) {
+    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
     const TileRef e = tiles[blockIdx.x];
     const ImgDesc& d = desc[e.img];
     if (!d.active) return;
@@ -240,30 +231,15 @@ size_t tnrd_bf16_smem_bytes(int F, int J) {
     return sizeof(float) * ((size_t)UH * UW + (size_t)NPOS * zs + (size_t)F * (J + 2 * WPAD));
 }
 
-static RbfC rbf_c(const TnrdDev& d) {
-    RbfC rc;
-    rc.mu0 = d.mu0;
-    rc.dmu = d.dmu;
-    rc.inv_dmu = 1.0f / d.dmu;
-    const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
-    rc.c = (float)c;
-    rc.two_cd = (float)(2.0 * c * d.dmu);
-    rc.b = (float)exp2(-c * (double)d.dmu * d.dmu);
-    rc.b2 = (float)exp2(-2.0 * c * (double)d.dmu * d.dmu);
-    rc.J = d.nrbf;
-    rc.K = d.kwin;
-    rc.cutoff = (float)(d.kwin + 0.5) * d.dmu;
-    return rc;
-}
 
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    const RbfC rc = rbf_c(d);
+    const RbfParams rc = rbf_params(d);
     const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
     const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
         k_tnrd_stage_bf16<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
                                                        rc, d.theta[t], out_mode);
@@ -275,11 +251,11 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                   const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st) {
-    const RbfC rc = rbf_c(d);
+    const RbfParams rc = rbf_params(d);
     const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
     const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * d.nrbf;
+    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
         k_tnrd_stage_bf16_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, bf,
                                                                 ba, wf, d.nfilt, rc, d.theta[t],

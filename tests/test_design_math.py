@@ -47,6 +47,54 @@ def test_rbf_window_recurrence_matches_full_sum(orc):
         assert np.abs(win - full).max() <= 1e-12 * np.abs(w).max()
 
 
+def _window_horner(z, w, mu0, dmu, gamma, K):
+    """The denoiser kernel's evaluation for z inside the centre range (|d0| <= dmu / 2), in
+    float64: phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w[j0+m-K] A^m by Horner in A, with
+    A = exp2(2 c dmu d0), c_k = exp2(-c dmu^2 k^2) and the prefactor G0 A^-K one exp2.
+    Outside the range the recurrence above is used."""
+    J = len(w)
+    c = math.log2(math.e) / (2 * gamma * gamma)
+    j0 = int(np.clip(np.rint((z - mu0) / dmu), 0, J - 1))
+    d0 = z - (mu0 + dmu * j0)
+    if abs(d0) > 0.5 * dmu:
+        return _window_recurrence(z, w, mu0, dmu, gamma, K)
+    wp = lambda j: w[j] if 0 <= j < J else 0.0  # noqa: E731
+    ck = [2.0 ** (-c * dmu * dmu * k * k) for k in range(K + 1)]
+    a = 2.0 ** (2 * c * dmu * d0)
+    pre = 2.0 ** (-c * d0 * d0 - K * 2 * c * dmu * d0)
+    poly = ck[K] * wp(j0 + K)
+    for m in range(2 * K - 1, -1, -1):
+        poly = poly * a + ck[abs(m - K)] * wp(j0 + m - K)
+    return pre * poly
+
+
+def test_rbf_window_horner_matches_full_sum(orc):
+    """The Horner arrangement of the same window reproduces the 63-term sum to 1e-12 of the
+    largest weight inside the centre range, and hands over to the recurrence beyond it."""
+    d = W.make_denoiser()
+    z = np.concatenate([np.linspace(-420, 420, 1201), [0.0, 5.0, -5.0, 4.999, 305.0, 315.0]])
+    K = 7
+    for t, i in [(0, 0), (1, 7), (3, 19), (4, 23)]:
+        w = d.rbf_w[t, i]
+        full = orc.phi(z, w, d.mu0, d.dmu, d.gamma)
+        hor = np.array([_window_horner(v, w, d.mu0, d.dmu, d.gamma, K) for v in z])
+        assert np.abs(hor - full).max() <= 1e-12 * np.abs(w).max()
+    # a mistake in the coefficient order (c_k paired with the wrong weight) is caught
+    w = d.rbf_w[2, 5]
+    bad = 0.0
+    for v in (3.0, 47.0, -118.0):
+        j0 = int(np.rint((v - d.mu0) / d.dmu))
+        d0 = v - (d.mu0 + d.dmu * j0)
+        c = math.log2(math.e) / (2 * d.gamma ** 2)
+        a = 2.0 ** (2 * c * d.dmu * d0)
+        pre = 2.0 ** (-c * d0 * d0 - K * 2 * c * d.dmu * d0)
+        poly = 0.0
+        for m in range(2 * K, -1, -1):
+            poly = poly * a + 2.0 ** (-c * d.dmu ** 2 * (m - K) ** 2) * w[j0 - (m - K)]
+        bad = max(bad, abs(pre * poly - orc.phi(np.array([v]), w, d.mu0, d.dmu, d.gamma)[0]))
+    assert bad > 1e-3 * np.abs(w).max()
+
+
 def test_correction_form_cg_equals_warm_start(orc):
     """CG on A d = rhs - A x0 from d = 0, then x0 + d, gives the warm-started CG iterate."""
     psf = W.psf_uniform(9)
