@@ -293,6 +293,36 @@ class OracleProblem:
         return apply_Ht(r, self.shape, self.psf, self.s) / self.sigma ** 2 + self.lam * (
             x - self.denoise(x))
 
+    def sd_step_size(self):
+        """Default fixed step of steepest descent (Sec. IV fixes it by hand): 1 / L with
+        L = ||H||^2 / sigma^2 + 2 lambda, a Lipschitz constant of grad E when the denoiser is
+        strongly passive (rho(grad f) <= 1, Sec. II-B); ||H|| <= sum |h|."""
+        nh = float(np.abs(self.psf).sum())
+        return 1.0 / (nh * nh / self.sigma ** 2 + 2.0 * self.lam)
+
+    def sd(self, x, mu):
+        """One steepest-descent step x - mu grad E(x) (the gradient of eq. (5)); one denoiser
+        call."""
+        self.calls += 1
+        return _f64(x) - mu * self.gradient(_f64(x))
+
+
+class SDMap:
+    """Steepest descent with a fixed step as the base iteration of Algorithm 3 (SD, and
+    SD-MPE / SD-RRE with extrapolation; Sec. IV): fp(x) = x - mu grad E(x). Its fixed point is
+    the stationary point of E, the same x* as the FP map's."""
+
+    def __init__(self, op: OracleProblem, mu=None):
+        self.op = op
+        self.mu = op.sd_step_size() if mu is None else float(mu)
+        self.shape = op.shape
+
+    def x0(self):
+        return self.op.x0()
+
+    def fp(self, x):
+        return self.op.sd(x, self.mu)
+
 
 # ---------------------------------------------------------------------------------------
 # Vector extrapolation (Sec. III-B)

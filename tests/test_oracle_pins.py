@@ -502,3 +502,45 @@ def test_identity_denoiser_gives_least_squares(orc):
     assert np.linalg.norm(r.x - xs) <= 1e-10 * np.linalg.norm(xs)
     r2 = orc.solve(op, "rre", L=6, m=0, tol=0.0, max_calls=30)
     assert np.linalg.norm(r2.x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------------ steepest descent (Sec. IV)
+
+
+def test_sd_map_fixes_the_fp_fixed_point(orc, small_solution):
+    """The SD step x - mu g(x) with g of eq. (5) leaves the FP fixed point in place (g(x*) = 0,
+    eq. (6)): FP and SD share x*."""
+    op, res = small_solution
+    x = res["rre"].x
+    sd = orc.SDMap(op)
+    assert np.linalg.norm(sd.fp(x) - x) <= 1e-6 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("method", ["mpe", "rre"])
+def test_sd_ve_reaches_the_fp_fixed_point(orc, small_solution, method):
+    """SD-MPE / SD-RRE (Algorithm 3 with the SD step as the base iteration, kappa = 8, i.e.
+    L = 9 difference columns; Sec. IV) converge to the same x* as FP, in a few hundred calls
+    (plain SD needs thousands on this problem)."""
+    op, res = small_solution
+    ref = res["none"].x
+    r = orc.solve(orc.SDMap(op), method, L=9, m=0, tol=1e-10, max_calls=400)
+    assert r.calls < 400
+    assert np.linalg.norm(r.x - ref) <= 1e-7 * np.linalg.norm(ref)
+
+
+def test_sd_identity_denoiser_gives_least_squares(orc):
+    """With D = identity, SD with the default step 1/L, L = ||H||^2/sigma^2 + 2 lambda, is
+    gradient descent on ||Hx - y||^2 / (2 sigma^2): it converges to the least-squares solution
+    of a dense 8x8 problem (|h_hat| >= 0.2, rate 1 - mu 0.04 / sigma^2 = 0.96 per call). A step
+    of the wrong sign, or beyond 2 / L, diverges instead."""
+    psf = np.full((3, 3), 0.05)
+    psf[1, 1] = 0.6
+    P = W.Problem("ls", RNG.uniform(0, 255, (8, 8)), psf, 1, 1.0, 0.02,
+                  RNG.standard_normal((8, 8)), 64, W.identity_denoiser())
+    op = orc.OracleProblem(P)
+    Hd = _dense(lambda p: orc.blur(p, op.psf), (8, 8))
+    xs = np.linalg.solve(Hd.T @ Hd, Hd.T @ op.y.ravel()).reshape(8, 8)
+    sd = orc.SDMap(op)
+    assert abs(sd.mu - 1.0 / (1.0 + 0.04)) < 1e-15
+    r = orc.solve(sd, "none", tol=0.0, max_calls=800)
+    assert np.linalg.norm(r.x - xs) <= 1e-9 * np.linalg.norm(xs)
