@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sd", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
@@ -208,6 +209,8 @@ def main():
         "roofline_2048x2048": {"k_tnrd_stage_bf16": roof_big, "k_tnrd_stage_f32": roof32_big,
                                "k_cg_iter<4>": roof_cg_big},
     }
+    if not args.no_sd:
+        res["steepest_descent"] = bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star)
     if not args.no_batch:
         res["batched"] = bench_batch(args, torch, np, W, Restorer, psnr)
     if not args.no_serve:
@@ -330,6 +333,64 @@ def roofline_stage(npx, stage_us, kernel):
             "traffic": traffic_of(kernel, npx), "avg_launch_us": stage_us,
             "flop_per_launch": work,
             "flop_per_px": STAGE_FLOP_PER_PX, "pixels_per_launch": npx}
+
+
+def bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star, nmax=2000, nmax_ve=300):
+    """Steepest descent as the base iteration (x - mu g(x), default mu; Sec. IV), plain and
+    with MPE (kappa = 8, L = 9) at the headline workload, BF16 banks: FP-call count n* to the
+    same target band, and the timed solve of n* calls."""
+    H, Wd = prob.hr_shape
+    npx = H * Wd
+    R.set_denoiser(prob.denoiser, "bf16")
+    R.set_base("sd", 0.0)
+    res = {"workload": "deblur 256x256 as the headline, steepest descent with the default step "
+                       "1 / (||H||^2/sigma^2 + 2 lambda), BF16 banks"}
+
+    def band_start(trace):
+        ns = None
+        for n, p in trace:
+            if abs(p - psnr_star) <= BAND_DB:
+                ns = n if ns is None else ns
+            else:
+                ns = None
+        return ns
+
+    # plain SD: one step at a time (every iterate is a returned vector)
+    x = y.clone()
+    trace = []
+    for n in range(1, nmax + 1):
+        x = R.fp_step(y, x)
+        trace.append((n, psnr(x)))
+    ns_sd = band_start(trace)
+    # SD-MPE: solves of n calls
+    trace = []
+    for n in range(1, nmax_ve + 1):
+        R.set_extrapolation("mpe", 9, 0)
+        R.set_solver(prob.cg_iters, n, 0.0, 0)
+        R.solve(y, H, Wd, out=out)
+        trace.append((n, psnr(out)))
+    ns_ve = band_start(trace)
+
+    def timed(method, L, calls, steps=10):
+        R.set_extrapolation(method, L, 0)
+        R.set_solver(prob.cg_iters, calls, 0.0, 0)
+        R.solve(y, H, Wd, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            R.solve(y, H, Wd, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        return {"fp_calls_to_target": calls, "mpix_s": npx / dt / 1e6, "ms_per_solve": dt * 1e3,
+                "psnr_db": psnr(out)}
+
+    res["plain_sd"] = timed("none", 5, ns_sd) if ns_sd else {"fp_calls_to_target": None,
+                                                              "searched_up_to": nmax}
+    res["sd_mpe_L9"] = timed("mpe", 9, ns_ve) if ns_ve else {"fp_calls_to_target": None,
+                                                              "searched_up_to": nmax_ve}
+    R.set_base("fp", 0.0)
+    log("steepest descent", res)
+    return res
 
 
 def observe(torch, R, probs):

@@ -44,6 +44,7 @@ enum {
 
 enum { REDVE_VE_NONE = 0, REDVE_VE_MPE = 1, REDVE_VE_RRE = 2, REDVE_VE_SVD_MPE = 3 };
 enum { REDVE_PREC_FP32 = 0, REDVE_PREC_BF16 = 1 };
+enum { REDVE_BASE_FP = 0, REDVE_BASE_SD = 1 };
 
 /* Largest supported sizes. */
 #define REDVE_MAX_PSF 15     /* PSF side (odd, 1..15)                              */
@@ -116,6 +117,14 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m);
  * with extrapolation: for the last call of a cycle, Sec. III-C); extra_fp >= 0 FP calls
  * follow (Sec. III-C recommends some). Defaults: 15, 500, 1e-5, 0. */
 int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int extra_fp);
+/* Base iteration that Algorithm 3 accelerates (Sec. IV runs VE on the FP method and on
+ * steepest descent). REDVE_BASE_FP (default): the FP map of eq. (7). REDVE_BASE_SD:
+ * x_{k+1} = x_k - mu g(x_k), g = H^T (H x - y) / sigma^2 + lambda (x - f(x)) the gradient of
+ * eq. (5), one denoiser call and no CG per step; mu > 0 a fixed step (the paper fixes it by
+ * hand), mu <= 0 the default 1 / (||H||^2 / sigma^2 + 2 lambda) with ||H|| <= sum |h|
+ * (computed per image in batches). Everything else (extrapolation, stopping, statistics) is
+ * the same; "FP call" then counts SD steps. */
+int redve_set_base(redve_t h, int base, double mu);
 
 /* Solve: y (device, hy x wy) -> x (device, hx x wx), hy = ceil(hx/decim), wy = ceil(wx/decim).
  * x0 (device, hx x wx) is the initial vector, or NULL for the default (y when decim = 1,
@@ -137,8 +146,9 @@ int redve_apply_A(redve_t h, const float* p, int hx, int wx, float* out);
 int redve_cg(redve_t h, const float* rhs, float* x, int hx, int wx, int iters);
 /* out = f(x), the denoiser. out must not alias x. */
 int redve_denoise(redve_t h, const float* x, int hx, int wx, float* out);
-/* One FP call of eq. (7): out = CG_{cg_iters}(A, b0 + lambda f(x); start x), where
- * b0 = H^T y / sigma^2 is computed from y (ceil(hx/decim) x ceil(wx/decim)). out may not alias x. */
+/* One call of the base iteration: the FP map of eq. (7), out = CG_{cg_iters}(A, b0 + lambda
+ * f(x); start x) with b0 = H^T y / sigma^2 computed from y (ceil(hx/decim) x ceil(wx/decim)),
+ * or with REDVE_BASE_SD one steepest-descent step out = x - mu g(x). out may not alias x. */
 int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, float* out);
 /* One extrapolation (Algorithm 1 with the configured method) from the L+1 iterates
  * xs[0..L] (device, each hx x wx, stored consecutively): out = x_(0,kappa), or xs[L] if the

@@ -250,6 +250,9 @@ struct Engine {
         op.lambda = (float)it.lambda;
         op.inv_s2_d = is2;
         op.lambda_d = it.lambda;
+        double l1 = 0.0;
+        for (int k = 0; k < kh * kw; ++k) l1 += fabs(it.psf[k]);
+        op.sd_mu = sd_step(h->sd_mu, l1, it.sigma, it.lambda);
         int im = 0;
         for (int k = 1; k < kh * kw; ++k)
             if (fabs(it.psf[k]) > fabs(it.psf[im])) im = k;
@@ -408,7 +411,9 @@ struct Engine {
             s_in = sres();
         }
         const int n = h->cg_iters;
-        if (n > 0) {
+        if (h->base == REDVE_BASE_SD) {
+            launch_sd_step_batch(d_desc, d_tile, nt, rs, s_in, st);
+        } else if (n > 0) {
             launch_cg_init_fp_batch(d_desc, d_tile, nt, rs, s_in, r(0), st);
             launch_cg_w0_batch(d_desc, d_tile, nt, rs, r(0), w(0), d_part, cap_tiles, st);
             for (int k = 0; k < n; ++k) {
@@ -605,6 +610,10 @@ int check_settings(redve_t h) {
         h->err = "redve_set_denoiser was not called";
         return REDVE_E_STATE;
     }
+    if (h->base == REDVE_BASE_FP && h->cg_iters < 1) {
+        h->err = "the batched FP iteration needs cg_iters >= 1";
+        return REDVE_E_ARG;
+    }
     return REDVE_OK;
 }
 
@@ -781,6 +790,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     if (!out || !proto || max_active < 1 || max_active > 4096) return REDVE_E_ARG;
     *out = nullptr;
     if (!proto->have_den) return REDVE_E_STATE;
+    if (proto->base == REDVE_BASE_FP && proto->cg_iters < 1) return REDVE_E_ARG;
     auto s = std::make_unique<redve_server>();
     // copy the settings; device buffers of the denoiser are shared read-only with proto
     redve_ctx& c = s->ctx;
@@ -806,6 +816,8 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.extra_fp = proto->extra_fp;
     c.tol = proto->tol;
     c.rank_eps = proto->rank_eps;
+    c.base = proto->base;
+    c.sd_mu = proto->sd_mu;
     if (hipSetDevice(c.device) != hipSuccess) return REDVE_E_HIP;
     // non-blocking (see redve_solve_batch); inputs are ordered by an event per request
     if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return REDVE_E_HIP;

@@ -63,6 +63,9 @@ struct redve_ctx {
     int method = REDVE_VE_NONE, L = 5, m = 0;
     int cg_iters = 15, max_fp = 500, extra_fp = 0;
     double tol = 1e-5;
+    int base = REDVE_BASE_FP;  // base iteration of Algorithm 3
+    double sd_mu = 0.0;        // steepest-descent step (<= 0: 1 / (||H||^2/sigma^2 + 2 lambda))
+    double psf_l1 = 1.0;       // sum |h|, a bound on ||H||
     double rank_eps = 1e-7;  // R_jj <= rank_eps * R_00 counts as rank deficient (FP32 data)
     Workspace ws;
     HostMirror* host = nullptr;  // pinned

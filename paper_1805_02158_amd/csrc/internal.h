@@ -27,6 +27,7 @@ struct LinOp {
     float lambda;
     double inv_s2_d;   // the same in FP64 (residual accumulation)
     double lambda_d;
+    double sd_mu;      // step of the steepest-descent base iteration
     float row[kMaxPsf], col[kMaxPsf];
     double row_d[kMaxPsf], col_d[kMaxPsf];
 };
@@ -84,6 +85,10 @@ struct CgImg {
 // Batched CG (see linear.hip). Partials are per tile (value v of tile T at part[v * cap + T]).
 void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                              const float* sres /* null: f = identity */, float* r, hipStream_t st);
+// Steepest-descent step of every active image: x_out = x_in + mu (H^T (y - H x_in) / sigma^2
+// + lambda s), FP64 sums, mu = op.sd_mu.
+void launch_sd_step_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
+                          const float* sres, hipStream_t st);
 void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                         const float* r, float* w, double* part, int cap, hipStream_t st);
 void launch_cg_fin_batch(const ImgDesc* desc, int nimg, int k, const double* part, int cap,
@@ -132,6 +137,11 @@ struct Partials {
 void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, int H, int W,
                     hipStream_t st);
 // CG start of one FP call: r = H^T (y - H x) / sigma^2 + lambda s, s = f(x) - x (may be null).
+// Step of the steepest-descent base iteration (mu > 0: mu; else 1 / (psf_l1^2/sigma^2 + 2 lambda)).
+double sd_step(double mu, double psf_l1, double sigma, double lambda);
+// x_out = x + op.sd_mu (H^T (y - H x) / sigma^2 + lambda s): one steepest-descent step.
+void launch_sd_step(const LinOp& op, const float* x, const float* y, const float* s,
+                    float* x_out, int H, int W, hipStream_t st);
 void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
                        int H, int W, hipStream_t st);
 // w0 = A r0; publishes r0.r0 and w0.r0.

@@ -274,7 +274,7 @@ template <int RS>
 __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x,
                                     const float* __restrict__ y, const float* __restrict__ s,
                                     float* __restrict__ r, int H, int W, int r0, int c0,
-                                    InitFpSmem<RS>& sm) {
+                                    InitFpSmem<RS>& sm, float* __restrict__ xo = nullptr) {
     constexpr int SW = InitFpSmem<RS>::S;
     float* sp = sm.sp;
     double* se = sm.se;
@@ -350,7 +350,10 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
             const size_t g = (size_t)gr * W + gc;
             double rv = op.inv_s2_d * bt;
             if (s) rv += op.lambda_d * (double)s[g];
-            r[g] = (float)rv;
+            if (xo)  // steepest descent: x - mu g(x) = x + mu r, rounded once
+                xo[g] = (float)((double)sp[(tr + 2 * rh) * SW + tc + 2 * rw] + op.sd_mu * rv);
+            else
+                r[g] = (float)rv;
         }
     }
     __syncthreads();
@@ -365,13 +368,14 @@ template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const float* __restrict__ x,
                                                          const float* __restrict__ y,
                                                          const float* __restrict__ s,
-                                                         float* __restrict__ r, int H, int W) {
+                                                         float* __restrict__ r, int H, int W,
+                                                         float* __restrict__ xo) {
     __shared__ InitFpSmem<RS> sm;
     const int nt = ntiles(H, W);
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
         tile_origin(xcd_tile(t, nt), W, r0, c0);
-        init_fp_tile<RS>(op, x, y, s, r, H, W, r0, c0, sm);
+        init_fp_tile<RS>(op, x, y, s, r, H, W, r0, c0, sm, xo);
     }
 }
 
@@ -643,13 +647,13 @@ template <int RS>
 __global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __restrict__ desc,
                                                                const TileRef* __restrict__ tiles,
                                                                const float* __restrict__ sres,
-                                                               float* __restrict__ r) {
+                                                               float* __restrict__ r, int sd) {
     __shared__ InitFpSmem<RS> sm;
     int bt, r0, c0;
     const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
-    init_fp_tile<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr, r + d->off, d->H, d->W,
-                     r0, c0, sm);
+    init_fp_tile<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr,
+                     sd ? nullptr : r + d->off, d->H, d->W, r0, c0, sm, sd ? d->x_out : nullptr);
 }
 
 template <int RS>
@@ -792,16 +796,26 @@ void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float*
         k_cg_init<0><<<g, kThreads, 0, st>>>(op, x_in, rhs, r, H, W);
 }
 
-void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
-                       int H, int W, hipStream_t st) {
+static void init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
+                    float* xo, int H, int W, hipStream_t st) {
     const int g = tile_blocks(H, W);
     const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
     if (rr == 4)
-        k_cg_init_fp<4><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
+        k_cg_init_fp<4><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W, xo);
     else if (rr == 3)
-        k_cg_init_fp<3><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
+        k_cg_init_fp<3><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W, xo);
     else
-        k_cg_init_fp<0><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W);
+        k_cg_init_fp<0><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W, xo);
+}
+
+void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
+                       int H, int W, hipStream_t st) {
+    init_fp(op, x, y, s, r, nullptr, H, W, st);
+}
+
+void launch_sd_step(const LinOp& op, const float* x, const float* y, const float* s,
+                    float* x_out, int H, int W, hipStream_t st) {
+    init_fp(op, x, y, s, nullptr, x_out, H, W, st);
 }
 
 Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, double* part,
@@ -836,14 +850,24 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
     return Partials{part, g};
 }
 
+static void init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
+                          const float* sres, float* r, int sd, hipStream_t st) {
+    if (rs == 4)
+        k_cg_init_fp_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r, sd);
+    else if (rs == 3)
+        k_cg_init_fp_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r, sd);
+    else
+        k_cg_init_fp_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r, sd);
+}
+
 void launch_cg_init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
                              const float* sres, float* r, hipStream_t st) {
-    if (rs == 4)
-        k_cg_init_fp_batch<4><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
-    else if (rs == 3)
-        k_cg_init_fp_batch<3><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
-    else
-        k_cg_init_fp_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, sres, r);
+    init_fp_batch(desc, tiles, ntiles, rs, sres, r, 0, st);
+}
+
+void launch_sd_step_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,
+                          const float* sres, hipStream_t st) {
+    init_fp_batch(desc, tiles, ntiles, rs, sres, nullptr, 1, st);
 }
 
 void launch_cg_w0_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,

@@ -79,6 +79,18 @@ int ensure_workspace(redve_t h, int hx, int wx, int L) {
     return REDVE_OK;
 }
 
+}  // namespace
+
+// Step of the steepest-descent base iteration: mu if mu > 0, else 1 / L with
+// L = ||H||^2 / sigma^2 + 2 lambda (gradient Lipschitz bound for a strongly passive denoiser,
+// Sec. II-B), ||H|| <= psf_l1 = sum |h|.
+double redve::sd_step(double mu, double psf_l1, double sigma, double lambda) {
+    if (mu > 0) return mu;
+    return 1.0 / (psf_l1 * psf_l1 / (sigma * sigma) + 2.0 * lambda);
+}
+
+namespace {
+
 LinOp linop_of(redve_t h) {
     const double is2 = 1.0 / (h->sigma * h->sigma);
     LinOp op{};
@@ -92,6 +104,7 @@ LinOp linop_of(redve_t h) {
     op.lambda = (float)h->lambda;
     op.inv_s2_d = is2;
     op.lambda_d = h->lambda;
+    op.sd_mu = sd_step(h->sd_mu, h->psf_l1, h->sigma, h->lambda);
     for (int i = 0; i < h->kh; ++i) {
         op.col_d[i] = h->col[i];
         op.col[i] = (float)h->col[i];
@@ -212,6 +225,11 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
     bool s_null = false;
     int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null);
     if (rc) return rc;
+    if (h->base == REDVE_BASE_SD) {  // x - mu g(x): the same residual, no linear solve
+        launch_sd_step(linop_of(h), x_in, y, s_null ? nullptr : w.sres, x_out, H, W, h->stream);
+        LAUNCH_CHECK(h);
+        return REDVE_OK;
+    }
     if (h->cg_iters <= 0) {
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
@@ -327,6 +345,8 @@ int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) 
     h->kh = kh;
     h->kw = kw;
     h->decim = decim;
+    h->psf_l1 = 0.0;
+    for (int i = 0; i < kh * kw; ++i) h->psf_l1 += fabs(psf[i]);
     // rank-1 test: psf = col (x) row with col = the column through the largest tap and
     // row = that tap's row divided by it (exact for any rank-1 matrix)
     int im = 0;
@@ -461,6 +481,16 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m) {
     h->method = method;
     h->L = L;
     h->m = m;
+    return REDVE_OK;
+}
+
+int redve_set_base(redve_t h, int base, double mu) {
+    if (!h) return REDVE_E_ARG;
+    if (base != REDVE_BASE_FP && base != REDVE_BASE_SD) return fail(h, REDVE_E_ARG, "bad base");
+    if (!std::isfinite(mu)) return fail(h, REDVE_E_ARG, "mu must be finite");
+    if (base != h->base) ++h->gen;
+    h->base = base;
+    h->sd_mu = mu;
     return REDVE_OK;
 }
 
