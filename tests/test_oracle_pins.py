@@ -544,3 +544,36 @@ def test_sd_identity_denoiser_gives_least_squares(orc):
     assert abs(sd.mu - 1.0 / (1.0 + 0.04)) < 1e-15
     r = orc.solve(sd, "none", tol=0.0, max_calls=800)
     assert np.linalg.norm(r.x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------------ the objective (eq. (4))
+
+
+def test_objective_identity_denoiser_is_least_squares(orc):
+    """With D = identity the prior x^T (x - f(x)) vanishes and E(x) = ||Hx - y||^2 / (2 sigma^2),
+    computed here with a dense H; a central finite difference of E along a random direction
+    matches the gradient of eq. (5) (the data term's gradient H^T (Hx - y) / sigma^2)."""
+    psf = W.psf_gaussian(5, 1.0)
+    P = W.Problem("obj", RNG.uniform(0, 255, (8, 10)), psf, 1, 1.7, 0.02,
+                  RNG.standard_normal((8, 10)), 15, W.identity_denoiser())
+    op = orc.OracleProblem(P)
+    Hd = _dense(lambda p: orc.blur(p, op.psf), (8, 10))
+    x = RNG.uniform(0, 255, (8, 10))
+    r = Hd @ x.ravel() - op.y.ravel()
+    assert abs(op.objective(x) - r @ r / (2 * 1.7 ** 2)) <= 1e-12 * abs(op.objective(x))
+    v = RNG.standard_normal((8, 10))
+    fd = (op.objective(x + 1e-3 * v) - op.objective(x - 1e-3 * v)) / 2e-3
+    assert abs(fd - (op.gradient(x).ravel() @ v.ravel())) <= 1e-7 * abs(fd)
+
+
+def test_objective_prior_vanishes_on_constants(orc):
+    """D(c 1) = c 1 (zero-mean filters, odd phi), so the RED prior of a constant image is 0 and
+    E reduces to the data term; for a textured image the prior term is positive here."""
+    P = W.problem("tiny")
+    op = orc.OracleProblem(P)
+    c = np.full(P.hr_shape, 87.5)
+    r = orc.apply_H(c, op.psf, op.s) - op.y
+    assert abs(op.objective(c) - r.ravel() @ r.ravel() / (2 * op.sigma ** 2)) <= 1e-9 * op.objective(c)
+    x = op.x0()
+    prior = 0.5 * op.lam * (x.ravel() @ (x - op.denoise(x)).ravel())
+    assert prior > 0
