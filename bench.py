@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=160)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--cost-protocol", action="store_true",
+                    help="run only the cost-based comparison (FP calls VE needs to reach the cost "
+                         "of 200 FP calls, m in {0,5,10}, kappa in {3,5,10}) and print it")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="run only a calibration copy and the dominant kernels (for rocprofv3 "
                          "--pmc FETCH_SIZE / WRITE_SIZE runs), print nothing")
@@ -95,6 +98,9 @@ def main():
     torch.cuda.synchronize()
     if args.pmc_probe:
         pmc_probe(torch, R, prob, y)
+        return
+    if args.cost_protocol:
+        print(json.dumps(cost_protocol(torch, W, Restorer)), flush=True)
         return
 
     def psnr(x, ref=x_true):
@@ -391,6 +397,47 @@ def bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star, nmax=2000, nmax_
     R.set_base("fp", 0.0)
     log("steepest descent", res)
     return res
+
+
+def cost_protocol(torch, W, Restorer, fp_calls=200):
+    """The cost-based comparison of Sec. IV (Tables I-II): E* = E(x after fp_calls plain FP
+    calls), E of eq. (4); for MPE and RRE with m in {0, 5, 10} and kappa in {3, 5, 10}
+    (L = kappa + 1 difference columns), the smallest FP-call count at the end of a cycle whose
+    vector has E <= E* (None: not within fp_calls). Synthetic stand-ins for the paper's images:
+    the 256x256 deblurring and the 512x512 3x super-resolution workloads, FP32 banks."""
+    out = {"metric": "FP calls for extrapolation to reach the objective of 200 plain FP calls",
+           "fp_calls": fp_calls, "workloads": {}}
+    for name in ("deblur256", "sr512"):
+        prob = W.problem(name)
+        R = Restorer(0)
+        R.configure(prob, method="none", tol=0.0, max_fp_calls=fp_calls)
+        xt = torch.tensor(prob.x_true, dtype=torch.float32, device="cuda")
+        nz = torch.tensor(prob.noise, dtype=torch.float32, device="cuda")
+        y = R.apply_H(xt) + float(prob.sigma) * nz
+        H, Wd = prob.hr_shape
+        t0 = time.perf_counter()
+        x, _ = R.solve(y, H, Wd)
+        e_star = R.objective(y, x)
+        res = {"E_fp": e_star}
+        for method in ("mpe", "rre"):
+            table = {}
+            for m in (0, 5, 10):
+                for kappa in (3, 5, 10):
+                    L, cyc, hit = kappa + 1, m + kappa + 1, None
+                    R.set_extrapolation(method, L, m)
+                    for c in range(1, fp_calls // cyc + 1):
+                        R.set_solver(prob.cg_iters, c * cyc, 0.0, 0)
+                        xn, _ = R.solve(y, H, Wd)
+                        if R.objective(y, xn) <= e_star:
+                            hit = c * cyc
+                            break
+                    table[f"m{m}_k{kappa}"] = hit
+            res[method] = table
+        res["seconds"] = time.perf_counter() - t0
+        out["workloads"][name] = res
+        log("cost protocol", name, res)
+        R.close()
+    return out
 
 
 def observe(torch, R, probs):

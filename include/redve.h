@@ -150,6 +150,10 @@ int redve_denoise(redve_t h, const float* x, int hx, int wx, float* out);
  * f(x); start x) with b0 = H^T y / sigma^2 computed from y (ceil(hx/decim) x ceil(wx/decim)),
  * or with REDVE_BASE_SD one steepest-descent step out = x - mu g(x). out may not alias x. */
 int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, float* out);
+/* The RED objective of eq. (4) with the data term of eq. (1): *E (host) =
+ * ||Hx - y||^2 / (2 sigma^2) + (lambda / 2) x^T (x - f(x)), one denoiser call, FP64 sums of the
+ * FP32 images. y: ceil(hx/decim) x ceil(wx/decim), x: hx x wx (device). Synchronises. */
+int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, double* E);
 /* One extrapolation (Algorithm 1 with the configured method) from the L+1 iterates
  * xs[0..L] (device, each hx x wx, stored consecutively): out = x_(0,kappa), or xs[L] if the
  * extrapolation does not exist. gamma (host, L doubles, may be NULL) receives gamma_0..kappa

@@ -29,11 +29,10 @@ EXPORTS = (
     "redve_create", "redve_destroy", "redve_set_stream", "redve_last_error",
     "redve_workspace_bytes", "redve_set_operator", "redve_set_noise", "redve_set_lambda",
     "redve_set_denoiser", "redve_set_extrapolation", "redve_set_solver", "redve_set_base",
-    "redve_solve",
-    "redve_apply_H", "redve_apply_Ht", "redve_apply_A", "redve_cg", "redve_denoise",
-    "redve_fp_step", "redve_extrapolate", "redve_solve_batch", "redve_server_create",
-    "redve_server_submit", "redve_server_poll", "redve_server_wait", "redve_server_counts",
-    "redve_server_destroy",
+    "redve_solve", "redve_apply_H", "redve_apply_Ht", "redve_apply_A", "redve_cg",
+    "redve_denoise", "redve_fp_step", "redve_objective", "redve_extrapolate",
+    "redve_solve_batch", "redve_server_create", "redve_server_submit", "redve_server_poll",
+    "redve_server_wait", "redve_server_counts", "redve_server_destroy",
 )
 
 
@@ -102,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "redve_cg": ([vp, vp, vp, i, i, i], i),
         "redve_denoise": ([vp, vp, i, i, vp], i),
         "redve_fp_step": ([vp, vp, vp, i, i, vp], i),
+        "redve_objective": ([vp, vp, vp, i, i, dp], i),
         "redve_extrapolate": ([vp, vp, i, i, i, vp, dp, ctypes.POINTER(i)], i),
         "redve_solve_batch": ([vp, i, ctypes.POINTER(Item), ctypes.POINTER(Stats)], i),
         "redve_server_create": ([ctypes.POINTER(vp), vp, sz, i], i),
@@ -309,6 +309,14 @@ class Restorer:
         if rc != OK and not any(s["status"] for s in stats):
             self._check(rc)
         return [m[1] for m in made], stats
+
+    def objective(self, y, x):
+        """E(x) of eq. (4): ||Hx - y||^2 / (2 sigma^2) + (lambda/2) x^T (x - f(x))."""
+        hx, wx = x.shape
+        e = ctypes.c_double()
+        self._check(self._L.redve_objective(self._h, _dev(y, lr_shape(hx, wx, self.decim)),
+                                            _dev(x), hx, wx, ctypes.byref(e)))
+        return e.value
 
     def extrapolate(self, xs):
         """xs: (L+1, h, w) stacked iterates -> (x_new, gamma, breakdown)."""

@@ -28,6 +28,7 @@ struct Workspace {
 
 struct HostMirror {
     VeInfo info;
+    double obj[2];  // ||Hx - y||^2, x.(f(x) - x)
 };
 
 }  // namespace redve_detail

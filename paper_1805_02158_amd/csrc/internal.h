@@ -137,6 +137,9 @@ struct Partials {
 void launch_cg_init(const LinOp& op, const float* x_in, const float* rhs, float* r, int H, int W,
                     hipStream_t st);
 // CG start of one FP call: r = H^T (y - H x) / sigma^2 + lambda s, s = f(x) - x (may be null).
+// out[0] = ||Hx - y||^2, out[1] = x.s (device, FP64); part: 2 x kMaxRedBlocks doubles.
+void launch_objective(const LinOp& op, const float* x, const float* y, const float* s, int H,
+                      int W, double* part, double* out, hipStream_t st);
 // Step of the steepest-descent base iteration (mu > 0: mu; else 1 / (psf_l1^2/sigma^2 + 2 lambda)).
 double sd_step(double mu, double psf_l1, double sigma, double lambda);
 // x_out = x + op.sd_mu (H^T (y - H x) / sigma^2 + lambda s): one steepest-descent step.

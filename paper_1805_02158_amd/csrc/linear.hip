@@ -8,6 +8,8 @@
 // is applied as separate column and row passes (2 (kh + kw) taps per pixel instead of
 // 2 kh kw). Reducing kernels loop over tiles with at most kMaxRedBlocks workgroups, publish
 // one FP64 partial per workgroup, and the next kernel re-sums them (see reduce.h).
+#include <algorithm>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -627,6 +629,52 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
+// ---- the RED objective E(x) = ||Hx - y||^2 / (2 sigma^2) + (lambda/2) x^T (x - f(x)), eq. (4)
+
+// Per-workgroup FP64 partials of ||Hx - y||^2 (over the decimated grid; H x summed in FP64 from
+// the FP32 image) and of x.s (s = f(x) - x; null: the identity denoiser).
+__global__ __launch_bounds__(kThreads) void k_objective(const LinOp op, const float* __restrict__ x,
+                                                        const float* __restrict__ y,
+                                                        const float* __restrict__ s, int H,
+                                                        int W, double* __restrict__ part) {
+    __shared__ double sred[2 * kThreads / 64];
+    const int dec = op.decim, h = (H + dec - 1) / dec, w = (W + dec - 1) / dec;
+    const int rh = op.kh / 2, rw = op.kw / 2;
+    const int n = max(h * w, H * W), stride = gridDim.x * kThreads;
+    double acc[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        if (i < h * w) {
+            const int ii = i / w, jj = i % w;
+            double hx = 0.0;
+            for (int a = -rh; a <= rh; ++a) {
+                const float* row = x + (size_t)wrapi(dec * ii - a, H) * W;
+                for (int b = -rw; b <= rw; ++b)
+                    hx += op.psf64[(a + rh) * op.kw + b + rw] * (double)row[wrapi(dec * jj - b, W)];
+            }
+            const double rr = hx - (double)y[i];
+            acc[0] += rr * rr;
+        }
+        if (s && i < H * W) acc[1] += (double)x[i] * (double)s[i];
+    }
+    block_sum<2>(acc, sred);
+    publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_objective_fin(const double* __restrict__ part, int nblk,
+                                                      double* __restrict__ out) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 64) {
+        s0 += part[i];
+        s1 += part[kMaxRedBlocks + i];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+    }
+}
+
 // ---- batched kernels: one workgroup per tile of the batch tile list ----------------------
 
 // This workgroup's list entry: its image, the tile's origin, and bt, the index its per-tile
@@ -806,6 +854,14 @@ static void init_fp(const LinOp& op, const float* x, const float* y, const float
         k_cg_init_fp<3><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W, xo);
     else
         k_cg_init_fp<0><<<g, kThreads, 0, st>>>(op, x, y, s, r, H, W, xo);
+}
+
+void launch_objective(const LinOp& op, const float* x, const float* y, const float* s, int H,
+                      int W, double* part, double* out, hipStream_t st) {
+    const int h = (H + op.decim - 1) / op.decim, w = (W + op.decim - 1) / op.decim;
+    const int g = upd_blocks(std::max(h * w, H * W));
+    k_objective<<<g, kThreads, 0, st>>>(op, x, y, s, H, W, part);
+    k_objective_fin<<<1, 64, 0, st>>>(part, g, out);
 }
 
 void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,

@@ -555,6 +555,27 @@ int redve_cg(redve_t h, const float* rhs, float* x, int hx, int wx, int iters) {
     return run_cg(h, rhs, h->ws.xa, x, hx, wx, iters);
 }
 
+int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, double* E) {
+    if (!h) return REDVE_E_ARG;
+    if (!y || !x || !E) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc || (rc = check_ready(h, true))) return rc;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    Workspace& w = h->ws;
+    bool s_null = false;
+    if ((rc = run_denoiser(h, x, hx, wx, w.sres, true, &s_null))) return rc;
+    double* out = w.ve_part + 2 * kMaxRedBlocks;  // the window partials are free here
+    launch_objective(linop_of(h), x, y, s_null ? nullptr : w.sres, hx, wx, w.ve_part, out,
+                     h->stream);
+    LAUNCH_CHECK(h);
+    HIP_TRY(h, hipMemcpyAsync(h->host->obj, out, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *E = h->host->obj[0] / (2.0 * h->sigma * h->sigma) - 0.5 * h->lambda * h->host->obj[1];
+    return REDVE_OK;
+}
+
 int redve_denoise(redve_t h, const float* x, int hx, int wx, float* out) {
     if (!h) return REDVE_E_ARG;
     if (!x || !out || x == out) return fail(h, REDVE_E_ARG, "bad pointers");
