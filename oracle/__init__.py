@@ -307,6 +307,33 @@ class OracleProblem:
         return _f64(x) - mu * self.gradient(_f64(x))
 
 
+class ExactFPMap:
+    """The FP map of eq. (7) with the inverse applied exactly, for periodic deblurring (s = 1):
+    A = H^T H / sigma^2 + lambda I is diagonalised by the 2-D DFT (the footnote to eq. (7)), so
+    x_{k+1} = F^-1[ F(b0 + lambda f(x_k)) / (|h_hat|^2 / sigma^2 + lambda) ]. h_hat is the DFT of
+    the PSF placed with its centre at the origin (circular convolution, as `blur`)."""
+
+    def __init__(self, op: OracleProblem):
+        if op.s != 1:
+            raise ValueError("the exact Fourier solve needs s = 1 (deblurring)")
+        self.op, self.shape = op, op.shape
+        H, W = op.shape
+        kh, kw = op.psf.shape
+        h = np.zeros((H, W))
+        for a in range(kh):
+            for b in range(kw):
+                h[(a - kh // 2) % H, (b - kw // 2) % W] += op.psf[a, b]
+        self.den = np.abs(np.fft.fft2(h)) ** 2 / op.sigma ** 2 + op.lam
+
+    def x0(self):
+        return self.op.x0()
+
+    def fp(self, x):
+        self.op.calls += 1
+        rhs = self.op.b0 + self.op.lam * self.op.denoise(_f64(x))
+        return np.real(np.fft.ifft2(np.fft.fft2(rhs) / self.den))
+
+
 class SDMap:
     """Steepest descent with a fixed step as the base iteration of Algorithm 3 (SD, and
     SD-MPE / SD-RRE with extrapolation; Sec. IV): fp(x) = x - mu grad E(x). Its fixed point is

@@ -577,3 +577,29 @@ def test_objective_prior_vanishes_on_constants(orc):
     x = op.x0()
     prior = 0.5 * op.lam * (x.ravel() @ (x - op.denoise(x)).ravel())
     assert prior > 0
+
+
+# ------------------------------------------------------------------ exact linear step (footnote to eq. (7))
+
+
+def test_exact_fp_map_is_cg_to_convergence(orc):
+    """The Fourier-diagonal FP map equals the CG FP map with CG run to convergence (300
+    iterations on a 24x20 problem), for a non-symmetric PSF (the DFT convention of `blur`)."""
+    psf = np.random.default_rng(11).uniform(0, 1, (5, 3))
+    psf /= psf.sum()
+    P = W.Problem("ex", W.make_image(24, 20, 1020), psf, 1, W.SQRT2, 0.02,
+                  W.make_noise((24, 20), 2020), 300, W.make_denoiser())
+    op = orc.OracleProblem(P)
+    ex = orc.ExactFPMap(op)
+    x = op.x0()
+    for _ in range(3):
+        a, b = ex.fp(x), op.fp(x)
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+        x = a
+
+
+def test_exact_fp_shares_the_fixed_point(orc, small_solution):
+    """The exact-solve FP iteration (with RRE) converges to the same x* as truncated-CG FP."""
+    op, res = small_solution
+    r = orc.solve(orc.ExactFPMap(op), "rre", L=5, m=0, tol=1e-11, max_calls=200)
+    assert np.linalg.norm(r.x - res["none"].x) <= 1e-7 * np.linalg.norm(res["none"].x)
