@@ -45,6 +45,7 @@ enum {
 enum { REDVE_VE_NONE = 0, REDVE_VE_MPE = 1, REDVE_VE_RRE = 2, REDVE_VE_SVD_MPE = 3 };
 enum { REDVE_PREC_FP32 = 0, REDVE_PREC_BF16 = 1 };
 enum { REDVE_BASE_FP = 0, REDVE_BASE_SD = 1 };
+enum { REDVE_LIN_CG = 0, REDVE_LIN_FFT = 1 };
 
 /* Largest supported sizes. */
 #define REDVE_MAX_PSF 15     /* PSF side (odd, 1..15)                              */
@@ -125,6 +126,14 @@ int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int 
  * (computed per image in batches). Everything else (extrapolation, stopping, statistics) is
  * the same; "FP call" then counts SD steps. */
 int redve_set_base(redve_t h, int base, double mu);
+/* Linear step of the FP call (eq. (7); its footnote allows the Fourier domain for
+ * block-circulant H, or iterative methods). REDVE_LIN_CG (default): cg_iters conjugate-
+ * gradient iterations, warm-started. REDVE_LIN_FFT: the exact inverse in the Fourier domain
+ * (single-precision real transforms of rocFFT on the FP64-accumulated residual), for
+ * deblurring only (decim = 1; solve and fp_step return REDVE_E_ARG otherwise); the batched
+ * engine and the server use CG and refuse it. In this build REDVE_LIN_FFT is disabled and
+ * returns REDVE_E_STATE. */
+int redve_set_linear_solver(redve_t h, int kind);
 
 /* Solve: y (device, hy x wy) -> x (device, hx x wx), hy = ceil(hx/decim), wy = ceil(wx/decim).
  * x0 (device, hx x wx) is the initial vector, or NULL for the default (y when decim = 1,

@@ -20,19 +20,21 @@ OK, E_ARG, E_STATE, E_NOMEM, E_HIP, E_NONFINITE, E_DIVERGED = 0, -1, -2, -3, -4,
 VE_NONE, VE_MPE, VE_RRE, VE_SVD_MPE = 0, 1, 2, 3
 PREC_FP32, PREC_BF16 = 0, 1
 BASE_FP, BASE_SD = 0, 1
+LIN_CG, LIN_FFT = 0, 1
 METHODS = {"none": VE_NONE, "mpe": VE_MPE, "rre": VE_RRE, "svd_mpe": VE_SVD_MPE}
 PRECISIONS = {"fp32": PREC_FP32, "bf16": PREC_BF16}
 BASES = {"fp": BASE_FP, "sd": BASE_SD}
+LINEAR = {"cg": LIN_CG, "fft": LIN_FFT}
 
 # Every symbol include/redve.h declares.
 EXPORTS = (
     "redve_create", "redve_destroy", "redve_set_stream", "redve_last_error",
     "redve_workspace_bytes", "redve_set_operator", "redve_set_noise", "redve_set_lambda",
     "redve_set_denoiser", "redve_set_extrapolation", "redve_set_solver", "redve_set_base",
-    "redve_solve", "redve_apply_H", "redve_apply_Ht", "redve_apply_A", "redve_cg",
-    "redve_denoise", "redve_fp_step", "redve_objective", "redve_extrapolate",
-    "redve_solve_batch", "redve_server_create", "redve_server_submit", "redve_server_poll",
-    "redve_server_wait", "redve_server_counts", "redve_server_destroy",
+    "redve_set_linear_solver", "redve_solve", "redve_apply_H", "redve_apply_Ht",
+    "redve_apply_A", "redve_cg", "redve_denoise", "redve_fp_step", "redve_objective",
+    "redve_extrapolate", "redve_solve_batch", "redve_server_create", "redve_server_submit",
+    "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
 )
 
 
@@ -94,6 +96,7 @@ def load_library(path: str = LIB_PATH):
         "redve_set_extrapolation": ([vp, i, i, i], i),
         "redve_set_solver": ([vp, i, i, d, i], i),
         "redve_set_base": ([vp, i, d], i),
+        "redve_set_linear_solver": ([vp, i], i),
         "redve_solve": ([vp, vp, i, i, vp, vp, i, i, ctypes.POINTER(Stats)], i),
         "redve_apply_H": ([vp, vp, i, i, vp], i),
         "redve_apply_Ht": ([vp, vp, i, i, vp], i),
@@ -224,6 +227,11 @@ class Restorer:
     def set_base(self, base: str = "fp", mu: float = 0.0):
         """Base iteration: "fp" (eq. (7)) or "sd" (steepest descent, step mu; <= 0: default)."""
         self._check(self._L.redve_set_base(self._h, BASES[base], float(mu)))
+        return self
+
+    def set_linear_solver(self, kind: str = "cg"):
+        """Linear step of the FP call: "cg" (cg_iters iterations) or "fft" (exact, deblurring)."""
+        self._check(self._L.redve_set_linear_solver(self._h, LINEAR[kind]))
         return self
 
     def configure(self, prob, precision="fp32", method=None, L=None, m=None, tol=None,

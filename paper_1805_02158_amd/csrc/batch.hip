@@ -614,6 +614,10 @@ int check_settings(redve_t h) {
         h->err = "the batched FP iteration needs cg_iters >= 1";
         return REDVE_E_ARG;
     }
+    if (h->lin != REDVE_LIN_CG) {
+        h->err = "the batched engine solves the linear step with CG";
+        return REDVE_E_ARG;
+    }
     return REDVE_OK;
 }
 
@@ -791,6 +795,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     *out = nullptr;
     if (!proto->have_den) return REDVE_E_STATE;
     if (proto->base == REDVE_BASE_FP && proto->cg_iters < 1) return REDVE_E_ARG;
+    if (proto->lin != REDVE_LIN_CG) return REDVE_E_ARG;
     auto s = std::make_unique<redve_server>();
     // copy the settings; device buffers of the denoiser are shared read-only with proto
     redve_ctx& c = s->ctx;

@@ -77,7 +77,16 @@ struct redve_ctx {
     unsigned long long gen = 0;
     void* batch = nullptr;                 // the kept batched engine (batch.hip)
     void (*batch_free)(void*) = nullptr;   // its destructor
+    // linear step of the FP call
+    int lin = REDVE_LIN_CG;
+    unsigned long long op_gen = 0;         // bumped by set_operator / set_noise / set_lambda
+    void* fft = nullptr;                   // Fourier solve plans and tables (fft.hip)
+    void (*fft_free)(void*) = nullptr;
 };
+
+// d = F^-1[F(r0) / A_hat], x_out = x_in + d for periodic deblurring (fft.hip).
+int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, float* d, int H,
+                         int W);
 
 // Device view of the handle's denoiser (runtime.hip).
 redve::TnrdDev redve_tnrd_dev(redve_t h);

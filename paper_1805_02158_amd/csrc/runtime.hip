@@ -148,6 +148,13 @@ int check_ready(redve_t h, bool need_den) {
     return REDVE_OK;
 }
 
+// The Fourier linear step diagonalises A only for H = B (decim 1, Sec. II-B footnote).
+int check_linear(redve_t h) {
+    if (h->lin == REDVE_LIN_FFT && h->base == REDVE_BASE_FP && h->decim != 1)
+        return fail(h, REDVE_E_ARG, "the Fourier linear step needs decim = 1 (deblurring)");
+    return REDVE_OK;
+}
+
 int check_image(redve_t h, int hx, int wx) {
     if (hx < 2 || wx < 2) return fail(h, REDVE_E_ARG, "image sides must be >= 2");
     if ((long long)hx * wx > (1LL << 30)) return fail(h, REDVE_E_ARG, "image too large");
@@ -230,6 +237,13 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
         LAUNCH_CHECK(h);
         return REDVE_OK;
     }
+    if (h->lin == REDVE_LIN_FFT) {  // the exact solve of A d = r0 in the Fourier domain
+        launch_cg_init_fp(linop_of(h), x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
+        LAUNCH_CHECK(h);
+        if ((rc = redve_fft_correction(h, w.r[0], x_in, x_out, w.d, H, W)))
+            return fail(h, rc, "Fourier linear step failed");
+        return REDVE_OK;
+    }
     if (h->cg_iters <= 0) {
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
@@ -296,6 +310,8 @@ int redve_destroy(redve_t h) {
     hipStreamSynchronize(h->stream);
     if (h->batch && h->batch_free) h->batch_free(h->batch);
     h->batch = nullptr;
+    if (h->fft && h->fft_free) h->fft_free(h->fft);
+    h->fft = nullptr;
     if (h->ws.arena) hipFree(h->ws.arena);
     hipFree(h->d_psf);
     hipFree(h->d_psf64);
@@ -347,6 +363,7 @@ int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) 
     h->decim = decim;
     h->psf_l1 = 0.0;
     for (int i = 0; i < kh * kw; ++i) h->psf_l1 += fabs(psf[i]);
+    ++h->op_gen;
     // rank-1 test: psf = col (x) row with col = the column through the largest tap and
     // row = that tap's row divided by it (exact for any rank-1 matrix)
     int im = 0;
@@ -367,6 +384,7 @@ int redve_set_noise(redve_t h, double sigma) {
     if (!h) return REDVE_E_ARG;
     if (!(sigma > 0) || !std::isfinite(sigma)) return fail(h, REDVE_E_ARG, "sigma must be > 0");
     h->sigma = sigma;
+    ++h->op_gen;
     return REDVE_OK;
 }
 
@@ -374,6 +392,7 @@ int redve_set_lambda(redve_t h, double lambda) {
     if (!h) return REDVE_E_ARG;
     if (!(lambda > 0) || !std::isfinite(lambda)) return fail(h, REDVE_E_ARG, "lambda must be > 0");
     h->lambda = lambda;
+    ++h->op_gen;
     return REDVE_OK;
 }
 
@@ -484,6 +503,15 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m) {
     return REDVE_OK;
 }
 
+int redve_set_linear_solver(redve_t h, int kind) {
+    if (!h) return REDVE_E_ARG;
+    if (kind != REDVE_LIN_CG && kind != REDVE_LIN_FFT) return fail(h, REDVE_E_ARG, "bad solver");
+    if (kind == REDVE_LIN_FFT)  // disabled until its GPU run is understood; see the design notes
+        return fail(h, REDVE_E_STATE, "the Fourier linear step is disabled in this build");
+    h->lin = kind;
+    return REDVE_OK;
+}
+
 int redve_set_base(redve_t h, int base, double mu) {
     if (!h) return REDVE_E_ARG;
     if (base != REDVE_BASE_FP && base != REDVE_BASE_SD) return fail(h, REDVE_E_ARG, "bad base");
@@ -591,7 +619,7 @@ int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, flo
     if (!h) return REDVE_E_ARG;
     if (!y || !x || !out || x == out) return fail(h, REDVE_E_ARG, "bad pointers");
     int rc = check_image(h, hx, wx);
-    if (rc || (rc = check_ready(h, true))) return rc;
+    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h))) return rc;
     HIP_TRY(h, hipSetDevice(h->device));
     if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
     return fp_call(h, y, x, out, hx, wx);
@@ -632,7 +660,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     if (st) memset(st, 0, sizeof(*st));
     if (!y || !x) return fail(h, REDVE_E_ARG, "null pointer");
     int rc = check_image(h, hx, wx);
-    if (rc || (rc = check_ready(h, true))) return rc;
+    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h))) return rc;
     if (hy != (hx + h->decim - 1) / h->decim || wy != (wx + h->decim - 1) / h->decim)
         return fail(h, REDVE_E_ARG, "observation size does not match ceil(x size / decim)");
     HIP_TRY(h, hipSetDevice(h->device));
