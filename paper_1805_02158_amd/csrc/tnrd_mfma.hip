@@ -31,8 +31,6 @@ constexpr int UH = TH + 8, UW = TW + 8;  // u region: rows r0-4 .. r0+TH+3
 constexpr int VH = TH + 4, VW = TW + 4;  // positions of z / v: rows r0-2 .. r0+TH+1
 constexpr int NPOS = VH * VW;            // 400 = 25 groups of 16
 constexpr int NGRP = NPOS / 16;
-constexpr int NTHR = 512;
-constexpr int NWAVE = NTHR / 64;
 constexpr int WPAD = kRbfPad;
 static_assert(NPOS % 16 == 0, "positions must fill MFMA groups");
 
@@ -46,7 +44,9 @@ __device__ inline bf16x8 load_frag(const uint16_t* p) {
     return r;
 }
 
-template <int KC>
+// NT threads per workgroup: 512 where the image has tiles for every CU several times over,
+// 1024 on small images (one tile per CU), where twice the waves hide twice the latency.
+template <int KC, int NT>
 __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float* __restrict__ f,
                                        float* __restrict__ out, int H, int W, int r0, int c0,
                                        const uint16_t* __restrict__ bfwd,
@@ -64,9 +64,10 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     float* su = sw + F * wstride;     // UH * UW
     float* sz = su + UH * UW;         // NPOS * ZS
     float* ss = sz;
+    constexpr int NWAVE = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    for (int e = threadIdx.x; e < UH * UW; e += NTHR) {
+    for (int e = threadIdx.x; e < UH * UW; e += NT) {
         const int er = r0 - 4 + e / UW, ec = c0 - 4 + e % UW;
         float val = 0.f;
         if (er >= -2 && er <= H + 1 && ec >= -2 && ec <= W + 1) {
@@ -75,7 +76,7 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         }
         su[e] = val;
     }
-    for (int e = threadIdx.x; e < F * wstride; e += NTHR) sw[e] = rbfw[e];  // padded rows
+    for (int e = threadIdx.x; e < F * wstride; e += NT) sw[e] = rbfw[e];  // padded rows
     __syncthreads();
 
     const int m = lane & 15, sl = lane >> 4;  // fragment row/column, K slice
@@ -110,25 +111,26 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     // ---- influence functions, dense over (filter, position) pairs, FP32. Consecutive lanes
     // take consecutive positions of one filter: they gather weights from the same LDS row,
     // mostly at the same or nearby centres (broadcast instead of bank conflicts), and read z
-    // at the odd stride ZS (conflict-free). The pair index advances by NTHR = NPOS + 112 per
-    // step, so the position, the row offsets and the filter are stepped, not divided out; in a
-    // tile whose positions are all inside the image no position is tested.
+    // at the odd stride ZS (conflict-free). The pair index advances by NT per step, i.e. by
+    // NT / NPOS filters and NT % NPOS positions, so the position, the row offsets and the
+    // filter are stepped, not divided out; in a tile whose positions are all inside the image
+    // no position is tested.
     {
-        static_assert(NTHR > NPOS && NTHR < 2 * NPOS, "one filter wrap per step");
+        constexpr int ISTEP = NT / NPOS, QSTEP = NT % NPOS;
         const bool inner = r0 >= 2 && c0 >= 2 && r0 + TH + 2 <= H && c0 + TW + 2 <= W;
-        int i = threadIdx.x / NPOS, q = threadIdx.x - i * NPOS;
-        int zoff = q * ZS + i, woff = i * wstride;
-        const int zstep = (NTHR - NPOS) * ZS + 1, zwrap = NPOS * ZS - 1;
-        for (int e = threadIdx.x; e < NPOS * F; e += NTHR) {
+        int q = threadIdx.x % NPOS;
+        int zoff = q * ZS + threadIdx.x / NPOS, woff = (threadIdx.x / NPOS) * wstride;
+        const int zstep = QSTEP * ZS + ISTEP, zwrap = NPOS * ZS - 1;
+        for (int e = threadIdx.x; e < NPOS * F; e += NT) {
             bool in = inner;
             if (!inner) {
                 const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
                 in = gr >= 0 && gr < H && gc >= 0 && gc < W;
             }
             sz[zoff] = in ? phi_eval<KC>(sz[zoff], sw + woff, rc) : 0.f;
-            q += NTHR - NPOS;
+            q += QSTEP;
             zoff += zstep;
-            woff += wstride;
+            woff += ISTEP * wstride;
             if (q >= NPOS) {
                 q -= NPOS;
                 zoff -= zwrap;
@@ -162,7 +164,7 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     }
     __syncthreads();
     // ---- shift-add of the tap sums, mirror fold at the border, reaction update
-    for (int e = threadIdx.x; e < TH * TW; e += NTHR) {
+    for (int e = threadIdx.x; e < TH * TW; e += NT) {
         const int tr = e / TW, tc = e % TW;
         const int gr = r0 + tr, gc = c0 + tc;
         if (gr >= H || gc >= W) continue;
@@ -199,18 +201,18 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     }
 }
 
-template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16(
+template <int KC, int NT>
+__global__ __launch_bounds__(NT) void k_tnrd_stage_bf16(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
     const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    stage_tile_bf16<KC>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, bfwd, badj, rbfw, F,
-                        rc, theta, out_mode);
+    stage_tile_bf16<KC, NT>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, bfwd,
+                            badj, rbfw, F, rc, theta, out_mode);
 }
 
 template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16_batch(
+__global__ __launch_bounds__(512) void k_tnrd_stage_bf16_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
     const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
@@ -219,9 +221,9 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_bf16_batch(
     const ImgDesc& d = desc[e.img];
     if (!d.active) return;
     const int t = e.t, ntx = (d.W + TW - 1) / TW;
-    stage_tile_bf16<KC>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H,
-                        d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta,
-                        out_mode);
+    stage_tile_bf16<KC, 512>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H,
+                             d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta,
+                             out_mode);
 }
 
 }  // namespace
@@ -240,12 +242,23 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
     const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
-    if (rc.K == 7)
-        k_tnrd_stage_bf16<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                                       rc, d.theta[t], out_mode);
-    else
-        k_tnrd_stage_bf16<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                                       rc, d.theta[t], out_mode);
+    // fewer tiles than two per CU: 1024 threads per tile
+    const bool wide = grid.x * grid.y < 512;
+#define REDVE_STAGE_BF16(KC, NT)                                                             \
+    k_tnrd_stage_bf16<KC, NT><<<grid, NT, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt, \
+                                                      rc, d.theta[t], out_mode)
+    if (rc.K == 7) {
+        if (wide)
+            REDVE_STAGE_BF16(7, 1024);
+        else
+            REDVE_STAGE_BF16(7, 512);
+    } else {
+        if (wide)
+            REDVE_STAGE_BF16(0, 1024);
+        else
+            REDVE_STAGE_BF16(0, 512);
+    }
+#undef REDVE_STAGE_BF16
 }
 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
@@ -257,11 +270,11 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
-        k_tnrd_stage_bf16_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, bf,
+        k_tnrd_stage_bf16_batch<7><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf,
                                                                 ba, wf, d.nfilt, rc, d.theta[t],
                                                                 out_mode);
     else
-        k_tnrd_stage_bf16_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, bf,
+        k_tnrd_stage_bf16_batch<0><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf,
                                                                 ba, wf, d.nfilt, rc, d.theta[t],
                                                                 out_mode);
 }
