@@ -88,8 +88,9 @@ struct TileSmem {
 // q = A P on the tile at (r0, c0). P must already be in sm.p on the tile + 2r halo (region
 // origin (r0 - 2rh, c0 - 2rw)). Returns P and q at the thread's NO outputs. RS > 0: separable
 // PSF of compile-time radius RS (fully unrolled passes); RS == 0: runtime sizes (separable or
-// general 2-D).
-template <int RS>
+// general 2-D). NTH threads share the passes; with NTH > kThreads (one output per thread of
+// the first kThreads) the other threads only help with the halo passes and get no output.
+template <int RS, int NTH = kThreads>
 __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, int c0,
                                        TileSmem<RS>& sm, float (&pc)[NO], float (&q)[NO]) {
     constexpr int SW = TileSmem<RS>::S;
@@ -100,7 +101,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
     const int s = op.decim;
     if (RS || op.separable) {
         // row pass over all P rows, B columns: h[pr][bc] = sum_b row[b] P[pr][bc + 2rw - b]
-        for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
+        for (int e = threadIdx.x; e < ph * bw; e += NTH) {
             const int pr = e / bw, bc = e % bw;
             const float* prow = sm.p + pr * SW + bc + 2 * rw;
             float acc = 0.f;
@@ -113,7 +114,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
         }
         __syncthreads();
         // column pass + decimation mask: t[br][bc] = m * sum_a col[a] h[br + 2rh - a][bc]
-        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+        for (int e = threadIdx.x; e < bh * bw; e += NTH) {
             const int br = e / bw, bc = e % bw;
             float acc = 0.f;
             bool keep = true;
@@ -133,7 +134,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
         }
         __syncthreads();
         // B^T row pass: h[br][tc] = sum_b row[b] t[br][tc + b]
-        for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
+        for (int e = threadIdx.x; e < bh * TW; e += NTH) {
             const int br = e / TW, tc = e % TW;
             const float* trow = sm.t + br * SW + tc;
             float acc = 0.f;
@@ -148,6 +149,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int o = threadIdx.x + k * kThreads;
+            if (NTH > kThreads && o >= TH * TW) break;
             const int tr = o / TW, tc = o % TW;
             const float* hcol = sm.h + tr * SW + tc;
             float acc = 0.f;
@@ -160,7 +162,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
             q[k] = op.inv_s2 * acc + op.lambda * pc[k];
         }
     } else {
-        for (int e = threadIdx.x; e < bh * bw; e += kThreads) {
+        for (int e = threadIdx.x; e < bh * bw; e += NTH) {
             const int br = e / bw, bc = e % bw;
             const int gr = wrapi(r0 - rh + br, H), gc = wrapi(c0 - rw + bc, W);
             float acc = 0.f;
@@ -177,6 +179,7 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int o = threadIdx.x + k * kThreads;
+            if (NTH > kThreads && o >= TH * TW) break;
             const int tr = o / TW, tc = o % TW;
             float acc = 0.f;
             for (int a = -rh; a <= rh; ++a) {
@@ -491,24 +494,24 @@ __device__ inline void cg_last_tile(int H, int W, int r0, int c0, int k, float a
 // Raw inputs of one CG iteration on one tile, loaded before the step lengths are known so that
 // these loads overlap the reduction that produces alpha and beta: r_k, w_k, s_{k-1} on the P
 // region (tile + 2r halo) and r_k, w_k, s_{k-1}, p_{k-1}, d_k at the thread's output pixel.
-template <int RS>
+template <int RS, int NTH = kThreads>
 struct CgIn {
     static constexpr int PHr = TH + 4 * RS, PWr = TW + 4 * RS;
-    static constexpr int NE = (PHr * PWr + kThreads - 1) / kThreads;
+    static constexpr int NE = (PHr * PWr + NTH - 1) / NTH;
     float r[NE], w[NE], s[NE];
     float ro, wo, so, po, dn;
 };
 static_assert(NO == 1, "one output pixel per thread");
 
-template <int RS>
+template <int RS, int NTH = kThreads>
 __device__ inline void cg_fetch(int H, int W, int r0, int c0, int k, const float* __restrict__ r_in,
                                 const float* __restrict__ w_in, const float* __restrict__ s_in,
                                 const float* __restrict__ p, const float* __restrict__ d,
-                                CgIn<RS>& f) {
-    using C = CgIn<RS>;
+                                CgIn<RS, NTH>& f) {
+    using C = CgIn<RS, NTH>;
 #pragma unroll
     for (int i = 0; i < C::NE; ++i) {
-        const int e = threadIdx.x + i * kThreads;
+        const int e = threadIdx.x + i * NTH;
         f.r[i] = f.w[i] = f.s[i] = 0.f;
         if (e < C::PHr * C::PWr) {
             const int pr = e / C::PWr, pc = e % C::PWr;
@@ -521,7 +524,7 @@ __device__ inline void cg_fetch(int H, int W, int r0, int c0, int k, const float
     }
     f.ro = f.wo = f.so = f.po = f.dn = 0.f;
     const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
-    if (gr < H && gc < W) {
+    if ((NTH == kThreads || threadIdx.x < TH * TW) && gr < H && gc < W) {
         const size_t g = (size_t)gr * W + gc;
         f.ro = r_in[g];
         f.wo = w_in[g];
@@ -533,19 +536,23 @@ __device__ inline void cg_fetch(int H, int W, int r0, int c0, int k, const float
     }
 }
 
-// cg_iter_tile on prefetched inputs (the same arithmetic).
-template <int RS>
-__device__ inline void cg_iter_fetched(const LinOp& op, int H, int W, int r0, int c0, int k,
-                                       float alpha, float beta, const CgIn<RS>& f,
-                                       float* __restrict__ r_out, float* __restrict__ w_out,
-                                       float* __restrict__ s_out, float* __restrict__ p,
-                                       float* __restrict__ d, TileSmem<RS>& sm,
-                                       double (&acc)[2]) {
-    using C = CgIn<RS>;
+// Outputs of one CG iteration at a thread's pixel g (valid: the thread has a pixel in the image).
+struct CgOut {
+    size_t g;
+    float s, p, d, r, w;
+    bool valid;
+};
+
+// cg_iter_tile on prefetched inputs (the same arithmetic), returning the outputs unstored.
+template <int RS, int NTH = kThreads>
+__device__ inline CgOut cg_iter_compute(const LinOp& op, int H, int W, int r0, int c0, int k,
+                                        float alpha, float beta, const CgIn<RS, NTH>& f,
+                                        TileSmem<RS>& sm, double (&acc)[2]) {
+    using C = CgIn<RS, NTH>;
     constexpr int SW = TileSmem<RS>::S;
 #pragma unroll
     for (int i = 0; i < C::NE; ++i) {
-        const int e = threadIdx.x + i * kThreads;
+        const int e = threadIdx.x + i * NTH;
         if (e < C::PHr * C::PWr) {
             const float sk = k ? f.w[i] + beta * f.s[i] : f.w[i];
             sm.p[(e / C::PWr) * SW + e % C::PWr] = f.r[i] - alpha * sk;
@@ -553,21 +560,44 @@ __device__ inline void cg_iter_fetched(const LinOp& op, int H, int W, int r0, in
     }
     __syncthreads();
     float r1[NO], w1[NO];
-    tile_A_from_lds<RS>(op, H, W, r0, c0, sm, r1, w1);
+    tile_A_from_lds<RS, NTH>(op, H, W, r0, c0, sm, r1, w1);
+    CgOut o{};
     const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
-    if (gr < H && gc < W) {
-        const size_t g = (size_t)gr * W + gc;
-        const float sk = k ? f.wo + beta * f.so : f.wo;
-        const float pk = k ? f.ro + beta * f.po : f.ro;
-        const float dn = k ? f.dn + alpha * pk : alpha * pk;
-        s_out[g] = sk;
-        p[g] = pk;
-        d[g] = dn;
-        r_out[g] = r1[0];
-        w_out[g] = w1[0];
+    if ((NTH == kThreads || threadIdx.x < TH * TW) && gr < H && gc < W) {
+        o.g = (size_t)gr * W + gc;
+        o.s = k ? f.wo + beta * f.so : f.wo;
+        o.p = k ? f.ro + beta * f.po : f.ro;
+        o.d = k ? f.dn + alpha * o.p : alpha * o.p;
+        o.r = r1[0];
+        o.w = w1[0];
+        o.valid = true;
         acc[0] += (double)r1[0] * (double)r1[0];
         acc[1] += (double)w1[0] * (double)r1[0];
     }
+    return o;
+}
+
+__device__ inline void cg_store(const CgOut& o, float* __restrict__ r_out,
+                                float* __restrict__ w_out, float* __restrict__ s_out,
+                                float* __restrict__ p, float* __restrict__ d) {
+    if (o.valid) {
+        s_out[o.g] = o.s;
+        p[o.g] = o.p;
+        d[o.g] = o.d;
+        r_out[o.g] = o.r;
+        w_out[o.g] = o.w;
+    }
+}
+
+template <int RS, int NTH = kThreads>
+__device__ inline void cg_iter_fetched(const LinOp& op, int H, int W, int r0, int c0, int k,
+                                       float alpha, float beta, const CgIn<RS, NTH>& f,
+                                       float* __restrict__ r_out, float* __restrict__ w_out,
+                                       float* __restrict__ s_out, float* __restrict__ p,
+                                       float* __restrict__ d, TileSmem<RS>& sm,
+                                       double (&acc)[2]) {
+    cg_store(cg_iter_compute<RS, NTH>(op, H, W, r0, c0, k, alpha, beta, f, sm, acc), r_out, w_out,
+             s_out, p, d);
 }
 
 // One conjugate-gradient iteration in the single-reduction (Chronopoulos-Gear) form: with
@@ -581,51 +611,77 @@ __device__ inline void cg_iter_fetched(const LinOp& op, int H, int W, int r0, in
 // iterates; one grid-wide reduction per iteration instead of two. r_{k+1} is formed on the
 // tile + halo from r_k, w_k and s_{k-1}, then w_{k+1} is its stencil. On the last iteration
 // only x_out = x_in + d_{k+1} is written.
-template <int RS>
-__global__ __launch_bounds__(kThreads) void k_cg_iter(
+//
+// NTH = kThreads: one output pixel per thread. NTH > kThreads (RS > 0, not the last
+// iteration): the extra threads share the loads and the halo passes of the tile, for small
+// images whose tiles give each CU a single workgroup.
+template <int RS, int NTH>
+__global__ __launch_bounds__(NTH) void k_cg_iter(
     const LinOp op, int H, int W, int k, int last, const float* __restrict__ r_in,
     const float* __restrict__ w_in, const float* __restrict__ s_in, float* __restrict__ r_out,
     float* __restrict__ w_out, float* __restrict__ s_out, float* __restrict__ p,
     float* __restrict__ d, const float* __restrict__ x_in, float* __restrict__ x_out,
     Partials rm, const double* __restrict__ hist_prev, double* __restrict__ hist_cur,
     double* __restrict__ part) {
+    static_assert(NTH == kThreads || RS > 0, "wide workgroups need a compile-time radius");
     __shared__ TileSmem<RS> sm;
-    __shared__ double sred[2 * kThreads / 64];
+    __shared__ double sred[2 * NTH / 64];
     __shared__ double bc[2];
     const int nt = ntiles(H, W);
     int r0 = 0, c0 = 0;
-    CgIn<RS> f;
+    // Loads in order of need: the published partials and (alpha, rho) of the previous
+    // iteration first, then the tile's inputs, so that the step lengths do not wait for those.
+    Early2 early;
+    const bool early_ok = rm.n <= kEarlyPartials;
+    if (early_ok) consume2_issue(rm.p, kMaxRedBlocks, rm.n, early);
+    const double alpha_prev = k ? hist_prev[0] : 0.0, rho_prev = k ? hist_prev[1] : 0.0;
+    CgIn<RS, NTH> f;
     if constexpr (RS > 0) {
         if (!last && (int)blockIdx.x < nt) {
             tile_origin(xcd_tile(blockIdx.x, nt), W, r0, c0);
-            cg_fetch<RS>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
+            cg_fetch<RS, NTH>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
         }
     }
     double rho, mu;
-    consume2(rm.p, kMaxRedBlocks, rm.n, bc, rho, mu);
+    if (early_ok)
+        consume2_finish(early, bc, rho, mu);
+    else
+        consume2(rm.p, kMaxRedBlocks, rm.n, bc, rho, mu);
     double alpha_d, beta_d;
-    cg_scalars(k, rho, mu, k ? hist_prev[0] : 0.0, k ? hist_prev[1] : 0.0, alpha_d, beta_d);
+    cg_scalars(k, rho, mu, alpha_prev, rho_prev, alpha_d, beta_d);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hist_cur[0] = alpha_d;
         hist_cur[1] = rho;
     }
     const float alpha = (float)alpha_d, beta = (float)beta_d;
     double acc[2] = {0.0, 0.0};
+    if constexpr (RS > 0) {
+        if (!last && nt <= (int)gridDim.x) {
+            // one tile per workgroup: the workgroup sum first, then every store at once
+            const CgOut o = cg_iter_compute<RS, NTH>(op, H, W, r0, c0, k, alpha, beta, f, sm, acc);
+            block_sum<2, NTH, kThreads>(acc, sred);  // outputs sit in the first kThreads
+            cg_store(o, r_out, w_out, s_out, p, d);
+            publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+            return;
+        }
+    }
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         tile_origin(xcd_tile(t, nt), W, r0, c0);
         if (last) {
-            cg_last_tile(H, W, r0, c0, k, alpha, beta, r_in, p, d, x_in, x_out);
+            if constexpr (NTH == kThreads)
+                cg_last_tile(H, W, r0, c0, k, alpha, beta, r_in, p, d, x_in, x_out);
         } else if constexpr (RS > 0) {
-            if (t != (int)blockIdx.x) cg_fetch<RS>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
-            cg_iter_fetched<RS>(op, H, W, r0, c0, k, alpha, beta, f, r_out, w_out, s_out, p, d,
-                                sm, acc);
+            if (t != (int)blockIdx.x)
+                cg_fetch<RS, NTH>(H, W, r0, c0, k, r_in, w_in, s_in, p, d, f);
+            cg_iter_fetched<RS, NTH>(op, H, W, r0, c0, k, alpha, beta, f, r_out, w_out, s_out, p,
+                                     d, sm, acc);
         } else {
             cg_iter_tile<RS>(op, H, W, r0, c0, k, alpha, beta, r_in, w_in, s_in, r_out, w_out,
                              s_out, p, d, sm, acc);
         }
     }
     if (last) return;
-    block_sum<2>(acc, sred);
+    block_sum<2, NTH>(acc, sred);
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
@@ -781,11 +837,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
     }
     double acc[2] = {0.0, 0.0};
     if constexpr (RS > 0) {
+        // the workgroup sum first, then every store of the tile at once
+        const CgImg c = cg[d - desc];
         CgIn<RS> f;
         cg_fetch<RS>(d->H, d->W, r0, c0, k, r_in + o, w_in + o, s_in + o, p + o, dd + o, f);
-        const CgImg c = cg[d - desc];
-        cg_iter_fetched<RS>(d->op, d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, f,
-                            r_out + o, w_out + o, s_out + o, p + o, dd + o, sm, acc);
+        const CgOut out = cg_iter_compute<RS>(d->op, d->H, d->W, r0, c0, k, (float)c.alpha,
+                                              (float)c.beta, f, sm, acc);
+        block_sum<2>(acc, sred);
+        cg_store(out, r_out + o, w_out + o, s_out + o, p + o, dd + o);
+        publish<2>(acc, part, cap, bt);
+        return;
     } else {
         const CgImg c = cg[d - desc];
         cg_iter_tile<RS>(d->op, d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, r_in + o,
@@ -796,10 +857,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
     publish<2>(acc, part, cap, bt);
 }
 
+inline int ntiles_host(int H, int W) { return ((H + TH - 1) / TH) * ((W + TW - 1) / TW); }
+
 inline int tile_blocks(int H, int W) {
-    const int nt = ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+    const int nt = ntiles_host(H, W);
     return nt < kMaxRedBlocks ? nt : kMaxRedBlocks;
 }
+
+// Images with fewer tiles than this run the CG iteration with kWideThreads per tile.
+constexpr int kWideThreads = 1024;
+constexpr int kWideBelowTiles = 512;
 
 inline int upd_blocks(int n) {
     const int b = (n + kThreads - 1) / kThreads;
@@ -894,15 +961,25 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
                         hipStream_t st) {
     const int g = last ? upd_blocks(H * W) : tile_blocks(H, W);
     const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
-    if (rr == 4)
-        k_cg_iter<4><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
-                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
-    else if (rr == 3)
-        k_cg_iter<3><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
-                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
-    else
-        k_cg_iter<0><<<g, kThreads, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out,
-                                             s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part);
+    // fewer tiles than two per CU: wide workgroups (see k_cg_iter)
+    const bool wide = !last && ntiles_host(H, W) < kWideBelowTiles;
+#define REDVE_CG_ITER(RS, NTH)                                                                 \
+    k_cg_iter<RS, NTH><<<g, NTH, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out, \
+                                          s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part)
+    if (rr == 4) {
+        if (wide)
+            REDVE_CG_ITER(4, kWideThreads);
+        else
+            REDVE_CG_ITER(4, kThreads);
+    } else if (rr == 3) {
+        if (wide)
+            REDVE_CG_ITER(3, kWideThreads);
+        else
+            REDVE_CG_ITER(3, kThreads);
+    } else {
+        REDVE_CG_ITER(0, kThreads);
+    }
+#undef REDVE_CG_ITER
     return Partials{part, g};
 }
 
