@@ -68,7 +68,9 @@ typedef struct {
     const double* filters;  /* T*nfilt*ksize*ksize, row-major taps                */
     const double* rbf_w;    /* T*nfilt*nrbf                                       */
     const double* react;    /* T reaction weights theta_t                         */
-    int precision;          /* REDVE_PREC_FP32 or REDVE_PREC_BF16 (filter banks)  */
+    int precision;          /* REDVE_PREC_FP32 or REDVE_PREC_BF16 (filter banks);
+                               BF16 needs 4 (576 + 400 z + nfilt (nrbf + 32)) <= 65536
+                               bytes, z = 25 (nfilt <= 25) or 33 (else)        */
 } redve_tnrd_t;
 
 /* Statistics of one solve (host struct written by redve_solve). */

@@ -431,6 +431,10 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     }
     if (p->precision != REDVE_PREC_FP32 && p->precision != REDVE_PREC_BF16)
         return fail(h, REDVE_E_ARG, "precision must be FP32 or BF16");
+    // a BF16 stage keeps a tile's per-position rows (z, v, tap sums) and the weight rows in LDS
+    if (p->stages > 0 && p->precision == REDVE_PREC_BF16 &&
+        tnrd_bf16_smem_bytes(p->nfilt, p->nrbf) > 64 * 1024)
+        return fail(h, REDVE_E_ARG, "BF16 stage: nfilt and nrbf exceed 64 KiB of LDS (use FP32)");
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     hipFree(h->d_filt);

@@ -46,7 +46,9 @@ __device__ inline bf16x8 load_frag(const uint16_t* p) {
 
 // NT threads per workgroup: 512 where the image has tiles for every CU several times over,
 // 1024 on small images (one tile per CU), where twice the waves hide twice the latency.
-template <int KC, int NT>
+// ZS: the odd row stride of the per-position rows in LDS (z, v, then the tap sums), at least
+// max(F, 25): 25 for up to 25 filters, 33 for up to 32.
+template <int KC, int NT, int ZS>
 __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float* __restrict__ f,
                                        float* __restrict__ out, int H, int W, int r0, int c0,
                                        const uint16_t* __restrict__ bfwd,
@@ -58,7 +60,7 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     // overwrites the rows of its own MFMA group after loading them as an operand).
     // The weight rows come first, so a lane's window of weights is within the immediate
     // offsets of one LDS address.
-    const int ZS = (F > 25 ? F : 25) | 1;
+    static_assert(ZS % 2 == 1 && ZS >= 25, "odd stride covering the 25 taps");
     const int wstride = rc.J + 2 * WPAD;
     float* sw = smem;                 // F * (J + 2 WPAD)
     float* su = sw + F * wstride;     // UH * UW
@@ -108,26 +110,19 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         }
     }
     __syncthreads();
-    // ---- influence functions, dense over (filter, position) pairs, FP32. Consecutive lanes
-    // take consecutive positions of one filter: they gather weights from the same LDS row,
-    // mostly at the same or nearby centres (broadcast instead of bank conflicts), and read z
-    // at the odd stride ZS (conflict-free). The pair index advances by NT per step, i.e. by
-    // NT / NPOS filters and NT % NPOS positions, so the position, the row offsets and the
-    // filter are stepped, not divided out; in a tile whose positions are all inside the image
-    // no position is tested.
+    // ---- influence functions, dense over (filter, position) pairs, FP32, at every position
+    // (the adjoint bank zeroes those outside the image). Consecutive lanes take consecutive
+    // positions of one filter: they gather weights from the same LDS row, mostly at the same
+    // or nearby centres (broadcast instead of bank conflicts), and read z at the odd stride ZS
+    // (conflict-free). The pair index advances by NT per step, i.e. by NT / NPOS filters and
+    // NT % NPOS positions, so the offsets are stepped, not divided out.
     {
         constexpr int ISTEP = NT / NPOS, QSTEP = NT % NPOS;
-        const bool inner = r0 >= 2 && c0 >= 2 && r0 + TH + 2 <= H && c0 + TW + 2 <= W;
         int q = threadIdx.x % NPOS;
         int zoff = q * ZS + threadIdx.x / NPOS, woff = (threadIdx.x / NPOS) * wstride;
         const int zstep = QSTEP * ZS + ISTEP, zwrap = NPOS * ZS - 1;
         for (int e = threadIdx.x; e < NPOS * F; e += NT) {
-            bool in = inner;
-            if (!inner) {
-                const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
-                in = gr >= 0 && gr < H && gc >= 0 && gc < W;
-            }
-            sz[zoff] = in ? phi_eval<KC>(sz[zoff], sw + woff, rc) : 0.f;
+            sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
             q += QSTEP;
             zoff += zstep;
             woff += ISTEP * wstride;
@@ -145,11 +140,13 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         const bf16x8 b1 = load_frag(badj + (1 * 64 + lane) * 8);
         for (int grp = wave; grp < NGRP; grp += NWAVE) {
             const int q = grp * 16 + m;
+            const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
+            const bool qin = gr >= 0 && gr < H && gc >= 0 && gc < W;  // v = 0 outside the image
             bf16x8 a;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int i = sl * 8 + j;
-                a[j] = (__bf16)(i < F ? sz[q * ZS + i] : 0.f);
+                a[j] = (__bf16)(i < F && qin ? sz[q * ZS + i] : 0.f);
             }
             f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
             s0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, s0, 0, 0, 0);
@@ -163,55 +160,81 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
         }
     }
     __syncthreads();
-    // ---- shift-add of the tap sums, mirror fold at the border, reaction update
-    for (int e = threadIdx.x; e < TH * TW; e += NT) {
-        const int tr = e / TW, tc = e % TW;
-        const int gr = r0 + tr, gc = c0 + tc;
-        if (gr >= H || gc >= W) continue;
-        float g = 0.f;
+    // ---- shift-add of the tap sums, g(p) = sum_tap S[p + (2, 2) - tap][tap], and the
+    // transpose of the mirror extension: a border pixel also receives t(e), the same sum at
+    // each position e of the extension (outside the image, at most 2 away) that mirrors onto
+    // it. S vanishes outside the image, and every S such a t(e) needs inside the image lies in
+    // the position region. The first TH * TW threads take one pixel each; in a tile at the
+    // border the others meanwhile write the t(e) to the u region (free after the forward bank).
+    constexpr int EH = TH + 5, EW = TW + 5;  // rows r0-2 .. r0+TH+2, columns c0-2 .. c0+TW+2
+    static_assert(EH * EW <= UH * UW, "extension sums fit the u region");
+    static_assert(NT >= 2 * TH * TW, "threads for the pixels and for the extension");
+    float* st = su;
+    const bool edge = r0 < 2 || c0 < 2 || r0 + TH + 2 > H || c0 + TW + 2 > W;
+    const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
+    const int gr = r0 + tr, gc = c0 + tc;
+    const bool pix = (int)threadIdx.x < TH * TW && gr < H && gc < W;
+    float g = 0.f;
+    if (pix) {
 #pragma unroll
         for (int a = 0; a < 5; ++a)
 #pragma unroll
             for (int b = 0; b < 5; ++b) g += ss[((tr + 4 - a) * VW + tc + 4 - b) * ZS + a * 5 + b];
-        if (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) {
-            const int cr[3] = {gr, -1 - gr, 2 * H - 1 - gr};
-            const int cc[3] = {gc, -1 - gc, 2 * W - 1 - gc};
-            for (int x = 0; x < 3; ++x) {
-                const int er = cr[x];
-                if (er < -2 || er > H + 1) continue;
-                for (int y = 0; y < 3; ++y) {
-                    const int ec = cc[y];
-                    if (ec < -2 || ec > W + 1 || (x == 0 && y == 0)) continue;
-                    for (int a = 0; a < 5; ++a) {
-                        const int vr = er - a + 2;
-                        if (vr < 0 || vr >= H) continue;
-                        for (int b = 0; b < 5; ++b) {
-                            const int vc = ec - b + 2;
-                            if (vc < 0 || vc >= W) continue;
-                            g += ss[((vr - r0 + 2) * VW + vc - c0 + 2) * ZS + a * 5 + b];
-                        }
-                    }
+    } else if (edge && (int)threadIdx.x >= TH * TW) {
+        const int rend = min(r0 + TH, H), cend = min(c0 + TW, W);
+        for (int e = threadIdx.x - TH * TW; e < EH * EW; e += NT - TH * TW) {
+            const int lr = e / EW, lc = e % EW;
+            const int er = r0 - 2 + lr, ec = c0 - 2 + lc;
+            if (er < -2 || er > H + 1 || ec < -2 || ec > W + 1) continue;
+            if (er >= 0 && er < H && ec >= 0 && ec < W) continue;  // inside the image
+            const int mr = mirror(er, H), mc = mirror(ec, W);
+            if (mr < r0 || mr >= rend || mc < c0 || mc >= cend) continue;  // not onto this tile
+            float t = 0.f;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int qr = lr + 2 - a;  // position row, local to the position region
+#pragma unroll
+                for (int b = 0; b < 5; ++b) {
+                    const int qc = lc + 2 - b;
+                    const bool ok = qr >= 0 && qr < VH && qc >= 0 && qc < VW;
+                    const float v = ss[((ok ? qr : 0) * VW + (ok ? qc : 0)) * ZS + a * 5 + b];
+                    t += ok ? v : 0.f;
                 }
             }
+            st[e] = t;
         }
-        const size_t gi = (size_t)gr * W + gc;
-        const float wc = w ? w[gi] : 0.f;
-        const float wn = wc - g - theta * wc;
-        out[gi] = out_mode ? f[gi] + wn : wn;
     }
+    if (edge) __syncthreads();
+    if (!pix) return;
+    // rows -1-r (r <= 1) and 2H-1-r (r >= H-2) mirror onto row r, the same for columns, and the
+    // corners of both (two of each on a side of 2 or 3 pixels); then the reaction update
+    if (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) {
+        int lr[3] = {tr + 2, 0, 0}, lc[3] = {tc + 2, 0, 0}, nr = 1, nc = 1;
+        if (gr <= 1) lr[nr++] = -1 - gr - r0 + 2;
+        if (gr >= H - 2) lr[nr++] = 2 * H - 1 - gr - r0 + 2;
+        if (gc <= 1) lc[nc++] = -1 - gc - c0 + 2;
+        if (gc >= W - 2) lc[nc++] = 2 * W - 1 - gc - c0 + 2;
+        for (int x = 0; x < nr; ++x)
+            for (int y = 0; y < nc; ++y)
+                if (x || y) g += st[lr[x] * EW + lc[y]];
+    }
+    const size_t gi = (size_t)gr * W + gc;
+    const float wc = w ? w[gi] : 0.f;
+    const float wn = wc - g - theta * wc;
+    out[gi] = out_mode ? f[gi] + wn : wn;
 }
 
-template <int KC, int NT>
+template <int KC, int NT, int ZS>
 __global__ __launch_bounds__(NT) void k_tnrd_stage_bf16(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
     const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    stage_tile_bf16<KC, NT>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW, bfwd,
-                            badj, rbfw, F, rc, theta, out_mode);
+    stage_tile_bf16<KC, NT, ZS>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW,
+                                bfwd, badj, rbfw, F, rc, theta, out_mode);
 }
 
-template <int KC>
+template <int KC, int ZS>
 __global__ __launch_bounds__(512) void k_tnrd_stage_bf16_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
@@ -221,18 +244,33 @@ __global__ __launch_bounds__(512) void k_tnrd_stage_bf16_batch(
     const ImgDesc& d = desc[e.img];
     if (!d.active) return;
     const int t = e.t, ntx = (d.W + TW - 1) / TW;
-    stage_tile_bf16<KC, 512>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off, d.H,
-                             d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta,
-                             out_mode);
+    stage_tile_bf16<KC, 512, ZS>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off,
+                                 d.H, d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F,
+                                 rc, theta, out_mode);
 }
+
+// Launch of the single-image kernel for one window K (KC) and row stride (ZS).
+template <int KC, int ZS>
+void stage_single(bool wide, dim3 grid, size_t smem, hipStream_t st, const float* w,
+                  const float* f, float* out, int H, int W, const uint16_t* bf,
+                  const uint16_t* ba, const float* wf, int F, const RbfParams& rc, float theta,
+                  int out_mode) {
+    if (wide)
+        k_tnrd_stage_bf16<KC, 1024, ZS>
+            <<<grid, 1024, smem, st>>>(w, f, out, H, W, bf, ba, wf, F, rc, theta, out_mode);
+    else
+        k_tnrd_stage_bf16<KC, 512, ZS>
+            <<<grid, 512, smem, st>>>(w, f, out, H, W, bf, ba, wf, F, rc, theta, out_mode);
+}
+
+int row_stride(int F) { return F > 25 ? 33 : 25; }
 
 }  // namespace
 
 size_t tnrd_bf16_smem_bytes(int F, int J) {
-    const int zs = (F > 25 ? F : 25) | 1;
-    return sizeof(float) * ((size_t)UH * UW + (size_t)NPOS * zs + (size_t)F * (J + 2 * WPAD));
+    return sizeof(float) *
+           ((size_t)UH * UW + (size_t)NPOS * row_stride(F) + (size_t)F * (J + 2 * WPAD));
 }
-
 
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st) {
@@ -244,21 +282,22 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     // fewer tiles than two per CU: 1024 threads per tile
     const bool wide = grid.x * grid.y < 512;
-#define REDVE_STAGE_BF16(KC, NT)                                                             \
-    k_tnrd_stage_bf16<KC, NT><<<grid, NT, smem, st>>>(w_prev, f, out, H, W, bf, ba, wf, d.nfilt, \
-                                                      rc, d.theta[t], out_mode)
+    const bool z33 = row_stride(d.nfilt) == 33;
     if (rc.K == 7) {
-        if (wide)
-            REDVE_STAGE_BF16(7, 1024);
+        if (z33)
+            stage_single<7, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
         else
-            REDVE_STAGE_BF16(7, 512);
+            stage_single<7, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
     } else {
-        if (wide)
-            REDVE_STAGE_BF16(0, 1024);
+        if (z33)
+            stage_single<0, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
         else
-            REDVE_STAGE_BF16(0, 512);
+            stage_single<0, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
     }
-#undef REDVE_STAGE_BF16
 }
 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
@@ -269,14 +308,23 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
     const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
     const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
-    if (rc.K == 7)
-        k_tnrd_stage_bf16_batch<7><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf,
-                                                                ba, wf, d.nfilt, rc, d.theta[t],
-                                                                out_mode);
-    else
-        k_tnrd_stage_bf16_batch<0><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf,
-                                                                ba, wf, d.nfilt, rc, d.theta[t],
-                                                                out_mode);
+#define REDVE_STAGE_BATCH(KC, ZS)                                                          \
+    k_tnrd_stage_bf16_batch<KC, ZS><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf, \
+                                                               ba, wf, d.nfilt, rc,          \
+                                                               d.theta[t], out_mode)
+    const bool z33 = row_stride(d.nfilt) == 33;
+    if (rc.K == 7) {
+        if (z33)
+            REDVE_STAGE_BATCH(7, 33);
+        else
+            REDVE_STAGE_BATCH(7, 25);
+    } else {
+        if (z33)
+            REDVE_STAGE_BATCH(0, 33);
+        else
+            REDVE_STAGE_BATCH(0, 25);
+    }
+#undef REDVE_STAGE_BATCH
 }
 
 }  // namespace redve

@@ -393,6 +393,13 @@ def test_errors(torch):
     with pytest.raises(P.RedveError) as e:
         r.solve(torch.zeros((1, 1), device="cuda"), 1, 1)
     assert e.value.code == P.E_ARG
+    # the BF16 stage's LDS budget: 32 filters of 63 centres exceed it, 24 of 127 fit; FP32 takes both
+    big = W.make_denoiser(stages=1, nfilt=32)
+    with pytest.raises(P.RedveError) as e:
+        r.set_denoiser(big, "bf16")
+    assert e.value.code == P.E_ARG
+    r.set_denoiser(big, "fp32")
+    r.set_denoiser(W.make_denoiser(stages=1, nrbf=127, mu0=-630.0), "bf16")
 
 
 # ------------------------------------------------------------------ mixed precision (BF16 banks)
