@@ -364,6 +364,110 @@ __device__ inline void init_fp_tile(const LinOp& op, const float* __restrict__ x
     __syncthreads();
 }
 
+// init_fp_tile for a separable square PSF of compile-time radius RS (the same sums in the same
+// order), with every global load issued at the start: x on the P region, y at the B region's
+// sampled positions, s at the thread's pixel.
+template <int RS>
+__device__ inline void init_fp_tile_rs(const LinOp& op, const float* __restrict__ x,
+                                       const float* __restrict__ y, const float* __restrict__ s,
+                                       float* __restrict__ r, int H, int W, int r0, int c0,
+                                       InitFpSmem<RS>& sm, float* __restrict__ xo) {
+    static_assert(RS > 0 && NO == 1, "compile-time radius, one pixel per thread");
+    constexpr int SW = InitFpSmem<RS>::S;
+    constexpr int K = 2 * RS + 1;
+    constexpr int ph = TH + 4 * RS, pw = TW + 4 * RS;
+    constexpr int bh = TH + 2 * RS, bw = TW + 2 * RS;
+    constexpr int NX = (ph * pw + kThreads - 1) / kThreads;
+    constexpr int NY = (bh * bw + kThreads - 1) / kThreads;
+    float* sp = sm.sp;
+    double* se = sm.se;
+    double* sh = sm.sh;
+    const int dec = op.decim;
+    const int wy = (W + dec - 1) / dec;
+    float xv[NX], yv[NY];
+    bool ys[NY];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        xv[i] = 0.f;
+        if (e < ph * pw)
+            xv[i] = x[(size_t)wrapi(r0 - 2 * RS + e / pw, H) * W + wrapi(c0 - 2 * RS + e % pw, W)];
+    }
+#pragma unroll
+    for (int i = 0; i < NY; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        ys[i] = false;
+        yv[i] = 0.f;
+        if (e < bh * bw) {
+            const int gr = wrapi(r0 - RS + e / bw, H), gc = wrapi(c0 - RS + e % bw, W);
+            ys[i] = dec == 1 || (gr % dec == 0 && gc % dec == 0);
+            if (ys[i]) yv[i] = y[(size_t)(gr / dec) * wy + gc / dec];
+        }
+    }
+    const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
+    const int gr = r0 + tr, gc = c0 + tc;
+    const bool pix = gr < H && gc < W;
+    const float sv = (s && pix) ? s[(size_t)gr * W + gc] : 0.f;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < ph * pw) sp[(e / pw) * SW + e % pw] = xv[i];
+    }
+    __syncthreads();
+    // B x: row pass over the P rows, then the column pass at the B region (FP64)
+    for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
+        const int pr = e / bw, bc = e % bw;
+        const float* prow = sp + pr * SW + bc + 2 * RS;
+        double a = 0.0;
+#pragma unroll
+        for (int b = 0; b < K; ++b) a += op.row_d[b] * (double)prow[-b];
+        sh[pr * SW + bc] = a;
+    }
+    __syncthreads();
+    // e = S^T (y - S B x) on the tile + r halo
+#pragma unroll
+    for (int i = 0; i < NY; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < bh * bw) {
+            const int br = e / bw, bc = e % bw;
+            double v = 0.0;
+            if (ys[i]) {
+                double bx = 0.0;
+                const double* hcol = sh + (br + 2 * RS) * SW + bc;
+#pragma unroll
+                for (int a = 0; a < K; ++a) bx += op.col_d[a] * hcol[-a * SW];
+                v = (double)yv[i] - bx;
+            }
+            se[br * SW + bc] = v;
+        }
+    }
+    __syncthreads();
+    // B^T e: row pass, then the column pass at the thread's pixel
+    for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
+        const int br = e / TW, c = e % TW;
+        const double* erow = se + br * SW + c;
+        double a = 0.0;
+#pragma unroll
+        for (int b = 0; b < K; ++b) a += op.row_d[b] * erow[b];
+        sh[br * SW + c] = a;
+    }
+    __syncthreads();
+    double bt = 0.0;
+    const double* hcol = sh + tr * SW + tc;
+#pragma unroll
+    for (int a = 0; a < K; ++a) bt += op.col_d[a] * hcol[a * SW];
+    if (pix) {
+        const size_t g = (size_t)gr * W + gc;
+        double rv = op.inv_s2_d * bt;
+        if (s) rv += op.lambda_d * (double)sv;
+        if (xo)  // steepest descent: x - mu g(x) = x + mu r, rounded once
+            xo[g] = (float)((double)sp[(tr + 2 * RS) * SW + tc + 2 * RS] + op.sd_mu * rv);
+        else
+            r[g] = (float)rv;
+    }
+    __syncthreads();
+}
+
 // CG start of one FP call (eq. (7)) in residual form. With rhs = H^T y / sigma^2 + lambda f(x),
 //   r = rhs - A x = H^T (y - H x) / sigma^2 + lambda (f(x) - x),
 // both terms small near the fixed point; the data term is accumulated in FP64 from the FP32
@@ -380,7 +484,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp(const LinOp op, const f
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
         tile_origin(xcd_tile(t, nt), W, r0, c0);
-        init_fp_tile<RS>(op, x, y, s, r, H, W, r0, c0, sm, xo);
+        if constexpr (RS > 0)
+            init_fp_tile_rs<RS>(op, x, y, s, r, H, W, r0, c0, sm, xo);
+        else
+            init_fp_tile<RS>(op, x, y, s, r, H, W, r0, c0, sm, xo);
     }
 }
 
@@ -412,6 +519,23 @@ __global__ __launch_bounds__(kThreads) void k_cg_w0(const LinOp op, const float*
     __shared__ double sred[2 * kThreads / 64];
     double acc[2] = {0.0, 0.0};
     const int nt = ntiles(H, W);
+    if (nt <= (int)gridDim.x) {  // one tile per workgroup: the sums before the store
+        int r0, c0;
+        tile_origin(xcd_tile(blockIdx.x, nt), W, r0, c0);
+        tile_load<RS>(op, H, W, r0, c0, sm, [&](size_t g) { return r[g]; });
+        float pc[NO], q[NO];
+        tile_A_from_lds<RS>(op, H, W, r0, c0, sm, pc, q);
+        const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
+        const bool pix = gr < H && gc < W;
+        if (pix) {
+            acc[0] += (double)pc[0] * (double)pc[0];
+            acc[1] += (double)q[0] * (double)pc[0];
+        }
+        block_sum<2>(acc, sred);
+        if (pix) w[(size_t)gr * W + gc] = q[0];
+        publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+        return;
+    }
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         int r0, c0;
         tile_origin(xcd_tile(t, nt), W, r0, c0);
@@ -756,8 +880,14 @@ __global__ __launch_bounds__(kThreads) void k_cg_init_fp_batch(const ImgDesc* __
     int bt, r0, c0;
     const ImgDesc* d = batch_tile(desc, tiles, bt, r0, c0);
     if (!d) return;
-    init_fp_tile<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr,
-                     sd ? nullptr : r + d->off, d->H, d->W, r0, c0, sm, sd ? d->x_out : nullptr);
+    if constexpr (RS > 0)  // every operator of the batch is padded to this radius
+        init_fp_tile_rs<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr,
+                            sd ? nullptr : r + d->off, d->H, d->W, r0, c0, sm,
+                            sd ? d->x_out : nullptr);
+    else
+        init_fp_tile<RS>(d->op, d->x_in, d->y, sres ? sres + d->off : nullptr,
+                         sd ? nullptr : r + d->off, d->H, d->W, r0, c0, sm,
+                         sd ? d->x_out : nullptr);
 }
 
 template <int RS>
