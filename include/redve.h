@@ -141,7 +141,12 @@ int redve_set_linear_solver(redve_t h, int kind);
  * x0 (device, hx x wx) is the initial vector, or NULL for the default (y when decim = 1,
  * decim^2 H^T y otherwise). x may alias x0. If the budget ends inside a cycle the last FP
  * iterate is returned; a completed cycle returns the extrapolated vector (Algorithm 3).
- * st (host, may be NULL) receives statistics. Synchronises the stream. */
+ * st (host, may be NULL) receives statistics. Returns once the statistics are on the host
+ * (the handle waits for its stream after every pass of the loop); the final copy into x is
+ * queued on the handle's stream, so work on that stream, or a synchronisation of it, sees x.
+ * The observation is copied into the workspace at the start, and each pass of the loop (a
+ * full cycle, or one FP call without extrapolation) is recorded into a HIP graph on first use
+ * and replayed while the handle's settings and the image size are unchanged. */
 int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, float* x, int hx,
                 int wx, redve_stats_t* st);
 

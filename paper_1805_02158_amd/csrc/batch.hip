@@ -290,6 +290,7 @@ struct Engine {
                 op.row[b] = (float)row[b];
             }
         }
+        set_autocorrelations(op);
         sl.op = op;
     }
 

@@ -19,12 +19,27 @@ struct Workspace {
     size_t cap_px = 0;
     int cap_L = 0;
     float *xa, *xb, *xc, *sres, *u0, *u1, *r[2], *w[2], *s[2], *p, *d, *U;
+    float* yw;        // the solve's copy of the observation (captured passes read it)
     double* cg_part;  // two slots of published (rho, mu) partials
     double* cg_hist;  // two slots of (alpha, rho) of the previous CG iteration
     double* ve_part;  // window partials: column j at j * win_stride
     size_t win_stride;
     VeInfo* info;
 };
+
+// A captured pass of the single-image solve loop (a full extrapolation cycle, or one FP call
+// with its relative-change pass), replayed while everything it recorded is unchanged: the
+// start vector, the image size, the workspace, the settings generations, m and the SD step.
+struct PassGraph {
+    hipGraphExec_t exec = nullptr;
+    const float* from = nullptr;
+    float* next = nullptr;  // where the pass leaves its iterate
+    int hx = 0, wx = 0, m = 0;
+    double sd_mu = 0.0;
+    unsigned long long gen = 0, op_gen = 0;
+    const void* arena = nullptr;
+};
+constexpr int kPassGraphs = 4;
 
 struct HostMirror {
     VeInfo info;
@@ -36,6 +51,8 @@ struct HostMirror {
 using redve_detail::kAlign;
 using redve_detail::Workspace;
 using redve_detail::HostMirror;
+using redve_detail::PassGraph;
+using redve_detail::kPassGraphs;
 
 struct redve_ctx {
     int device = 0;
@@ -82,6 +99,11 @@ struct redve_ctx {
     unsigned long long op_gen = 0;         // bumped by set_operator / set_noise / set_lambda
     void* fft = nullptr;                   // Fourier solve plans and tables (fft.hip)
     void (*fft_free)(void*) = nullptr;
+    // captured passes of redve_solve, their capture stream, and whether capture failed once
+    PassGraph pass[kPassGraphs];
+    int pass_next = 0;
+    hipStream_t gstream = nullptr;
+    bool graphs_off = false;
 };
 
 // d = F^-1[F(r0) / A_hat], x_out = x_in + d for periodic deblurring (fft.hip).

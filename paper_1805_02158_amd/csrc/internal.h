@@ -14,6 +14,7 @@ constexpr int kRbfPad = kMaxRbfWindow;  // zeros on both sides of each RBF weigh
 
 constexpr int kMaxRedBlocks = 1024;  // workgroups of any kernel that publishes partial sums
 constexpr int kMaxPsf = 15;
+constexpr int kMaxAc = 17;  // autocorrelation taps of a PSF side of at most 9
 
 // Linear operator H = S B (eq. (1)) and the CG pieces (footnote to eq. (7)). Passed by value:
 // the PSF taps live in kernel-argument registers. A rank-1 PSF (both blurs of the paper's
@@ -30,7 +31,30 @@ struct LinOp {
     double sd_mu;      // step of the steepest-descent base iteration
     float row[kMaxPsf], col[kMaxPsf];
     double row_d[kMaxPsf], col_d[kMaxPsf];
+    // B^T B for a separable square PSF of side <= 9: the separable filter of the
+    // autocorrelations of col and row (2 kh - 1 taps each; see set_autocorrelations)
+    float acr[kMaxAc], acc[kMaxAc];
 };
+
+// acr[j] = sum_b row[b] row[b + j - (kw - 1)], acc likewise from col, j = 0 .. 2 (kw - 1), in
+// FP64 rounded once: (B^T B p)(y) = sum_{i,j} acc[i] acr[j] p(y + (i, j) - (kh - 1, kw - 1))
+// for B = col (x) row. Zero unless the PSF is separable, square and at most 9 x 9.
+inline void set_autocorrelations(LinOp& op) {
+    for (int j = 0; j < kMaxAc; ++j) op.acr[j] = op.acc[j] = 0.f;
+    if (!op.separable || op.kh != op.kw || 2 * op.kh - 1 > kMaxAc) return;
+    const int k = op.kh, r2 = k - 1;
+    for (int j = 0; j <= 2 * r2; ++j) {
+        double sr = 0.0, sc = 0.0;
+        for (int b = 0; b < k; ++b) {
+            const int b2 = b + j - r2;
+            if (b2 < 0 || b2 >= k) continue;
+            sr += op.row_d[b] * op.row_d[b2];
+            sc += op.col_d[b] * op.col_d[b2];
+        }
+        op.acr[j] = (float)sr;
+        op.acc[j] = (float)sc;
+    }
+}
 
 // One image of a batch (batched kernels take a device array of these and a tile list that gives
 // each workgroup a 16x16 tile of an image).
@@ -117,7 +141,8 @@ struct TnrdDev {
     const uint16_t* frag_fwd;   // per stage: 2 x 64 lanes x 8 BF16 forward-bank MFMA operands
     const uint16_t* frag_adj;   // per stage: 2 x 64 lanes x 8 BF16 adjoint-bank MFMA operands
     int precision;
-    int kwin;                   // RBF window half-width: centres beyond it add < 1e-12 w
+    int kwin;                   // RBF window half-width: centres beyond it add < eps w
+                                // (1e-12 for the FP32 form, 1e-6 for BF16)
 };
 
 // ---- launchers (all asynchronous on `st`) ----------------------------------------------

@@ -99,6 +99,37 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
     const int ph = TH + 4 * rh;                    // P region rows
     const int bh = TH + 2 * rh, bw = TW + 2 * rw;  // B P region
     const int s = op.decim;
+    if constexpr (RS > 0) {
+        if (s == 1) {
+            // no decimation: B^T B is separable with the autocorrelations of row and col
+            // (4 RS + 1 taps): a row pass over the P rows at the tile's columns, then the
+            // column pass at the tile
+            constexpr int KA = 4 * RS + 1;
+            for (int e = threadIdx.x; e < ph * TW; e += NTH) {
+                const int pr = e / TW, tc = e % TW;
+                const float* prow = sm.p + pr * SW + tc;
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < KA; ++j) acc += op.acr[j] * prow[j];
+                sm.h[pr * SW + tc] = acc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                const int o = threadIdx.x + k * kThreads;
+                if (NTH > kThreads && o >= TH * TW) break;
+                const int tr = o / TW, tc = o % TW;
+                const float* hcol = sm.h + tr * SW + tc;
+                float acc = 0.f;
+#pragma unroll
+                for (int i = 0; i < KA; ++i) acc += op.acc[i] * hcol[i * SW];
+                pc[k] = sm.p[(tr + 2 * RS) * SW + tc + 2 * RS];
+                q[k] = op.inv_s2 * acc + op.lambda * pc[k];
+            }
+            __syncthreads();
+            return;
+        }
+    }
     if (RS || op.separable) {
         // row pass over all P rows, B columns: h[pr][bc] = sum_b row[b] P[pr][bc + 2rw - b]
         for (int e = threadIdx.x; e < ph * bw; e += NTH) {

@@ -3,11 +3,12 @@
 // evaluated exactly on the 2K+1 centres nearest z. With j0 the nearest centre, d0 = z - mu_j0,
 // c = log2(e) / (2 gamma^2), A = exp2(2 c dmu d0), B = exp2(-c dmu^2), the term of centre
 // j0 + k is w_{j0+k} G0 A^k B^(k^2), G0 = exp2(-c d0^2). Centres farther than K + 1/2
-// spacings add less than 1e-12 of a weight (K = 7 for gamma = dmu).
+// spacings add less than eps of a weight: eps = 1e-12 in the FP32 form (K = 7 for gamma = dmu),
+// 1e-6 in the BF16 form (K = 5), whose operands carry 3.9e-3 relative error.
 //
 // Inside the centre range (|d0| <= dmu / 2): phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w_{j0+m-K} A^m
 // by Horner in A, c_k = B^(k^2) precomputed, the prefactor one exp2 (two exp2 and 2K FMA +
-// 2K+1 multiplies per evaluation). Every intermediate stays below 2^(7 c dmu^2) there. Outside
+// 2K+1 multiplies per evaluation). Every intermediate stays below 2^(K c dmu^2) there. Outside
 // (z beyond the first or last centre) A^2K could overflow, so the terms are built by the
 // two-sided recurrence term(k+1) = term(k) R_k, R_{k+1} = R_k B^2, which stays bounded; past
 // the cut-off (K + 1/2) dmu every term is negligible and the result is 0.

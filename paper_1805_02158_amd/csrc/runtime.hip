@@ -35,6 +35,25 @@ int fail(redve_t h, int code, const std::string& msg) {
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Byte offsets of the workspace arena for cap_px pixels and a window of cap_L.
+struct Layout {
+    static constexpr int kVecs = 15;
+    size_t vec, win_stride, o_cg, o_hist, o_ve, o_info, bytes;
+    Layout(size_t cap_px, int cap_L) {
+        vec = align_up(cap_px * sizeof(float));
+        win_stride = (size_t)(cap_L + 1) * kMaxRedBlocks;
+        bytes = vec * (kVecs + (size_t)cap_L);
+        o_cg = bytes;
+        bytes += align_up(4 * kMaxRedBlocks * sizeof(double));
+        o_hist = bytes;
+        bytes += kAlign;
+        o_ve = bytes;
+        bytes += align_up((size_t)cap_L * win_stride * sizeof(double));
+        o_info = bytes;
+        bytes += align_up(sizeof(VeInfo));
+    }
+};
+
 int ensure_workspace(redve_t h, int hx, int wx, int L) {
     const size_t npx = (size_t)hx * wx;
     Workspace& w = h->ws;
@@ -46,34 +65,24 @@ int ensure_workspace(redve_t h, int hx, int wx, int L) {
     }
     const size_t cap_px = std::max(npx, w.cap_px);
     const int cap_L = std::max(std::max(L, w.cap_L), 1);
-    const size_t vec = align_up(cap_px * sizeof(float));
-    const size_t win_stride = (size_t)(cap_L + 1) * kMaxRedBlocks;
-    constexpr int kVecs = 14;
-    size_t bytes = vec * (kVecs + (size_t)cap_L);
-    const size_t o_cg = bytes;
-    bytes += align_up(4 * kMaxRedBlocks * sizeof(double));
-    const size_t o_hist = bytes;
-    bytes += kAlign;
-    const size_t o_ve = bytes;
-    bytes += align_up((size_t)cap_L * win_stride * sizeof(double));
-    const size_t o_info = bytes;
-    bytes += align_up(sizeof(VeInfo));
+    const Layout lay(cap_px, cap_L);
     void* arena = nullptr;
-    if (hipMalloc(&arena, bytes) != hipSuccess)
-        return fail(h, REDVE_E_NOMEM, "device workspace allocation of " + std::to_string(bytes) +
-                                          " bytes failed");
+    if (hipMalloc(&arena, lay.bytes) != hipSuccess)
+        return fail(h, REDVE_E_NOMEM, "device workspace allocation of " +
+                                          std::to_string(lay.bytes) + " bytes failed");
     char* base = (char*)arena;
-    float** vecs[kVecs] = {&w.xa,   &w.xb,   &w.xc,   &w.sres, &w.u0, &w.u1, &w.r[0],
-                           &w.r[1], &w.w[0], &w.w[1], &w.s[0], &w.s[1], &w.p, &w.d};
-    for (int i = 0; i < kVecs; ++i) *vecs[i] = (float*)(base + vec * i);
-    w.U = (float*)(base + vec * kVecs);
-    w.cg_part = (double*)(base + o_cg);
-    w.cg_hist = (double*)(base + o_hist);
-    w.ve_part = (double*)(base + o_ve);
-    w.win_stride = win_stride;
-    w.info = (VeInfo*)(base + o_info);
+    float** vecs[Layout::kVecs] = {&w.xa,   &w.xb,   &w.xc,   &w.sres, &w.u0,
+                                   &w.u1,   &w.r[0], &w.r[1], &w.w[0], &w.w[1],
+                                   &w.s[0], &w.s[1], &w.p,    &w.d,    &w.yw};
+    for (int i = 0; i < Layout::kVecs; ++i) *vecs[i] = (float*)(base + lay.vec * i);
+    w.U = (float*)(base + lay.vec * Layout::kVecs);
+    w.cg_part = (double*)(base + lay.o_cg);
+    w.cg_hist = (double*)(base + lay.o_hist);
+    w.ve_part = (double*)(base + lay.o_ve);
+    w.win_stride = lay.win_stride;
+    w.info = (VeInfo*)(base + lay.o_info);
     w.arena = arena;
-    w.bytes = bytes;
+    w.bytes = lay.bytes;
     w.cap_px = cap_px;
     w.cap_L = cap_L;
     return REDVE_OK;
@@ -113,6 +122,7 @@ LinOp linop_of(redve_t h) {
         op.row_d[j] = h->row[j];
         op.row[j] = (float)h->row[j];
     }
+    set_autocorrelations(op);
     return op;
 }
 
@@ -266,6 +276,131 @@ float* third(float* a, float* b, float* c, float* not1, float* not2) {
     return c;
 }
 
+// Waits for the handle's stream by polling it: a solve waits once per pass, and a sleeping
+// wait adds the host's wake-up latency to each.
+int wait_stream(redve_t h) {
+    for (;;) {
+        const hipError_t e = hipStreamQuery(h->stream);
+        if (e == hipSuccess) return REDVE_OK;
+        if (e != hipErrorNotReady) return fail(h, REDVE_E_HIP, hipGetErrorString(e));
+    }
+}
+
+// Enqueues one pass of the solve loop from x_cur on h->stream: with extrapolation a full cycle
+// of Algorithm 3 (m + L FP calls, whose last L differences form U, the small solve, and the
+// combination written over x_(m,kappa)); without, one FP call and its relative-change pass.
+// Ends with the copy of VeInfo to the host mirror; *next is where the pass leaves its iterate.
+int enqueue_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float** next) {
+    Workspace& w = h->ws;
+    const int n = hx * wx;
+    int rc;
+    if (h->method == REDVE_VE_NONE) {
+        float* nxt = x_cur == w.xa ? w.xb : w.xa;
+        if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
+        const int nb = launch_diff_gram(nxt, x_cur, nullptr, 0, n, w.ve_part, h->stream);
+        launch_delta(w.ve_part, nb, w.info, h->stream);
+        LAUNCH_CHECK(h);
+        *next = nxt;
+    } else {
+        float* wbase = h->m == 0 ? x_cur : nullptr;
+        float* cur = x_cur;
+        int nblk = 1;
+        for (int i = 0; i < h->m + h->L; ++i) {
+            float* nxt = third(w.xa, w.xb, w.xc, cur, wbase ? wbase : cur);
+            if ((rc = fp_call(h, y, cur, nxt, hx, wx))) return rc;
+            if (i >= h->m) {
+                nblk = launch_diff_gram(nxt, cur, w.U, i - h->m, n,
+                                        w.ve_part + (i - h->m) * w.win_stride, h->stream);
+                LAUNCH_CHECK(h);
+            }
+            cur = nxt;
+            if (i == h->m - 1) wbase = cur;
+        }
+        launch_ve_solve(w.ve_part, w.win_stride, nblk, h->L, h->method, h->rank_eps, w.info,
+                        h->stream);
+        launch_ve_combine(wbase, w.U, n, w.info, wbase, h->stream);
+        LAUNCH_CHECK(h);
+        *next = wbase;
+    }
+    HIP_TRY(h, hipMemcpyAsync(&h->host->info, w.info, sizeof(VeInfo), hipMemcpyDeviceToHost,
+                              h->stream));
+    return REDVE_OK;
+}
+
+// Captures enqueue_pass into a graph on the handle's capture stream (the null stream cannot
+// be captured). On a capture failure graphs stay off for the handle and the caller enqueues
+// the pass itself.
+int capture_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, PassGraph& g) {
+    if (!h->gstream && hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking) != hipSuccess) {
+        h->gstream = nullptr;
+        return REDVE_E_HIP;
+    }
+    hipStream_t user = h->stream;
+    h->stream = h->gstream;
+    if (hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        h->stream = user;
+        return REDVE_E_HIP;
+    }
+    float* next = nullptr;
+    const int rc = enqueue_pass(h, y, x_cur, hx, wx, &next);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->gstream, &graph);
+    h->stream = user;
+    hipGraphExec_t exec = nullptr;
+    const bool ok = rc == REDVE_OK && ec == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) hipGraphDestroy(graph);
+    if (!ok) {
+        (void)hipGetLastError();
+        return rc ? rc : REDVE_E_HIP;
+    }
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    g.exec = exec;
+    g.from = x_cur;
+    g.next = next;
+    g.hx = hx;
+    g.wx = wx;
+    g.m = h->m;
+    g.sd_mu = h->sd_mu;
+    g.gen = h->gen;
+    g.op_gen = h->op_gen;
+    g.arena = h->ws.arena;
+    return REDVE_OK;
+}
+
+// Runs one pass from x_cur (replaying its captured graph, capturing it on first use) and
+// waits for it; the host mirror then holds its VeInfo.
+int run_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float** next) {
+    PassGraph* g = nullptr;
+    if (!h->graphs_off && h->lin == REDVE_LIN_CG) {
+        for (auto& e : h->pass)
+            if (e.exec && e.from == x_cur && e.hx == hx && e.wx == wx && e.m == h->m &&
+                e.sd_mu == h->sd_mu && e.gen == h->gen && e.op_gen == h->op_gen &&
+                e.arena == h->ws.arena)
+                g = &e;
+        if (!g) {
+            PassGraph& slot = h->pass[h->pass_next];
+            const int rc = capture_pass(h, y, x_cur, hx, wx, slot);
+            if (rc == REDVE_OK) {
+                g = &slot;
+                h->pass_next = (h->pass_next + 1) % kPassGraphs;
+            } else if (rc == REDVE_E_HIP) {
+                h->graphs_off = true;
+            } else {
+                return rc;
+            }
+        }
+    }
+    if (g) {
+        HIP_TRY(h, hipGraphLaunch(g->exec, h->stream));
+        *next = g->next;
+    } else {
+        const int rc = enqueue_pass(h, y, x_cur, hx, wx, next);
+        if (rc) return rc;
+    }
+    return wait_stream(h);
+}
+
 struct Progress {
     double last = -1.0;
     int grow = 0;
@@ -319,6 +454,9 @@ int redve_destroy(redve_t h) {
     hipFree(h->d_rbfw);
     hipFree(h->d_frag);
     if (h->bstream) hipStreamDestroy(h->bstream);
+    for (auto& g : h->pass)
+        if (g.exec) hipGraphExecDestroy(g.exec);
+    if (h->gstream) hipStreamDestroy(h->gstream);
     hipHostFree(h->host);
     delete h;
     return REDVE_OK;
@@ -334,8 +472,7 @@ const char* redve_last_error(redve_t h) { return h ? h->err.c_str() : "null hand
 
 size_t redve_workspace_bytes(redve_t h, int hx, int wx) {
     if (!h || hx <= 0 || wx <= 0) return 0;
-    const size_t vec = align_up((size_t)hx * wx * sizeof(float));
-    return vec * (14 + (size_t)std::max(h->L, 1)) + 64 * 1024;
+    return Layout((size_t)hx * wx, std::max(h->L, 1)).bytes;
 }
 
 int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim) {
@@ -449,7 +586,11 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     h->dmu = p->dmu;
     h->gamma = p->gamma;
     h->precision = p->precision;
-    h->kwin = p->stages > 0 ? std::max(1, (int)ceil(7.4338 * p->gamma / p->dmu - 0.5)) : 1;
+    // RBF window: the centres beyond (K + 1/2) dmu from z add less than eps of a weight each,
+    // (K + 1/2) dmu / gamma >= sqrt(2 ln(1/eps)): eps = 1e-12 for the FP32 form (7.4338), and
+    // 1e-6 for the BF16 form (5.2565), far below the BF16 operands' own 3.9e-3
+    const double reach = p->precision == REDVE_PREC_BF16 ? 5.2565 : 7.4338;
+    h->kwin = p->stages > 0 ? std::max(1, (int)ceil(reach * p->gamma / p->dmu - 0.5)) : 1;
     h->theta.assign(h->T, 0.f);
     if (h->T > 0) {
         // weights as rows of J + 2 kRbfPad, zero-padded both sides (the stage kernels copy
@@ -685,22 +826,23 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
         LAUNCH_CHECK(h);
     }
 
+    // the passes read the observation from the workspace, so a captured pass serves any y
+    HIP_TRY(h, hipMemcpyAsync(w.yw, y, sizeof(float) * (size_t)hy * wy, hipMemcpyDeviceToDevice,
+                              h->stream));
+    const float* yw = w.yw;
+
     int calls = 0, cycles = 0, breakdowns = 0, status = REDVE_OK;
     double delta = INFINITY, gl1max = 0.0;
     Progress prog;
     float* x_cur = w.xa;
 
     if (h->method == REDVE_VE_NONE) {
-        float* nxt = w.xb;
         while (calls < h->max_fp) {
-            if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
+            float* nxt = nullptr;
+            if ((rc = run_pass(h, yw, x_cur, hx, wx, &nxt))) return rc;
             ++calls;
-            const int nb = launch_diff_gram(nxt, x_cur, nullptr, 0, n, w.ve_part, h->stream);
-            launch_delta(w.ve_part, nb, w.info, h->stream);
-            LAUNCH_CHECK(h);
-            if ((rc = read_back(h))) return rc;
             delta = sqrt(h->host->info.uu / h->host->info.xx);
-            std::swap(x_cur, nxt);
+            x_cur = nxt;
             if ((status = prog.check(delta))) break;
             if (delta < h->tol) break;
         }
@@ -708,38 +850,24 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
         // Algorithm 3 (full cycling): m FP calls, then L = kappa+1 more whose differences form
         // U; extrapolate (Algorithm 1) and restart from x_(m,kappa).
         while (calls < h->max_fp) {
-            float* base = x_cur;  // x_0 of this cycle
-            int nblk = 1;
-            float* wbase = nullptr;
-            float* cur = base;
-            bool early = false;
-            if (h->m == 0) wbase = base;
-            for (int i = 0; i < h->m + L; ++i) {
-                if (calls >= h->max_fp) {
-                    early = true;
-                    break;
+            if (calls + h->m + L > h->max_fp) {
+                // the FP-call budget ends inside this cycle: its FP calls, no extrapolation
+                float* wbase = h->m == 0 ? x_cur : nullptr;
+                float* cur = x_cur;
+                for (int i = 0; i < h->m + L && calls < h->max_fp; ++i) {
+                    float* nxt = third(w.xa, w.xb, w.xc, cur, wbase ? wbase : cur);
+                    if ((rc = fp_call(h, yw, cur, nxt, hx, wx))) return rc;
+                    ++calls;
+                    cur = nxt;
+                    if (i == h->m - 1) wbase = cur;
                 }
-                float* nxt = third(w.xa, w.xb, w.xc, cur, wbase ? wbase : cur);
-                if ((rc = fp_call(h, y, cur, nxt, hx, wx))) return rc;
-                ++calls;
-                if (i >= h->m) {
-                    nblk = launch_diff_gram(nxt, cur, w.U, i - h->m, n,
-                                            w.ve_part + (i - h->m) * w.win_stride, h->stream);
-                    LAUNCH_CHECK(h);
-                }
-                cur = nxt;
-                if (i == h->m - 1) wbase = cur;
-            }
-            if (early) {
                 x_cur = cur;
                 break;
             }
-            launch_ve_solve(w.ve_part, w.win_stride, nblk, L, h->method, h->rank_eps, w.info,
-                            h->stream);
-            launch_ve_combine(wbase, w.U, n, w.info, wbase, h->stream);
-            LAUNCH_CHECK(h);
-            x_cur = wbase;
-            if ((rc = read_back(h))) return rc;
+            float* next = nullptr;
+            if ((rc = run_pass(h, yw, x_cur, hx, wx, &next))) return rc;
+            calls += h->m + L;
+            x_cur = next;
             ++cycles;
             if (h->host->info.breakdown)
                 ++breakdowns;
@@ -757,13 +885,13 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     if (status == REDVE_OK) {
         for (int e = 0; e < h->extra_fp; ++e) {
             float* nxt = third(w.xa, w.xb, w.xc, x_cur, x_cur);
-            if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
+            if ((rc = fp_call(h, yw, x_cur, nxt, hx, wx))) return rc;
             ++calls;
             x_cur = nxt;
         }
     }
+    // the result is queued in stream order; the statistics are already on the host
     HIP_TRY(h, hipMemcpyAsync(x, x_cur, bytes, hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (st) {
         st->fp_calls = calls;
         st->cycles = cycles;

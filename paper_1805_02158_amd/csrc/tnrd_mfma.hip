@@ -283,7 +283,14 @@ void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
     // fewer tiles than two per CU: 1024 threads per tile
     const bool wide = grid.x * grid.y < 512;
     const bool z33 = row_stride(d.nfilt) == 33;
-    if (rc.K == 7) {
+    if (rc.K == 5) {  // the BF16 form's window for gamma = dmu
+        if (z33)
+            stage_single<5, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
+        else
+            stage_single<5, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
+                                rc, d.theta[t], out_mode);
+    } else if (rc.K == 7) {
         if (z33)
             stage_single<7, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
                                 rc, d.theta[t], out_mode);
@@ -313,7 +320,12 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                                                ba, wf, d.nfilt, rc,          \
                                                                d.theta[t], out_mode)
     const bool z33 = row_stride(d.nfilt) == 33;
-    if (rc.K == 7) {
+    if (rc.K == 5) {
+        if (z33)
+            REDVE_STAGE_BATCH(5, 33);
+        else
+            REDVE_STAGE_BATCH(5, 25);
+    } else if (rc.K == 7) {
         if (z33)
             REDVE_STAGE_BATCH(7, 33);
         else
