@@ -19,8 +19,9 @@ struct Workspace {
     size_t cap_px = 0;
     int cap_L = 0;
     float *xa, *xb, *xc, *sres, *u0, *u1, *r[2], *w[2], *s[2], *p, *d, *U;
+    float *a[2], *b[2];  // A w and A s of the two-iteration CG kernels
     float* yw;        // the solve's copy of the observation (captured passes read it)
-    double* cg_part;  // two slots of published (rho, mu) partials
+    double* cg_part;  // two slots of published CG partials, kCgSums arrays each
     double* cg_hist;  // two slots of (alpha, rho) of the previous CG iteration
     double* ve_part;  // window partials: column j at j * win_stride
     size_t win_stride;

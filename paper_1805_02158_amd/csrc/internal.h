@@ -175,6 +175,19 @@ void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const fl
 // w0 = A r0; publishes r0.r0 and w0.r0.
 Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, double* part,
                       hipStream_t st);
+// Two CG iterations per kernel for an undecimated, separable, square PSF of side 7 or 9 (see
+// linear.hip): cg_block_ok says whether they apply to iters iterations on an H x W image.
+// The block start writes w_0 = A r_0, a_0 = A w_0 and publishes nine Gram sums of
+// [r, w, s, a, b] (entry 0 rho, entry 1 mu, so a single iteration can follow); a block takes
+// iterations k and k + 1.
+constexpr int kCgSums = 16;  // partial arrays per CG slot
+bool cg_block_ok(const LinOp& op, int iters, int H, int W);
+Partials launch_cg_w0_block(const LinOp& op, const float* r, float* w, float* a, int H, int W,
+                            double* part, hipStream_t st);
+Partials launch_cg_block(const LinOp& op, int H, int W, int k, const float* const* vin,
+                         float* const* vout, float* p, float* d, Partials rm,
+                         const double* hist_prev, double* hist_cur, double* part,
+                         hipStream_t st);
 // One single-reduction CG iteration k (see linear.hip); hist_prev holds (alpha, rho) of
 // iteration k-1, hist_cur receives those of iteration k. The last iteration writes
 // x_out = x_in + d only.

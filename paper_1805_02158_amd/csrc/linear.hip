@@ -21,6 +21,7 @@ constexpr int TH = 16, TW = 16;  // CG tile: 256 outputs per 256-thread workgrou
 constexpr int MAXR = (kMaxPsf - 1) / 2;
 constexpr int PH = TH + 4 * MAXR, PW = TW + 4 * MAXR;
 constexpr int NO = TH * TW / kThreads;  // outputs per thread
+constexpr int kWideThreadsBlk = 1024;  // threads of the two-iteration CG kernels
 
 // i mod n in [0, n). Stencil indexes are at most one period outside [0, n) unless the image
 // is smaller than the halo; only then is the division needed.
@@ -586,8 +587,12 @@ __device__ inline void cg_scalars(int k, double rho, double mu, double alpha_pre
         if (k == 0) {
             alpha = mu > 0.0 ? rho / mu : 0.0;
         } else {
-            beta = rho_prev > 1e-300 ? rho / rho_prev : 0.0;
-            const double den = alpha_prev != 0.0 ? mu - beta * rho / alpha_prev : 0.0;
+            // beta rho / alpha_prev as rho^2 / (rho_prev alpha_prev): two divisions in parallel,
+            // then the third
+            const bool prev = rho_prev > 1e-300;
+            beta = prev ? rho / rho_prev : 0.0;
+            const double t = prev && alpha_prev != 0.0 ? (rho * rho) / (rho_prev * alpha_prev) : 0.0;
+            const double den = alpha_prev != 0.0 ? mu - t : 0.0;
             alpha = den > 0.0 ? rho / den : 0.0;
         }
     }
@@ -1018,6 +1023,350 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
     publish<2>(acc, part, cap, bt);
 }
 
+// ---- two CG iterations per kernel (undecimated, separable square PSF) --------------------
+//
+// The single-reduction iteration above needs one grid-wide sum per iteration. Two iterations
+// k, k+1 need only the sums available at k if the kernel also carries a = A w and b = A s:
+// with V = [r_k, w_k, s_{k-1}, a_k, b_{k-1}] (w = A r, s = A p, a = A w, b = A s) and G its
+// Gram matrix,
+//   s_k = w + beta_{k-1} s,  A s_k = a + beta_{k-1} b,
+//   r_{k+1} = r - alpha_k s_k,  w_{k+1} = w - alpha_k A s_k        (linear in V)
+//   rho_{k+1} = r_{k+1}.r_{k+1},  mu_{k+1} = w_{k+1}.r_{k+1}      (quadratic forms in G)
+// give alpha_{k+1} and beta_k without a second sum, then
+//   s_{k+1} = w_{k+1} + beta_k s_k,  r_{k+2} = r_{k+1} - alpha_{k+1} s_{k+1}   (linear in V)
+//   p_k = r_k + beta_{k-1} p_{k-1},  p_{k+1} = r_{k+1} + beta_k p_k,
+//   d_{k+2} = d_k + alpha_k p_k + alpha_{k+1} p_{k+1},
+// and the stencils w_{k+2} = A r_{k+2}, a_{k+2} = A w_{k+2}, b_{k+1} = A s_{k+1} complete the
+// next V, whose Gram sums are the kernel's only reduction. rho_{k+1} and mu_{k+1} use nine of
+// them, with r.a = w.w, r.b = w.s and w.b = a.s (A symmetric): r.r, w.r, w.w, s.r, s.w, s.s,
+// a.w, a.s, b.s, stored in that order (entry 0 is rho = r.r, entry 1 mu = w.r, so the
+// single-iteration kernel can follow a block). In exact arithmetic the iterates are those of
+// CG; with FP32 vectors and FP64 sums the rounding is of the same size. A is applied in the
+// autocorrelation form (a row pass and a column pass of 4 RS + 1 taps), so r_{k+2} is formed
+// on the tile plus a 4 RS halo, and s_{k+1}, w_{k+2} on a 2 RS halo.
+constexpr int kGram = 9;
+enum GramEntry { G_RR, G_WR, G_WW, G_SR, G_SW, G_SS, G_AW, G_AS, G_BS };
+
+template <int RS>
+struct BlkSmem {
+    static constexpr int RH = TH + 8 * RS, RW = TW + 8 * RS;  // r_{k+2} region
+    static constexpr int QH = TH + 4 * RS, QW = TW + 4 * RS;  // s_{k+1}, w_{k+2} regions
+    float R[RH * RW];
+    float hR[RH * QW];
+    float Wn[QH * QW];
+    float S[QH * QW];
+    float hS[QH * TW];
+    float hw[QH * TW];
+    float Bn[TH * TW];
+    float An[TH * TW];
+};
+
+// Row pass of B^T B over the rows of X (nr rows, stride xs) at nc output columns:
+// out[r][c] = sum_j acr[j] X[r][c + j].
+template <int RS, int NTH>
+__device__ inline void ac_rows(const LinOp& op, const float* X, int xs, int nr, int nc,
+                               float* out) {
+    constexpr int KA = 4 * RS + 1;
+    for (int e = threadIdx.x; e < nr * nc; e += NTH) {
+        const int r = e / nc, c = e % nc;
+        const float* x = X + r * xs + c;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < KA; ++j) acc += op.acr[j] * x[j];
+        out[r * nc + c] = acc;
+    }
+}
+
+// Column pass completing A = B^T B / sigma^2 + lambda I at an nr x nc region: h holds the row
+// pass (stride nc, nr + 4 RS rows), X the input (stride xs) whose point (r, c) of the output
+// sits at X[r + 2 RS][c + 2 RS].
+template <int RS, int NTH>
+__device__ inline void ac_cols(const LinOp& op, const float* h, const float* X, int xs, int nr,
+                               int nc, float* out) {
+    constexpr int KA = 4 * RS + 1;
+    for (int e = threadIdx.x; e < nr * nc; e += NTH) {
+        const int r = e / nc, c = e % nc;
+        const float* hc = h + r * nc + c;
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < KA; ++i) acc += op.acc[i] * hc[i * nc];
+        out[r * nc + c] = op.inv_s2 * acc + op.lambda * X[(r + 2 * RS) * xs + c + 2 * RS];
+    }
+}
+
+// The published Gram sums: wave v < kGram sums array v, in partial order (as consume2). For at most
+// kEarlyPartials partials the loads are issued first (gram_issue, before the tile's loads) and
+// summed later (gram_finish); beyond that gram_finish loads them itself.
+struct GramEarly {
+    double a[4];
+};
+
+template <int NTH>
+__device__ inline void gram_issue(const double* part, int n, GramEarly& q) {
+    static_assert(NTH / 64 >= kGram, "one wave per Gram entry");
+    const int v = threadIdx.x >> 6;
+    if (v < kGram && n <= kEarlyPartials) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = (threadIdx.x & 63) + 64 * i;
+            q.a[i] = j < n ? part[(size_t)v * kMaxRedBlocks + j] : 0.0;
+        }
+    }
+}
+
+template <int NTH>
+__device__ inline void gram_finish(const double* part, int n, const GramEarly& q,
+                                   double* bc /* kGram */) {
+    const int v = threadIdx.x >> 6;
+    if (v < kGram) {
+        double s = 0.0;
+        if (n <= kEarlyPartials) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += q.a[i];
+        } else {
+            for (int i = threadIdx.x & 63; i < n; i += 64) s += part[(size_t)v * kMaxRedBlocks + i];
+        }
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) bc[v] = s;
+    }
+    __syncthreads();
+}
+
+// Scalars of the two iterations from G, and the coefficient rows over V of r_{k+1}, s_{k+1},
+// r_{k+2}.
+struct BlkScalars {
+    double a0, b1, a1, b2, rho1;
+    float cr1[5], cs1[5], cr2[5];
+};
+
+__device__ inline BlkScalars blk_scalars(int k, const double* G, double alpha_prev,
+                                         double rho_prev) {
+    BlkScalars q;
+    cg_scalars(k, G[0], G[1], alpha_prev, rho_prev, q.a0, q.b1);
+    // r_{k+1} = r - x w - y s, w_{k+1} = w - x a - y b with x = alpha_k, y = alpha_k beta_{k-1}
+    const double x = q.a0, y = q.a0 * q.b1;
+    const double rho1 = (G[G_RR] - 2.0 * (x * G[G_WR] + y * G[G_SR])) +
+                        (x * x * G[G_WW] + 2.0 * x * y * G[G_SW] + y * y * G[G_SS]);
+    const double mu1 = (G[G_WR] - x * G[G_WW] - y * G[G_SW]) -
+                       x * (G[G_WW] - x * G[G_AW] - y * G[G_AS]) -
+                       y * (G[G_SW] - x * G[G_AS] - y * G[G_BS]);
+    const double c1[5] = {1.0, -x, -y, 0.0, 0.0};
+    q.rho1 = rho1;
+    cg_scalars(k + 1, rho1, mu1, q.a0, G[0], q.a1, q.b2);
+    const double cs[5] = {0.0, 1.0 + q.b2, q.b2 * q.b1, -q.a0, -q.a0 * q.b1};
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        q.cr1[i] = (float)c1[i];
+        q.cs1[i] = (float)cs[i];
+        q.cr2[i] = (float)(c1[i] - q.a1 * cs[i]);
+    }
+    return q;
+}
+
+// V on the r_{k+2} region of one tile (NE positions per thread), and V, p, d at the pixel.
+template <int RS, int NTH>
+struct BlkIn {
+    static constexpr int RH = TH + 8 * RS, RW = TW + 8 * RS;
+    static constexpr int NE = (RH * RW + NTH - 1) / NTH;
+    float v[NE][5];
+    float vo[5], po, dn;
+};
+
+template <int RS, int NTH>
+__device__ inline void blk_fetch(int H, int W, int r0, int c0, int k, const float* const* vin,
+                                 const float* __restrict__ p, const float* __restrict__ d,
+                                 BlkIn<RS, NTH>& f) {
+    using C = BlkIn<RS, NTH>;
+    const int nv = k ? 5 : 4;  // s_{-1} = b_{-1} = 0: the loads of s and b are skipped at k = 0
+#pragma unroll
+    for (int i = 0; i < C::NE; ++i) {
+        const int e = threadIdx.x + i * NTH;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) f.v[i][j] = 0.f;
+        if (e < C::RH * C::RW) {
+            const size_t g = (size_t)wrapi(r0 - 4 * RS + e / C::RW, H) * W +
+                             wrapi(c0 - 4 * RS + e % C::RW, W);
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                if (j != 2 && j != 4 ? true : nv == 5) f.v[i][j] = vin[j][g];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) f.vo[j] = 0.f;
+    f.po = f.dn = 0.f;
+    const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
+    if ((int)threadIdx.x < TH * TW && gr < H && gc < W) {
+        const size_t g = (size_t)gr * W + gc;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (j != 2 && j != 4 ? true : nv == 5) f.vo[j] = vin[j][g];
+        if (k) {
+            f.po = p[g];
+            f.dn = d[g];
+        }
+    }
+}
+
+// Two CG iterations k, k + 1 on one tile (see above); accumulates the Gram matrix of the next
+// V at the tile's pixels.
+template <int RS, int NTH>
+__device__ inline void blk_tile(const LinOp& op, int H, int W, int r0, int c0,
+                                const BlkScalars& q, const BlkIn<RS, NTH>& f,
+                                float* const* vout, float* __restrict__ p, float* __restrict__ d,
+                                BlkSmem<RS>& sm, double (&g)[kGram]) {
+    using M = BlkSmem<RS>;
+    using C = BlkIn<RS, NTH>;
+    // r_{k+2} on the whole region, s_{k+1} on its inner 2 RS halo
+#pragma unroll
+    for (int i = 0; i < C::NE; ++i) {
+        const int e = threadIdx.x + i * NTH;
+        if (e < M::RH * M::RW) {
+            const int rr = e / M::RW, rc = e % M::RW;
+            float rv = 0.f, sv = 0.f;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                rv += q.cr2[j] * f.v[i][j];
+                sv += q.cs1[j] * f.v[i][j];
+            }
+            sm.R[e] = rv;
+            const int qr = rr - 2 * RS, qc = rc - 2 * RS;
+            if (qr >= 0 && qr < M::QH && qc >= 0 && qc < M::QW) sm.S[qr * M::QW + qc] = sv;
+        }
+    }
+    __syncthreads();
+    ac_rows<RS, NTH>(op, sm.R, M::RW, M::RH, M::QW, sm.hR);
+    ac_rows<RS, NTH>(op, sm.S, M::QW, M::QH, TW, sm.hS);
+    __syncthreads();
+    ac_cols<RS, NTH>(op, sm.hR, sm.R, M::RW, M::QH, M::QW, sm.Wn);  // w_{k+2} = A r_{k+2}
+    ac_cols<RS, NTH>(op, sm.hS, sm.S, M::QW, TH, TW, sm.Bn);        // b_{k+1} = A s_{k+1}
+    __syncthreads();
+    ac_rows<RS, NTH>(op, sm.Wn, M::QW, M::QH, TW, sm.hw);
+    __syncthreads();
+    ac_cols<RS, NTH>(op, sm.hw, sm.Wn, M::QW, TH, TW, sm.An);  // a_{k+2} = A w_{k+2}
+    __syncthreads();
+    const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
+    const int gr = r0 + tr, gc = c0 + tc;
+    if ((int)threadIdx.x < TH * TW && gr < H && gc < W) {
+        const size_t gi = (size_t)gr * W + gc;
+        float r1 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) r1 += q.cr1[j] * f.vo[j];
+        const float pk = f.vo[0] + (float)q.b1 * f.po;
+        const float pk1 = r1 + (float)q.b2 * pk;
+        const float dn = f.dn + (float)q.a0 * pk + (float)q.a1 * pk1;
+        const float v[5] = {sm.R[(tr + 4 * RS) * M::RW + tc + 4 * RS],
+                            sm.Wn[(tr + 2 * RS) * M::QW + tc + 2 * RS],
+                            sm.S[(tr + 2 * RS) * M::QW + tc + 2 * RS], sm.An[tr * TW + tc],
+                            sm.Bn[tr * TW + tc]};
+#pragma unroll
+        for (int i = 0; i < 5; ++i) vout[i][gi] = v[i];
+        const double dr = v[0], dw = v[1], ds = v[2], da = v[3], db = v[4];
+        g[G_RR] += dr * dr;
+        g[G_WR] += dw * dr;
+        g[G_WW] += dw * dw;
+        g[G_SR] += ds * dr;
+        g[G_SW] += ds * dw;
+        g[G_SS] += ds * ds;
+        g[G_AW] += da * dw;
+        g[G_AS] += da * ds;
+        g[G_BS] += db * ds;
+        p[gi] = pk1;
+        d[gi] = dn;
+    }
+    __syncthreads();
+}
+
+// Pointers of V = [r, w, s, a, b] (kernel argument).
+struct VecSet {
+    const float* in[5];
+    float* out[5];
+};
+
+template <int RS>
+__global__ __launch_bounds__(kWideThreadsBlk) void k_cg_block(
+    const LinOp op, int H, int W, int k, VecSet vs, float* __restrict__ p, float* __restrict__ d,
+    Partials rm, const double* __restrict__ hist_prev, double* __restrict__ hist_cur,
+    double* __restrict__ part) {
+    constexpr int NTH = kWideThreadsBlk;
+    __shared__ BlkSmem<RS> sm;
+    __shared__ double sred[kGram * (TH * TW / 64)];
+    __shared__ double bc[kGram];
+    const int nt = ntiles(H, W);
+    GramEarly early;
+    gram_issue<NTH>(rm.p, rm.n, early);
+    const double alpha_prev = k ? hist_prev[0] : 0.0, rho_prev = k ? hist_prev[1] : 0.0;
+    int r0 = 0, c0 = 0;
+    BlkIn<RS, NTH> f;
+    if ((int)blockIdx.x < nt) {
+        tile_origin(xcd_tile(blockIdx.x, nt), W, r0, c0);
+        blk_fetch<RS, NTH>(H, W, r0, c0, k, vs.in, p, d, f);
+    }
+    gram_finish<NTH>(rm.p, rm.n, early, bc);
+    const BlkScalars q = blk_scalars(k, bc, alpha_prev, rho_prev);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hist_cur[0] = q.a1;
+        hist_cur[1] = q.rho1;
+    }
+    double g[kGram];
+#pragma unroll
+    for (int i = 0; i < kGram; ++i) g[i] = 0.0;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
+        if (t != (int)blockIdx.x) blk_fetch<RS, NTH>(H, W, r0, c0, k, vs.in, p, d, f);
+        blk_tile<RS, NTH>(op, H, W, r0, c0, q, f, vs.out, p, d, sm, g);
+    }
+    block_sum_publish<kGram, NTH, TH * TW>(g, sred, part, kMaxRedBlocks, blockIdx.x);
+}
+
+// Block start at k = 0: from r_0, w_0 = A r_0 and a_0 = A w_0 on the tile and the Gram sums
+// of V_0 = [r_0, w_0, 0, a_0, 0] (s_{-1} = b_{-1} = 0).
+template <int RS>
+__global__ __launch_bounds__(kWideThreadsBlk) void k_cg_w0_block(
+    const LinOp op, int H, int W, const float* __restrict__ r, float* __restrict__ w,
+    float* __restrict__ a, double* __restrict__ part) {
+    constexpr int NTH = kWideThreadsBlk;
+    using M = BlkSmem<RS>;
+    __shared__ BlkSmem<RS> sm;
+    __shared__ double sred[kGram * (TH * TW / 64)];
+    const int nt = ntiles(H, W);
+    double g[kGram];
+#pragma unroll
+    for (int i = 0; i < kGram; ++i) g[i] = 0.0;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        int r0, c0;
+        tile_origin(xcd_tile(t, nt), W, r0, c0);
+        // w_0 = A r_0 is needed on the tile plus 2 RS (for a_0): r_0 on 4 RS
+        for (int e = threadIdx.x; e < M::RH * M::RW; e += NTH)
+            sm.R[e] = r[(size_t)wrapi(r0 - 4 * RS + e / M::RW, H) * W +
+                        wrapi(c0 - 4 * RS + e % M::RW, W)];
+        __syncthreads();
+        ac_rows<RS, NTH>(op, sm.R, M::RW, M::RH, M::QW, sm.hR);
+        __syncthreads();
+        ac_cols<RS, NTH>(op, sm.hR, sm.R, M::RW, M::QH, M::QW, sm.Wn);
+        __syncthreads();
+        ac_rows<RS, NTH>(op, sm.Wn, M::QW, M::QH, TW, sm.hw);
+        __syncthreads();
+        ac_cols<RS, NTH>(op, sm.hw, sm.Wn, M::QW, TH, TW, sm.An);
+        __syncthreads();
+        const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
+        const int gr = r0 + tr, gc = c0 + tc;
+        if ((int)threadIdx.x < TH * TW && gr < H && gc < W) {
+            const size_t gi = (size_t)gr * W + gc;
+            const float rv = sm.R[(tr + 4 * RS) * M::RW + tc + 4 * RS];
+            const float wv = sm.Wn[(tr + 2 * RS) * M::QW + tc + 2 * RS];
+            const float av = sm.An[tr * TW + tc];
+            w[gi] = wv;
+            a[gi] = av;
+            g[G_RR] += (double)rv * rv;
+            g[G_WR] += (double)wv * rv;
+            g[G_WW] += (double)wv * wv;
+            g[G_AW] += (double)av * wv;
+        }
+        __syncthreads();
+    }
+    block_sum_publish<kGram, NTH, TH * TW>(g, sred, part, kMaxRedBlocks, blockIdx.x);
+}
+
 inline int ntiles_host(int H, int W) { return ((H + TH - 1) / TH) * ((W + TW - 1) / TW); }
 
 inline int tile_blocks(int H, int W) {
@@ -1112,6 +1461,42 @@ Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, d
         k_cg_w0<3><<<g, kThreads, 0, st>>>(op, r, w, H, W, part);
     else
         k_cg_w0<0><<<g, kThreads, 0, st>>>(op, r, w, H, W, part);
+    return Partials{part, g};
+}
+
+bool cg_block_ok(const LinOp& op, int iters, int H, int W) {
+    // small images only: there the per-kernel latency dominates; on large ones the wider
+    // halos of the two-iteration kernel cost more than the launch they save
+    return op.decim == 1 && op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9) &&
+           iters >= 3 && ntiles_host(H, W) < kWideBelowTiles;
+}
+
+Partials launch_cg_w0_block(const LinOp& op, const float* r, float* w, float* a, int H, int W,
+                            double* part, hipStream_t st) {
+    const int g = tile_blocks(H, W);
+    if (op.kh == 9)
+        k_cg_w0_block<4><<<g, kWideThreadsBlk, 0, st>>>(op, H, W, r, w, a, part);
+    else
+        k_cg_w0_block<3><<<g, kWideThreadsBlk, 0, st>>>(op, H, W, r, w, a, part);
+    return Partials{part, g};
+}
+
+Partials launch_cg_block(const LinOp& op, int H, int W, int k, const float* const* vin,
+                         float* const* vout, float* p, float* d, Partials rm,
+                         const double* hist_prev, double* hist_cur, double* part,
+                         hipStream_t st) {
+    const int g = tile_blocks(H, W);
+    VecSet vs;
+    for (int j = 0; j < 5; ++j) {
+        vs.in[j] = vin[j];
+        vs.out[j] = vout[j];
+    }
+    if (op.kh == 9)
+        k_cg_block<4><<<g, kWideThreadsBlk, 0, st>>>(op, H, W, k, vs, p, d, rm, hist_prev,
+                                                     hist_cur, part);
+    else
+        k_cg_block<3><<<g, kWideThreadsBlk, 0, st>>>(op, H, W, k, vs, p, d, rm, hist_prev,
+                                                     hist_cur, part);
     return Partials{part, g};
 }
 

@@ -66,6 +66,33 @@ __device__ inline void block_sum(double (&v)[NV], double* scratch /* NV * NACT/6
     __syncthreads();
 }
 
+// block_sum and publish of many values at once: the active waves' DPP sums of all NV values
+// go to LDS, then thread v < NV of the first wave sums value v over the waves (in wave order,
+// as block_sum) and writes it to part[v * stride + blk].
+template <int NV, int NTH, int NACT>
+__device__ inline void block_sum_publish(const double (&v)[NV], double* scratch /* NV * NACT/64 */,
+                                         double* part, int stride, int blk) {
+    constexpr int NW = NACT / 64;
+    static_assert(NACT % 64 == 0 && NACT <= NTH && NV <= 64, "active waves");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w < NW) {
+        double s[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] = wave_sum(v[k]);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) scratch[k * NW + w] = s[k];
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) t += scratch[threadIdx.x * NW + i];
+        part[(size_t)threadIdx.x * stride + blk] = t;
+    }
+}
+
 // Writes this workgroup's NV partials (valid in thread 0) to part[k * stride + blk].
 template <int NV>
 __device__ inline void publish(const double (&v)[NV], double* part, int stride, int blk) {

@@ -37,14 +37,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the workspace arena for cap_px pixels and a window of cap_L.
 struct Layout {
-    static constexpr int kVecs = 15;
+    static constexpr int kVecs = 19;
     size_t vec, win_stride, o_cg, o_hist, o_ve, o_info, bytes;
     Layout(size_t cap_px, int cap_L) {
         vec = align_up(cap_px * sizeof(float));
         win_stride = (size_t)(cap_L + 1) * kMaxRedBlocks;
         bytes = vec * (kVecs + (size_t)cap_L);
         o_cg = bytes;
-        bytes += align_up(4 * kMaxRedBlocks * sizeof(double));
+        bytes += align_up(2 * kCgSums * kMaxRedBlocks * sizeof(double));
         o_hist = bytes;
         bytes += kAlign;
         o_ve = bytes;
@@ -71,9 +71,9 @@ int ensure_workspace(redve_t h, int hx, int wx, int L) {
         return fail(h, REDVE_E_NOMEM, "device workspace allocation of " +
                                           std::to_string(lay.bytes) + " bytes failed");
     char* base = (char*)arena;
-    float** vecs[Layout::kVecs] = {&w.xa,   &w.xb,   &w.xc,   &w.sres, &w.u0,
-                                   &w.u1,   &w.r[0], &w.r[1], &w.w[0], &w.w[1],
-                                   &w.s[0], &w.s[1], &w.p,    &w.d,    &w.yw};
+    float** vecs[Layout::kVecs] = {&w.xa,   &w.xb,   &w.xc,   &w.sres, &w.u0,   &w.u1,   &w.r[0],
+                                   &w.r[1], &w.w[0], &w.w[1], &w.s[0], &w.s[1], &w.p,    &w.d,
+                                   &w.yw,   &w.a[0], &w.a[1], &w.b[0], &w.b[1]};
     for (int i = 0; i < Layout::kVecs; ++i) *vecs[i] = (float*)(base + lay.vec * i);
     w.U = (float*)(base + lay.vec * Layout::kVecs);
     w.cg_part = (double*)(base + lay.o_cg);
@@ -207,15 +207,35 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
 int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int iters) {
     Workspace& w = h->ws;
     LinOp op = linop_of(h);
-    double* slot[2] = {w.cg_part, w.cg_part + 2 * kMaxRedBlocks};
-    Partials rm = launch_cg_w0(op, w.r[0], w.w[0], H, W, slot[0], h->stream);
-    LAUNCH_CHECK(h);
-    for (int k = 0; k < iters; ++k) {
-        const int a = k & 1, b = a ^ 1;
-        rm = launch_cg_iter(op, H, W, k, k == iters - 1, w.r[a], w.w[a], w.s[b], w.r[b], w.w[b],
-                            w.s[a], w.p, w.d, x_in, x_out, rm, w.cg_hist + 2 * b,
-                            w.cg_hist + 2 * a, slot[b], h->stream);
+    double* slot[2] = {w.cg_part, w.cg_part + kCgSums * kMaxRedBlocks};
+    Partials rm;
+    int k = 0, a = 0;
+    if (cg_block_ok(op, iters, H, W)) {
+        // two iterations per kernel while at least one iteration remains after the pair
+        rm = launch_cg_w0_block(op, w.r[0], w.w[0], w.a[0], H, W, slot[0], h->stream);
         LAUNCH_CHECK(h);
+        for (; k + 2 <= iters - 1; k += 2) {
+            const int b = a ^ 1;
+            const float* vin[5] = {w.r[a], w.w[a], w.s[a], w.a[a], w.b[a]};
+            float* vout[5] = {w.r[b], w.w[b], w.s[b], w.a[b], w.b[b]};
+            rm = launch_cg_block(op, H, W, k, vin, vout, w.p, w.d, rm, w.cg_hist + 2 * a,
+                                 w.cg_hist + 2 * b, slot[b], h->stream);
+            LAUNCH_CHECK(h);
+            a = b;
+        }
+    } else {
+        rm = launch_cg_w0(op, w.r[0], w.w[0], H, W, slot[0], h->stream);
+        LAUNCH_CHECK(h);
+    }
+    // single iterations (the last writes x_out = x_in + d); the vectors of iteration k are in
+    // buffer set a, the previous step lengths in hist slot a
+    for (; k < iters; ++k) {
+        const int b = a ^ 1;
+        rm = launch_cg_iter(op, H, W, k, k == iters - 1, w.r[a], w.w[a], w.s[a], w.r[b], w.w[b],
+                            w.s[b], w.p, w.d, x_in, x_out, rm, w.cg_hist + 2 * a,
+                            w.cg_hist + 2 * b, slot[b], h->stream);
+        LAUNCH_CHECK(h);
+        a = b;
     }
     return REDVE_OK;
 }
