@@ -164,22 +164,24 @@ def main():
 
     # ---- rooflines of the two kernels of an FP call, timed with HIP events on the library's
     # stream (torch's current stream): the fused denoiser stage of the headline form (BF16
-    # banks) and the CG iteration; `roofline` is the one with the larger share of an FP call
-    # (5 stages, 15 CG iterations) at the headline size.
+    # banks) and the CG kernel; `roofline` is the one with the larger share of an FP call
+    # (5 stages, 15 CG iterations) at the headline size. The library runs two CG iterations
+    # per launch (k_cg_block) for a separable square 7x7 or 9x9 PSF without decimation on
+    # images of fewer than 512 16x16 tiles (256x256 here), one (k_cg_iter) otherwise.
     R.set_denoiser(prob.denoiser, "bf16")
     stage_us = time_stage(torch, R, y, prob.denoiser.stages)
-    cg_us = time_cg_iter(torch, R, y)
+    blk_us = 2 * time_cg_iter(torch, R, y)  # 30 iterations = 15 launches of two
     roof_stage = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16")
-    roof_cg = roofline_cg(npx, cg_us, "k_cg_iter<4>")
+    roof_cg = roofline_cg(npx, blk_us, "k_cg_block<4>", 2)
     share = {"k_tnrd_stage_bf16": prob.denoiser.stages * stage_us,
-             "k_cg_iter<4>": prob.cg_iters * cg_us}
-    roof = roof_cg if share["k_cg_iter<4>"] >= share["k_tnrd_stage_bf16"] else roof_stage
+             "k_cg_block<4>": (prob.cg_iters // 2) * blk_us}
+    roof = roof_cg if share["k_cg_block<4>"] >= share["k_tnrd_stage_bf16"] else roof_stage
     roof["share_of_fp_call_us"] = share
     big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device=dev)
     stage_big_us = time_stage(torch, R, big, prob.denoiser.stages)
     roof_big = roofline_stage(big.numel(), stage_big_us, "k_tnrd_stage_bf16")
     cg_big_us = time_cg_iter(torch, R, big)
-    roof_cg_big = roofline_cg(big.numel(), cg_big_us, "k_cg_iter<4>")
+    roof_cg_big = roofline_cg(big.numel(), cg_big_us, "k_cg_iter<4>", 1)
     R.set_denoiser(prob.denoiser, "fp32")
     stage32_big_us = time_stage(torch, R, big, prob.denoiser.stages)
     roof32_big = roofline_stage(big.numel(), stage32_big_us, "k_tnrd_stage_f32")
@@ -211,7 +213,7 @@ def main():
         "forms": res_forms,
         "ve_bf16_speedup_vs_plain_fp32": fp["ms_per_step"] / ve["ms_per_step"],
         "roofline": roof,
-        "roofline_kernels": {"k_tnrd_stage_bf16": roof_stage, "k_cg_iter<4>": roof_cg},
+        "roofline_kernels": {"k_tnrd_stage_bf16": roof_stage, "k_cg_block<4>": roof_cg},
         "roofline_2048x2048": {"k_tnrd_stage_bf16": roof_big, "k_tnrd_stage_f32": roof32_big,
                                "k_cg_iter<4>": roof_cg_big},
     }
@@ -242,8 +244,8 @@ def time_stage(torch, R, x, stages, reps=20):
 
 
 def time_cg_iter(torch, R, x, reps=10):
-    """Average duration of one CG iteration launch: HIP events around `reps` CG runs of 45 and
-    of 15 iterations (the same set-up launches); the difference over 30 * reps iterations."""
+    """Average time of one CG iteration: HIP events around `reps` CG runs of 45 and of 15
+    iterations (the same set-up launches); the difference over 30 * reps iterations."""
     stream = torch.cuda.current_stream()
 
     def run(iters):
@@ -265,17 +267,18 @@ CG_BYTES_PER_PX = 24
 HBM_PEAK_GBS = 8000.0
 
 
-def roofline_cg(npx, iter_us, kernel):
-    """The CG iteration is bound by HBM bandwidth (its stencil work is 84 FLOP per pixel).
-    achieved = algorithmic bytes per launch / average launch time. traffic: the bytes the
-    FETCH_SIZE and WRITE_SIZE counters saw per launch at this size (profiles/traffic.json),
-    null if the kernel's source changed since."""
-    work = npx * CG_BYTES_PER_PX
-    achieved = work / (iter_us * 1e-6) / 1e9
+def roofline_cg(npx, launch_us, kernel, iters_per_launch):
+    """CG is bound by HBM bandwidth (its stencil work is under 100 FLOP per pixel and
+    iteration). achieved = algorithmic bytes per launch (24 B per pixel and iteration, times
+    the iterations one launch takes) / average launch time. traffic: the bytes the FETCH_SIZE
+    and WRITE_SIZE counters saw per launch at this size (profiles/traffic.json), null if the
+    kernel's source changed since."""
+    work = npx * CG_BYTES_PER_PX * iters_per_launch
+    achieved = work / (launch_us * 1e-6) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_of(kernel, npx),
-            "avg_launch_us": iter_us, "bytes_per_launch": work, "bytes_per_px": CG_BYTES_PER_PX,
-            "pixels_per_launch": npx}
+            "avg_launch_us": launch_us, "bytes_per_launch": work, "bytes_per_px": CG_BYTES_PER_PX,
+            "iterations_per_launch": iters_per_launch, "pixels_per_launch": npx}
 
 
 def traffic_of(kernel, npx):

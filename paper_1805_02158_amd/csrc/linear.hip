@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_Ht(const float* __restrict__
 // LDS of one tile product, sized for stencil radius RS (RS = 0: any radius up to MAXR): the P
 // region (tile + 2r halo), the row-pass results, and B P masked by S^T S on the tile + r halo.
 template <int RS>
-struct TileSmem {
+struct __align__(16) TileSmem {
     static constexpr int S = RS ? TW + 4 * RS : PW;   // row stride of every region
     static constexpr int RP = RS ? TH + 4 * RS : PH;  // rows of the P and row-pass regions
     static constexpr int RT = RS ? TH + 2 * RS : PH;  // rows of the B P region
@@ -85,6 +85,67 @@ struct TileSmem {
     float h[RP * S];
     float t[RT * S];
 };
+
+// Row pass of B^T B over the rows of X (nr rows, stride xs) at nc output columns:
+// out[r][c] = sum_j acr[j] X[r][c + j]. Each item is four adjacent outputs from one window of
+// 4 RS + 4 values, read as 16-byte words (xs, nc multiples of 4, X 16-byte aligned): a
+// quarter of the LDS reads of one output per item, the same sums in the same order.
+template <int RS, int NTH>
+__device__ inline void ac_rows(const LinOp& op, const float* X, int xs, int nr, int nc,
+                               float* out) {
+    constexpr int KA = 4 * RS + 1, NWIN = KA + 3;
+    static_assert(NWIN % 4 == 0, "whole 16-byte words");
+    const int nq = nc / 4;
+    for (int e = threadIdx.x; e < nr * nq; e += NTH) {
+        const int r = e / nq, c = (e % nq) * 4;
+        const float4* x4 = reinterpret_cast<const float4*>(X + r * xs + c);
+        float x[NWIN];
+#pragma unroll
+        for (int i = 0; i < NWIN / 4; ++i) {
+            const float4 v = x4[i];
+            x[4 * i] = v.x;
+            x[4 * i + 1] = v.y;
+            x[4 * i + 2] = v.z;
+            x[4 * i + 3] = v.w;
+        }
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < KA; ++j) {
+            o0 += op.acr[j] * x[j];
+            o1 += op.acr[j] * x[j + 1];
+            o2 += op.acr[j] * x[j + 2];
+            o3 += op.acr[j] * x[j + 3];
+        }
+        *reinterpret_cast<float4*>(out + r * nc + c) = make_float4(o0, o1, o2, o3);
+    }
+}
+
+// Column pass completing A = B^T B / sigma^2 + lambda I at an nr x nc region: h holds the row
+// pass (stride nc, nr + 4 RS rows), X the input (stride xs) whose point (r, c) of the output
+// sits at X[r + 2 RS][c + 2 RS]. Each item is four outputs down one column (nr a multiple of
+// 4), from one window of 4 RS + 4 values of h.
+template <int RS, int NTH>
+__device__ inline void ac_cols(const LinOp& op, const float* h, const float* X, int xs, int nr,
+                               int nc, float* out) {
+    constexpr int KA = 4 * RS + 1, NWIN = KA + 3;
+    const int nq = nr / 4;
+    for (int e = threadIdx.x; e < nq * nc; e += NTH) {
+        const int r = (e / nc) * 4, c = e % nc;
+        const float* hc = h + r * nc + c;
+        float x[NWIN];
+#pragma unroll
+        for (int i = 0; i < NWIN; ++i) x[i] = hc[i * nc];
+        float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < KA; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] += op.acc[i] * x[i + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            out[(r + k) * nc + c] =
+                op.inv_s2 * o[k] + op.lambda * X[(r + k + 2 * RS) * xs + c + 2 * RS];
+    }
+}
 
 // q = A P on the tile at (r0, c0). P must already be in sm.p on the tile + 2r halo (region
 // origin (r0 - 2rh, c0 - 2rw)). Returns P and q at the thread's NO outputs. RS > 0: separable
@@ -106,24 +167,17 @@ __device__ inline void tile_A_from_lds(const LinOp& op, int H, int W, int r0, in
             // (4 RS + 1 taps): a row pass over the P rows at the tile's columns, then the
             // column pass at the tile
             constexpr int KA = 4 * RS + 1;
-            for (int e = threadIdx.x; e < ph * TW; e += NTH) {
-                const int pr = e / TW, tc = e % TW;
-                const float* prow = sm.p + pr * SW + tc;
-                float acc = 0.f;
-#pragma unroll
-                for (int j = 0; j < KA; ++j) acc += op.acr[j] * prow[j];
-                sm.h[pr * SW + tc] = acc;
-            }
+            ac_rows<RS, NTH>(op, sm.p, SW, ph, TW, sm.h);  // h: stride TW
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 const int o = threadIdx.x + k * kThreads;
                 if (NTH > kThreads && o >= TH * TW) break;
                 const int tr = o / TW, tc = o % TW;
-                const float* hcol = sm.h + tr * SW + tc;
+                const float* hcol = sm.h + tr * TW + tc;
                 float acc = 0.f;
 #pragma unroll
-                for (int i = 0; i < KA; ++i) acc += op.acc[i] * hcol[i * SW];
+                for (int i = 0; i < KA; ++i) acc += op.acc[i] * hcol[i * TW];
                 pc[k] = sm.p[(tr + 2 * RS) * SW + tc + 2 * RS];
                 q[k] = op.inv_s2 * acc + op.lambda * pc[k];
             }
@@ -1048,7 +1102,7 @@ constexpr int kGram = 9;
 enum GramEntry { G_RR, G_WR, G_WW, G_SR, G_SW, G_SS, G_AW, G_AS, G_BS };
 
 template <int RS>
-struct BlkSmem {
+struct __align__(16) BlkSmem {
     static constexpr int RH = TH + 8 * RS, RW = TW + 8 * RS;  // r_{k+2} region
     static constexpr int QH = TH + 4 * RS, QW = TW + 4 * RS;  // s_{k+1}, w_{k+2} regions
     float R[RH * RW];
@@ -1060,39 +1114,6 @@ struct BlkSmem {
     float Bn[TH * TW];
     float An[TH * TW];
 };
-
-// Row pass of B^T B over the rows of X (nr rows, stride xs) at nc output columns:
-// out[r][c] = sum_j acr[j] X[r][c + j].
-template <int RS, int NTH>
-__device__ inline void ac_rows(const LinOp& op, const float* X, int xs, int nr, int nc,
-                               float* out) {
-    constexpr int KA = 4 * RS + 1;
-    for (int e = threadIdx.x; e < nr * nc; e += NTH) {
-        const int r = e / nc, c = e % nc;
-        const float* x = X + r * xs + c;
-        float acc = 0.f;
-#pragma unroll
-        for (int j = 0; j < KA; ++j) acc += op.acr[j] * x[j];
-        out[r * nc + c] = acc;
-    }
-}
-
-// Column pass completing A = B^T B / sigma^2 + lambda I at an nr x nc region: h holds the row
-// pass (stride nc, nr + 4 RS rows), X the input (stride xs) whose point (r, c) of the output
-// sits at X[r + 2 RS][c + 2 RS].
-template <int RS, int NTH>
-__device__ inline void ac_cols(const LinOp& op, const float* h, const float* X, int xs, int nr,
-                               int nc, float* out) {
-    constexpr int KA = 4 * RS + 1;
-    for (int e = threadIdx.x; e < nr * nc; e += NTH) {
-        const int r = e / nc, c = e % nc;
-        const float* hc = h + r * nc + c;
-        float acc = 0.f;
-#pragma unroll
-        for (int i = 0; i < KA; ++i) acc += op.acc[i] * hc[i * nc];
-        out[r * nc + c] = op.inv_s2 * acc + op.lambda * X[(r + 2 * RS) * xs + c + 2 * RS];
-    }
-}
 
 // The published Gram sums: wave v < kGram sums array v, in partial order (as consume2). For at most
 // kEarlyPartials partials the loads are issued first (gram_issue, before the tile's loads) and
