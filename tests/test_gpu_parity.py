@@ -95,8 +95,12 @@ def test_operators(torch, orc, psf, decim, shape):
 
 
 @pytest.mark.parametrize("shape,psf,decim", [((64, 64), "u9", 1), ((37, 53), "g7", 3),
-                                             ((256, 256), "u9", 1), ((8, 8), "g7", 1)])
+                                             ((256, 256), "u9", 1), ((8, 8), "g7", 1),
+                                             ((37, 53), "g7", 1)])
 def test_cg(torch, orc, shape, psf, decim):
+    """CG on A x = rhs against the oracle's CG. Undecimated 7x7 and 9x9 cases run two
+    iterations per kernel for all but the last (and an odd) iteration: the counts cover no
+    block (1, 2), one block (3, 4), several with and without a single iteration left over."""
     say("cg", shape, psf, decim)
     k = PSFS[psf]
     sig = 5.0 if decim > 1 else math.sqrt(2)
@@ -105,7 +109,7 @@ def test_cg(torch, orc, shape, psf, decim):
     rng = np.random.default_rng(7)
     x0 = f32(rng.uniform(0, 255, shape))
     rhs = f32(orc.apply_A(rng.uniform(0, 255, shape), k, decim, sig, 0.02))
-    for iters in (0, 1, 15):
+    for iters in (0, 1, 2, 3, 4, 10, 15):
         xg = host(r.cg(dev(torch, rhs), dev(torch, x0), iters))
         xo = orc.cg(rhs, x0, f32(k), decim, sig, 0.02, iters)
         assert rel(xg, xo) <= 2e-5, iters
