@@ -209,14 +209,17 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     // rows -1-r (r <= 1) and 2H-1-r (r >= H-2) mirror onto row r, the same for columns, and the
     // corners of both (two of each on a side of 2 or 3 pixels); then the reaction update
     if (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) {
-        int lr[3] = {tr + 2, 0, 0}, lc[3] = {tc + 2, 0, 0}, nr = 1, nc = 1;
-        if (gr <= 1) lr[nr++] = -1 - gr - r0 + 2;
-        if (gr >= H - 2) lr[nr++] = 2 * H - 1 - gr - r0 + 2;
-        if (gc <= 1) lc[nc++] = -1 - gc - c0 + 2;
-        if (gc >= W - 2) lc[nc++] = 2 * W - 1 - gc - c0 + 2;
-        for (int x = 0; x < nr; ++x)
-            for (int y = 0; y < nc; ++y)
-                if (x || y) g += st[lr[x] * EW + lc[y]];
+        // local rows / columns of the pixel and its mirror images, with their validity (fixed
+        // indices, so the arrays stay in registers)
+        const int lr[3] = {tr + 2, 1 - gr - r0, 2 * H + 1 - gr - r0};
+        const int lc[3] = {tc + 2, 1 - gc - c0, 2 * W + 1 - gc - c0};
+        const bool vr[3] = {true, gr <= 1, gr >= H - 2};
+        const bool vc[3] = {true, gc <= 1, gc >= W - 2};
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+                if ((x || y) && vr[x] && vc[y]) g += st[lr[x] * EW + lc[y]];
     }
     const size_t gi = (size_t)gr * W + gc;
     const float wc = w ? w[gi] : 0.f;
