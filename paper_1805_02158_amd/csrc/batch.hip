@@ -813,6 +813,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.d_filt = proto->d_filt;
     c.d_rbfw = proto->d_rbfw;
     c.d_frag = proto->d_frag;
+    c.d_frag32 = proto->d_frag32;
     c.have_den = true;
     c.method = proto->method;
     c.L = proto->L;
@@ -928,6 +929,7 @@ extern "C" int redve_server_destroy(redve_server_t s) {
     s->ctx.d_filt = nullptr;
     s->ctx.d_rbfw = nullptr;
     s->ctx.d_frag = nullptr;
+    s->ctx.d_frag32 = nullptr;
     delete s;
     return REDVE_OK;
 }

@@ -78,6 +78,7 @@ struct redve_ctx {
     float* d_filt = nullptr;
     float* d_rbfw = nullptr;
     uint16_t* d_frag = nullptr;  // BF16 MFMA operand fragments: forward then adjoint, per stage
+    float* d_frag32 = nullptr;   // FP32 MFMA operand fragments: forward then adjoint, per stage
     // solver
     int method = REDVE_VE_NONE, L = 5, m = 0;
     int cg_iters = 15, max_fp = 500, extra_fp = 0;

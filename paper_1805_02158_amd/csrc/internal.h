@@ -132,6 +132,12 @@ void launch_ve_combine_batch(const ImgDesc* desc, const TileRef* tiles, int ntil
                              size_t ustride, const VeInfo* info, hipStream_t st);
 
 // Denoiser parameters on the device (FP32; BF16 copies of the filters for the MFMA path).
+// FP32 MFMA operand fragments per stage (v_mfma_f32_16x16x4_f32, B operand, 64 lanes per
+// slice): forward 7 slices of four taps x 2 blocks of 16 filters, adjoint 8 slices of four
+// filters x 2 blocks of 16 taps.
+constexpr int kFrag32Fwd = 7 * 2 * 64;
+constexpr int kFrag32Adj = 8 * 2 * 64;
+
 struct TnrdDev {
     int stages, nfilt, nrbf;
     float mu0, dmu, gamma;
@@ -140,6 +146,8 @@ struct TnrdDev {
     float theta[kMaxStages]; // reaction weights theta_t (kernel arguments)
     const uint16_t* frag_fwd;   // per stage: 2 x 64 lanes x 8 BF16 forward-bank MFMA operands
     const uint16_t* frag_adj;   // per stage: 2 x 64 lanes x 8 BF16 adjoint-bank MFMA operands
+    const float* frag32_fwd;    // per stage: kFrag32Fwd FP32 forward-bank MFMA operands
+    const float* frag32_adj;    // per stage: kFrag32Adj FP32 adjoint-bank MFMA operands
     int precision;
     int kwin;                   // RBF window half-width: centres beyond it add < eps w
                                 // (1e-12 for the FP32 form, 1e-6 for BF16)
@@ -210,7 +218,16 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st);
-size_t tnrd_bf16_smem_bytes(int F, int J);
+// LDS of one MFMA stage tile (either form), and whether it fits the 64 KiB a workgroup gets.
+size_t tnrd_mfma_smem_bytes(int F, int J);
+bool tnrd_mfma_fits(int F, int J);
+// The FP32 form's stage on the vector ALUs (tnrd.hip), for denoisers whose MFMA tile does not
+// fit; launch_tnrd_stage / launch_tnrd_stage_batch choose between the two.
+void launch_tnrd_stage_valu(const TnrdDev& d, int t, const float* w_prev, const float* f,
+                            float* out, int H, int W, int out_mode, hipStream_t st);
+void launch_tnrd_stage_valu_batch(const TnrdDev& d, int t, const ImgDesc* desc,
+                                  const TileRef* tiles, int ntiles, const float* w_prev,
+                                  float* out, int out_mode, hipStream_t st);
 // One denoiser stage in residual form: w_t = w_{t-1} - sum_i K_i^T phi_i(K_i (f + w_{t-1}))
 // - theta_t w_{t-1}, with w = u - f (w_prev null: w_0 = 0). out_mode 0 writes w_t, 1 writes
 // f + w_t (= u_t).

@@ -141,6 +141,8 @@ TnrdDev redve_tnrd_dev(redve_t h) {
     for (int t = 0; t < h->T && t < kMaxStages; ++t) d.theta[t] = h->theta[t];
     d.frag_fwd = h->d_frag;
     d.frag_adj = h->d_frag ? h->d_frag + (size_t)h->T * 2 * 64 * 8 : nullptr;
+    d.frag32_fwd = h->d_frag32;
+    d.frag32_adj = h->d_frag32 ? h->d_frag32 + (size_t)h->T * kFrag32Fwd : nullptr;
     d.precision = h->precision;
     d.kwin = h->kwin;
     return d;
@@ -473,6 +475,7 @@ int redve_destroy(redve_t h) {
     hipFree(h->d_filt);
     hipFree(h->d_rbfw);
     hipFree(h->d_frag);
+    hipFree(h->d_frag32);
     if (h->bstream) hipStreamDestroy(h->bstream);
     for (auto& g : h->pass)
         if (g.exec) hipGraphExecDestroy(g.exec);
@@ -590,15 +593,17 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
         return fail(h, REDVE_E_ARG, "precision must be FP32 or BF16");
     // a BF16 stage keeps a tile's per-position rows (z, v, tap sums) and the weight rows in LDS
     if (p->stages > 0 && p->precision == REDVE_PREC_BF16 &&
-        tnrd_bf16_smem_bytes(p->nfilt, p->nrbf) > 64 * 1024)
+        !tnrd_mfma_fits(p->nfilt, p->nrbf))
         return fail(h, REDVE_E_ARG, "BF16 stage: nfilt and nrbf exceed 64 KiB of LDS (use FP32)");
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     hipFree(h->d_filt);
     hipFree(h->d_rbfw);
     hipFree(h->d_frag);
+    hipFree(h->d_frag32);
     h->d_filt = h->d_rbfw = nullptr;
     h->d_frag = nullptr;
+    h->d_frag32 = nullptr;
     h->T = p->stages;
     h->F = p->stages > 0 ? p->nfilt : 0;
     h->J = p->stages > 0 ? p->nrbf : 0;
@@ -644,6 +649,26 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
                         if (kk < 25 && n < h->F) frag[o] = bf16(ft[n * 25 + kk]);
                         if (kk < h->F && n < 25) frag[(size_t)h->T * per + o] = bf16(ft[kk * 25 + n]);
                     }
+        // FP32 fragments (v_mfma_f32_16x16x4_f32, B operand): lane l of block hf holds column
+        // n = l % 16 + 16 hf and K value 4 k + l / 16 of slice k. Forward: K = tap, n = filter;
+        // adjoint: K = filter, n = tap.
+        std::vector<float> frag32((size_t)h->T * (kFrag32Fwd + kFrag32Adj), 0.f);
+        for (int t = 0; t < h->T; ++t) {
+            const double* ft = p->filters + (size_t)t * h->F * 25;
+            float* fw = frag32.data() + (size_t)t * kFrag32Fwd;
+            float* fa = frag32.data() + (size_t)h->T * kFrag32Fwd + (size_t)t * kFrag32Adj;
+            for (int k = 0; k < 8; ++k)
+                for (int hf = 0; hf < 2; ++hf)
+                    for (int l = 0; l < 64; ++l) {
+                        const int kk = 4 * k + l / 16, n = l % 16 + 16 * hf;
+                        const size_t o = ((size_t)k * 2 + hf) * 64 + l;
+                        if (k < 7 && kk < 25 && n < h->F) fw[o] = (float)ft[n * 25 + kk];
+                        if (kk < h->F && n < 25) fa[o] = (float)ft[kk * 25 + n];
+                    }
+        }
+        HIP_TRY(h, hipMalloc(&h->d_frag32, frag32.size() * sizeof(float)));
+        HIP_TRY(h, hipMemcpy(h->d_frag32, frag32.data(), frag32.size() * sizeof(float),
+                             hipMemcpyHostToDevice));
         HIP_TRY(h, hipMalloc(&h->d_filt, nf * sizeof(float)));
         HIP_TRY(h, hipMalloc(&h->d_rbfw, nw * sizeof(float)));
         HIP_TRY(h, hipMalloc(&h->d_frag, frag.size() * sizeof(uint16_t)));

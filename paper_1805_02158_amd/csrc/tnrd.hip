@@ -1,5 +1,7 @@
-// TNRD-style reaction-diffusion denoiser f (the denoising engine of Sec. IV), one fused kernel
-// per stage:
+// TNRD-style reaction-diffusion denoiser f (the denoising engine of Sec. IV), FP32 banks on the
+// vector ALUs, one fused kernel per stage. The FP32 form runs on the MFMA stage of
+// tnrd_mfma.hip; this one takes denoisers whose tile would not fit 64 KiB of LDS there (up to
+// 32 filters of 127 centres):
 //   u_t = u_{t-1} - sum_i K_i^T phi_i(K_i u_{t-1}) - theta_t (u_{t-1} - f_in)
 // K_i = 5x5 correlation of the half-sample mirror extension, K_i^T its exact adjoint,
 // phi_i(z) = sum_j w_ij exp(-(z - mu_j)^2 / (2 gamma^2)).
@@ -183,7 +185,7 @@ __device__ inline void stage_tile(const float* __restrict__ w, const float* __re
 }
 
 template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_valu(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
     int W, const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfParams rc,
     float theta, int out_mode) {
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32(
 // Batched: one workgroup per tile of the batch's tile list. Vector v of image i lives at
 // base_v + desc[i].off; w_base null means w = 0 (first stage).
 template <int KC>
-__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_batch(
+__global__ __launch_bounds__(NTHR) void k_tnrd_stage_f32_valu_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
     const float* __restrict__ w_base, float* __restrict__ out_base,
     const float* __restrict__ filt, const float* __restrict__ rbfw, int F, RbfParams rc,
@@ -218,7 +220,7 @@ size_t tnrd_smem_bytes(int F, int J) {
 }
 
 
-void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+void launch_tnrd_stage_valu(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
     const RbfParams rc = rbf_params(d);
@@ -226,14 +228,14 @@ void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
-        k_tnrd_stage_f32<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
+        k_tnrd_stage_f32_valu<7><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
                                                       d.theta[t], out_mode);
     else
-        k_tnrd_stage_f32<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
+        k_tnrd_stage_f32_valu<0><<<grid, NTHR, smem, st>>>(w_prev, f, out, H, W, kf, wf, d.nfilt, rc,
                                                       d.theta[t], out_mode);
 }
 
-void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
+void launch_tnrd_stage_valu_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
                              int ntiles, const float* w_prev, float* out, int out_mode,
                              hipStream_t st) {
     const RbfParams rc = rbf_params(d);
@@ -241,10 +243,10 @@ void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const
     const float* kf = d.filters + (size_t)t * d.nfilt * 25;
     const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     if (rc.K == 7)
-        k_tnrd_stage_f32_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
+        k_tnrd_stage_f32_valu_batch<7><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
                                                                wf, d.nfilt, rc, d.theta[t], out_mode);
     else
-        k_tnrd_stage_f32_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
+        k_tnrd_stage_f32_valu_batch<0><<<ntiles, NTHR, smem, st>>>(desc, tiles, w_prev, out, kf,
                                                                wf, d.nfilt, rc, d.theta[t], out_mode);
 }
 

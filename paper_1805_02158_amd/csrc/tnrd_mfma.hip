@@ -1,20 +1,25 @@
-// Mixed-precision denoiser stage: both 5x5 filter banks on MFMA (BF16 operands, FP32
-// accumulation), influence functions and the reaction update in FP32.
+// Denoiser stage with both 5x5 filter banks on MFMA, in two forms: BF16 operands
+// (v_mfma_f32_16x16x32_bf16) or FP32 operands (v_mfma_f32_16x16x4_f32), FP32 accumulation in
+// both; influence functions and the reaction update in FP32.
 //
-// Same stage as tnrd.hip (u_t = u_{t-1} - sum_i K_i^T phi_i(K_i u_{t-1}) - theta (u_{t-1} - f),
-// carried as the residual w = u - f), reorganised as two implicit GEMMs per 16x16 tile:
+// The stage u_t = u_{t-1} - sum_i K_i^T phi_i(K_i u_{t-1}) - theta (u_{t-1} - f), carried as
+// the residual w = u - f, is organised as two implicit GEMMs per 16x16 tile:
 //   forward  Z[q][i] = sum_tap A[q][tap] Kf[tap][i]   q: 400 positions (tile + 2 halo, 25 groups
-//            of 16), taps 25 -> 32, filters F -> 32; A[q][tap] = u(q + tap) - u(q) (the filters
-//            have zero mean, so subtracting the window centre is exact and keeps the BF16
-//            operand small: an image value of 100 carries a BF16 error of 0.4, a local
-//            difference of 5 one of 0.02).
-//   adjoint S[q][tap] = sum_i V[q][i] Kf[tap][i]    V = phi(Z) (FP32 phi, BF16 operand),
+//            of 16), taps 25 -> 32 (BF16) or 28 (FP32), filters F -> 32; A[q][tap] =
+//            u(q + tap) - u(q) (the filters have zero mean, so subtracting the window centre
+//            is exact and keeps the operand small: in BF16 an image value of 100 carries an
+//            error of 0.4, a local difference of 5 one of 0.02).
+//   adjoint S[q][tap] = sum_i V[q][i] Kf[tap][i]    V = phi(Z) (FP32),
 //            then g(p) = sum_tap S[p - off(tap)][tap] (shift-add in LDS) plus the mirror fold at
 //            the image border.
-// v_mfma_f32_16x16x32_bf16 operand layout (checked on gfx950): lane l holds row (A) or column
-// (B) l % 16 and the eight K values of slice l / 16; the accumulator holds column l % 16, rows
-// 4 (l / 16) + 0..3. The filter fragments are prepacked on the host per stage.
+// MFMA operand layout (checked on gfx950 for BF16): lane l holds row (A) or column (B) l % 16
+// and the K values of slice l / 16 (eight for BF16, one for FP32); the accumulator holds
+// column l % 16, rows 4 (l / 16) + 0..3. The filter fragments are prepacked on the host per
+// stage. The FP32 form's stage is also in tnrd.hip (vector ALU banks), which takes denoisers
+// whose tile would not fit 64 KiB of LDS here.
 #include <math.h>
+
+#include <type_traits>
 
 #include "internal.h"
 #include "rbf.h"
@@ -48,11 +53,13 @@ __device__ inline bf16x8 load_frag(const uint16_t* p) {
 // 1024 on small images (one tile per CU), where twice the waves hide twice the latency.
 // ZS: the odd row stride of the per-position rows in LDS (z, v, then the tap sums), at least
 // max(F, 25): 25 for up to 25 filters, 33 for up to 32.
-template <int KC, int NT, int ZS>
-__device__ inline void stage_tile_bf16(const float* __restrict__ w, const float* __restrict__ f,
+// F32: FP32 operands on v_mfma_f32_16x16x4_f32 (the FP32 form) instead of BF16; bfwd / badj
+// then hold FP32 fragments (forward 7 x 2, adjoint 8 x 2 slices of 64 lanes).
+template <int KC, int NT, int ZS, bool F32>
+__device__ inline void stage_tile_mfma(const float* __restrict__ w, const float* __restrict__ f,
                                        float* __restrict__ out, int H, int W, int r0, int c0,
-                                       const uint16_t* __restrict__ bfwd,
-                                       const uint16_t* __restrict__ badj,
+                                       const void* __restrict__ bfwd,
+                                       const void* __restrict__ badj,
                                        const float* __restrict__ rbfw, int F, const RbfParams& rc,
                                        float theta, int out_mode) {
     extern __shared__ float smem[];
@@ -83,9 +90,36 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
 
     const int m = lane & 15, sl = lane >> 4;  // fragment row/column, K slice
     // ---- forward bank: Z = A Kf on MFMA, one group of 16 positions per step
-    {
-        const bf16x8 b0 = load_frag(bfwd + (0 * 64 + lane) * 8);
-        const bf16x8 b1 = load_frag(bfwd + (1 * 64 + lane) * 8);
+    if constexpr (F32) {
+        // seven K slices of four taps, two blocks of 16 filters
+        const float* fr = static_cast<const float*>(bfwd);
+        float b[7][2];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) b[k][h] = fr[(k * 2 + h) * 64 + lane];
+        for (int grp = wave; grp < NGRP; grp += NWAVE) {
+            const int q = grp * 16 + m;
+            const int vr = q / VW, vc = q % VW;
+            const float centre = su[(vr + 2) * UW + vc + 2];
+            f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const int tap = 4 * k + sl;
+                const float x = tap < 25 ? su[(vr + tap / 5) * UW + vc + tap % 5] - centre : 0.f;
+                z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][0], z0, 0, 0, 0);
+                z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][1], z1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qq = grp * 16 + sl * 4 + i;
+                sz[qq * ZS + m] = z0[i];
+                if (m + 16 < F) sz[qq * ZS + m + 16] = z1[i];
+            }
+        }
+    } else {
+        const bf16x8 b0 = load_frag((const uint16_t*)bfwd + (0 * 64 + lane) * 8);
+        const bf16x8 b1 = load_frag((const uint16_t*)bfwd + (1 * 64 + lane) * 8);
         for (int grp = wave; grp < NGRP; grp += NWAVE) {
             const int q = grp * 16 + m;
             const int vr = q / VW, vc = q % VW;
@@ -135,9 +169,37 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
     }
     __syncthreads();
     // ---- adjoint bank: S = V Kf^T on MFMA
-    {
-        const bf16x8 b0 = load_frag(badj + (0 * 64 + lane) * 8);
-        const bf16x8 b1 = load_frag(badj + (1 * 64 + lane) * 8);
+    if constexpr (F32) {
+        // K slices of four filters (as many as F needs, at most eight), two blocks of 16 taps
+        const float* fr = static_cast<const float*>(badj);
+        float b[8][2];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) b[k][h] = 4 * k < F ? fr[(k * 2 + h) * 64 + lane] : 0.f;
+        for (int grp = wave; grp < NGRP; grp += NWAVE) {
+            const int q = grp * 16 + m;
+            const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
+            const bool qin = gr >= 0 && gr < H && gc >= 0 && gc < W;  // v = 0 outside the image
+            f32x4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (4 * k >= F) break;
+                const int i = 4 * k + sl;
+                const float x = i < F && qin ? sz[q * ZS + i] : 0.f;
+                s0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][0], s0, 0, 0, 0);
+                s1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][1], s1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int qq = grp * 16 + sl * 4 + i;
+                ss[qq * ZS + m] = s0[i];
+                if (m + 16 < 25) ss[qq * ZS + m + 16] = s1[i];
+            }
+        }
+    } else {
+        const bf16x8 b0 = load_frag((const uint16_t*)badj + (0 * 64 + lane) * 8);
+        const bf16x8 b1 = load_frag((const uint16_t*)badj + (1 * 64 + lane) * 8);
         for (int grp = wave; grp < NGRP; grp += NWAVE) {
             const int q = grp * 16 + m;
             const int gr = r0 - 2 + q / VW, gc = c0 - 2 + q % VW;
@@ -230,116 +292,207 @@ __device__ inline void stage_tile_bf16(const float* __restrict__ w, const float*
 template <int KC, int NT, int ZS>
 __global__ __launch_bounds__(NT) void k_tnrd_stage_bf16(
     const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
-    int W, const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
+    int W, const void* __restrict__ bfwd, const void* __restrict__ badj,
     const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
     const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    stage_tile_bf16<KC, NT, ZS>(w, f, out, H, W, (t / gridDim.x) * TH, (t % gridDim.x) * TW,
-                                bfwd, badj, rbfw, F, rc, theta, out_mode);
+    stage_tile_mfma<KC, NT, ZS, false>(w, f, out, H, W, (t / gridDim.x) * TH,
+                                       (t % gridDim.x) * TW, bfwd, badj, rbfw, F, rc, theta,
+                                       out_mode);
+}
+
+template <int KC, int NT, int ZS>
+__global__ __launch_bounds__(NT) void k_tnrd_stage_f32(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const void* __restrict__ bfwd, const void* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    stage_tile_mfma<KC, NT, ZS, true>(w, f, out, H, W, (t / gridDim.x) * TH,
+                                      (t % gridDim.x) * TW, bfwd, badj, rbfw, F, rc, theta,
+                                      out_mode);
+}
+
+template <int KC, int ZS, bool F32>
+__device__ inline void stage_batch_tile(const ImgDesc* __restrict__ desc,
+                                        const TileRef* __restrict__ tiles,
+                                        const float* __restrict__ w_base,
+                                        float* __restrict__ out_base, const void* bfwd,
+                                        const void* badj, const float* __restrict__ rbfw, int F,
+                                        const RbfParams& rc, float theta, int out_mode) {
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc& d = desc[e.img];
+    if (!d.active) return;
+    const int t = e.t, ntx = (d.W + TW - 1) / TW;
+    stage_tile_mfma<KC, 512, ZS, F32>(w_base ? w_base + d.off : nullptr, d.x_in,
+                                      out_base + d.off, d.H, d.W, (t / ntx) * TH,
+                                      (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta, out_mode);
 }
 
 template <int KC, int ZS>
 __global__ __launch_bounds__(512) void k_tnrd_stage_bf16_batch(
     const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
-    const float* __restrict__ w_base, float* __restrict__ out_base,
-    const uint16_t* __restrict__ bfwd, const uint16_t* __restrict__ badj,
-    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode) {
-    const TileRef e = tiles[blockIdx.x];
-    const ImgDesc& d = desc[e.img];
-    if (!d.active) return;
-    const int t = e.t, ntx = (d.W + TW - 1) / TW;
-    stage_tile_bf16<KC, 512, ZS>(w_base ? w_base + d.off : nullptr, d.x_in, out_base + d.off,
-                                 d.H, d.W, (t / ntx) * TH, (t % ntx) * TW, bfwd, badj, rbfw, F,
-                                 rc, theta, out_mode);
+    const float* __restrict__ w_base, float* __restrict__ out_base, const void* __restrict__ bfwd,
+    const void* __restrict__ badj, const float* __restrict__ rbfw, int F, RbfParams rc,
+    float theta, int out_mode) {
+    stage_batch_tile<KC, ZS, false>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
+                                    theta, out_mode);
 }
 
-// Launch of the single-image kernel for one window K (KC) and row stride (ZS).
 template <int KC, int ZS>
-void stage_single(bool wide, dim3 grid, size_t smem, hipStream_t st, const float* w,
-                  const float* f, float* out, int H, int W, const uint16_t* bf,
-                  const uint16_t* ba, const float* wf, int F, const RbfParams& rc, float theta,
-                  int out_mode) {
-    if (wide)
-        k_tnrd_stage_bf16<KC, 1024, ZS>
-            <<<grid, 1024, smem, st>>>(w, f, out, H, W, bf, ba, wf, F, rc, theta, out_mode);
-    else
-        k_tnrd_stage_bf16<KC, 512, ZS>
-            <<<grid, 512, smem, st>>>(w, f, out, H, W, bf, ba, wf, F, rc, theta, out_mode);
+__global__ __launch_bounds__(512) void k_tnrd_stage_f32_batch(
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
+    const float* __restrict__ w_base, float* __restrict__ out_base, const void* __restrict__ bfwd,
+    const void* __restrict__ badj, const float* __restrict__ rbfw, int F, RbfParams rc,
+    float theta, int out_mode) {
+    stage_batch_tile<KC, ZS, true>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
+                                   theta, out_mode);
 }
 
 int row_stride(int F) { return F > 25 ? 33 : 25; }
 
+// Arguments of one stage launch.
+struct StageArgs {
+    const float *w, *f;
+    float* out;
+    int H, W;
+    const void *bf, *ba;
+    const float* wf;
+    int F;
+    RbfParams rc;
+    float theta;
+    int out_mode;
+};
+
+template <int KC, int ZS, bool F32>
+void stage_single(bool wide, dim3 grid, size_t smem, hipStream_t st, const StageArgs& a) {
+#define REDVE_STAGE(NAME, NT)                                                                \
+    NAME<KC, NT, ZS><<<grid, NT, smem, st>>>(a.w, a.f, a.out, a.H, a.W, a.bf, a.ba, a.wf, a.F, \
+                                             a.rc, a.theta, a.out_mode)
+    if constexpr (F32) {
+        if (wide)
+            REDVE_STAGE(k_tnrd_stage_f32, 1024);
+        else
+            REDVE_STAGE(k_tnrd_stage_f32, 512);
+    } else {
+        if (wide)
+            REDVE_STAGE(k_tnrd_stage_bf16, 1024);
+        else
+            REDVE_STAGE(k_tnrd_stage_bf16, 512);
+    }
+#undef REDVE_STAGE
+}
+
+template <int KC, int ZS, bool F32>
+void stage_batch(int ntiles, size_t smem, hipStream_t st, const ImgDesc* desc,
+                 const TileRef* tiles, const StageArgs& a) {
+    if constexpr (F32)
+        k_tnrd_stage_f32_batch<KC, ZS><<<ntiles, 512, smem, st>>>(
+            desc, tiles, a.w, a.out, a.bf, a.ba, a.wf, a.F, a.rc, a.theta, a.out_mode);
+    else
+        k_tnrd_stage_bf16_batch<KC, ZS><<<ntiles, 512, smem, st>>>(
+            desc, tiles, a.w, a.out, a.bf, a.ba, a.wf, a.F, a.rc, a.theta, a.out_mode);
+}
+
+// Dispatch over the window K (5, 7 or any) and the row stride.
+template <bool F32, typename Launch>
+void dispatch(const StageArgs& a, Launch&& go) {
+    const bool z33 = row_stride(a.F) == 33;
+    auto by_zs = [&](auto kc) {
+        if (z33)
+            go(kc, std::integral_constant<int, 33>{});
+        else
+            go(kc, std::integral_constant<int, 25>{});
+    };
+    if (a.rc.K == 5)
+        by_zs(std::integral_constant<int, 5>{});
+    else if (a.rc.K == 7)
+        by_zs(std::integral_constant<int, 7>{});
+    else
+        by_zs(std::integral_constant<int, 0>{});
+}
+
+template <bool F32>
+StageArgs stage_args(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+                     int H, int W, int out_mode) {
+    StageArgs a;
+    a.w = w_prev;
+    a.f = f;
+    a.out = out;
+    a.H = H;
+    a.W = W;
+    if constexpr (F32) {
+        a.bf = d.frag32_fwd + (size_t)t * kFrag32Fwd;
+        a.ba = d.frag32_adj + (size_t)t * kFrag32Adj;
+    } else {
+        a.bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
+        a.ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
+    }
+    a.wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
+    a.F = d.nfilt;
+    a.rc = rbf_params(d);
+    a.theta = d.theta[t];
+    a.out_mode = out_mode;
+    return a;
+}
+
+template <bool F32>
+void launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+                   int H, int W, int out_mode, hipStream_t st) {
+    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
+    const StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode);
+    const size_t smem = tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
+    // fewer tiles than two per CU: 1024 threads per tile
+    const bool wide = grid.x * grid.y < 512;
+    dispatch<F32>(a, [&](auto kc, auto zs) {
+        stage_single<decltype(kc)::value, decltype(zs)::value, F32>(wide, grid, smem, st, a);
+    });
+}
+
+template <bool F32>
+void launch_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
+                  int ntiles, const float* w_prev, float* out, int out_mode, hipStream_t st) {
+    const StageArgs a = stage_args<F32>(d, t, w_prev, nullptr, out, 0, 0, out_mode);
+    const size_t smem = tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
+    dispatch<F32>(a, [&](auto kc, auto zs) {
+        stage_batch<decltype(kc)::value, decltype(zs)::value, F32>(ntiles, smem, st, desc, tiles,
+                                                                   a);
+    });
+}
+
 }  // namespace
 
-size_t tnrd_bf16_smem_bytes(int F, int J) {
+size_t tnrd_mfma_smem_bytes(int F, int J) {
     return sizeof(float) *
            ((size_t)UH * UW + (size_t)NPOS * row_stride(F) + (size_t)F * (J + 2 * WPAD));
 }
 
+bool tnrd_mfma_fits(int F, int J) { return tnrd_mfma_smem_bytes(F, J) <= 64 * 1024; }
+
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st) {
-    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    const RbfParams rc = rbf_params(d);
-    const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
-    const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
-    const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
-    // fewer tiles than two per CU: 1024 threads per tile
-    const bool wide = grid.x * grid.y < 512;
-    const bool z33 = row_stride(d.nfilt) == 33;
-    if (rc.K == 5) {  // the BF16 form's window for gamma = dmu
-        if (z33)
-            stage_single<5, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-        else
-            stage_single<5, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-    } else if (rc.K == 7) {
-        if (z33)
-            stage_single<7, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-        else
-            stage_single<7, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-    } else {
-        if (z33)
-            stage_single<0, 33>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-        else
-            stage_single<0, 25>(wide, grid, smem, st, w_prev, f, out, H, W, bf, ba, wf, d.nfilt,
-                                rc, d.theta[t], out_mode);
-    }
+    launch_single<false>(d, t, w_prev, f, out, H, W, out_mode, st);
 }
 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                   const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st) {
-    const RbfParams rc = rbf_params(d);
-    const size_t smem = tnrd_bf16_smem_bytes(d.nfilt, d.nrbf);
-    const uint16_t* bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
-    const uint16_t* ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
-    const float* wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
-#define REDVE_STAGE_BATCH(KC, ZS)                                                          \
-    k_tnrd_stage_bf16_batch<KC, ZS><<<ntiles, 512, smem, st>>>(desc, tiles, w_prev, out, bf, \
-                                                               ba, wf, d.nfilt, rc,          \
-                                                               d.theta[t], out_mode)
-    const bool z33 = row_stride(d.nfilt) == 33;
-    if (rc.K == 5) {
-        if (z33)
-            REDVE_STAGE_BATCH(5, 33);
-        else
-            REDVE_STAGE_BATCH(5, 25);
-    } else if (rc.K == 7) {
-        if (z33)
-            REDVE_STAGE_BATCH(7, 33);
-        else
-            REDVE_STAGE_BATCH(7, 25);
-    } else {
-        if (z33)
-            REDVE_STAGE_BATCH(0, 33);
-        else
-            REDVE_STAGE_BATCH(0, 25);
-    }
-#undef REDVE_STAGE_BATCH
+    launch_batch<false>(d, t, desc, tiles, ntiles, w_prev, out, out_mode, st);
+}
+
+void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+                       int H, int W, int out_mode, hipStream_t st) {
+    if (tnrd_mfma_fits(d.nfilt, d.nrbf))
+        launch_single<true>(d, t, w_prev, f, out, H, W, out_mode, st);
+    else
+        launch_tnrd_stage_valu(d, t, w_prev, f, out, H, W, out_mode, st);
+}
+
+void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
+                             int ntiles, const float* w_prev, float* out, int out_mode,
+                             hipStream_t st) {
+    if (tnrd_mfma_fits(d.nfilt, d.nrbf))
+        launch_batch<true>(d, t, desc, tiles, ntiles, w_prev, out, out_mode, st);
+    else
+        launch_tnrd_stage_valu_batch(d, t, desc, tiles, ntiles, w_prev, out, out_mode, st);
 }
 
 }  // namespace redve
