@@ -301,7 +301,8 @@ def traffic_of(kernel, npx):
 def pmc_probe(torch, R, prob, y):
     """Launches for the counter runs: 5 plain copies of 256 MiB (calibration: each moves
     exactly 256 MiB in and 256 MiB out), then at the headline size 5 CG runs of 15 iterations
-    (FP32) and 5 denoiser calls with BF16 banks, then one of each on a 2048x2048 image."""
+    (FP32) and 5 denoiser calls with BF16 banks, then one of each on a 2048x2048 image and one
+    denoiser call there with FP32 banks."""
     src = torch.rand(64 << 20, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
@@ -317,6 +318,8 @@ def pmc_probe(torch, R, prob, y):
     import workload as W
     big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device="cuda")
     R.cg(big, big, prob.cg_iters)
+    R.denoise(big)
+    R.set_denoiser(prob.denoiser, "fp32")
     R.denoise(big)
     torch.cuda.synchronize()
 
