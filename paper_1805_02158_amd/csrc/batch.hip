@@ -814,6 +814,11 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.d_rbfw = proto->d_rbfw;
     c.d_frag = proto->d_frag;
     c.d_frag32 = proto->d_frag32;
+    c.d_phitab = proto->d_phitab;
+    c.tab_n = proto->tab_n;
+    c.tab_lo = proto->tab_lo;
+    c.tab_h = proto->tab_h;
+    c.lds_max = proto->lds_max;
     c.have_den = true;
     c.method = proto->method;
     c.L = proto->L;
@@ -930,6 +935,7 @@ extern "C" int redve_server_destroy(redve_server_t s) {
     s->ctx.d_rbfw = nullptr;
     s->ctx.d_frag = nullptr;
     s->ctx.d_frag32 = nullptr;
+    s->ctx.d_phitab = nullptr;
     delete s;
     return REDVE_OK;
 }

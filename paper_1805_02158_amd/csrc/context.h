@@ -58,6 +58,7 @@ using redve_detail::kPassGraphs;
 struct redve_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    int lds_max = 64 * 1024;  // LDS one workgroup may use on this device (queried)
     hipStream_t bstream = nullptr;  // the batched engine's own stream (created on first use)
     std::string err;
     // operator H = S B
@@ -79,6 +80,9 @@ struct redve_ctx {
     float* d_rbfw = nullptr;
     uint16_t* d_frag = nullptr;  // BF16 MFMA operand fragments: forward then adjoint, per stage
     float* d_frag32 = nullptr;   // FP32 MFMA operand fragments: forward then adjoint, per stage
+    float* d_phitab = nullptr;   // BF16 form: influence-function tables per stage (or null)
+    int tab_n = 0;
+    double tab_lo = 0, tab_h = 1;
     // solver
     int method = REDVE_VE_NONE, L = 5, m = 0;
     int cg_iters = 15, max_fp = 500, extra_fp = 0;

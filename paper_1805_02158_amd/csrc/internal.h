@@ -151,7 +151,19 @@ struct TnrdDev {
     int precision;
     int kwin;                   // RBF window half-width: centres beyond it add < eps w
                                 // (1e-12 for the FP32 form, 1e-6 for BF16)
+    // BF16 form, tabulated influence functions (null: evaluated on the window): per stage and
+    // filter tab_n intervals of width h, each the cubic (a0, a1, a2, a3) in u in [0, 1) of the
+    // Hermite interpolant of phi on [lo + k h, lo + (k + 1) h]; k = floor(t), u = t - k with
+    // t = z tab_scale + tab_off = (z - lo) / h.
+    const float* phi_tab;
+    int tab_n;
+    float tab_scale, tab_off;
 };
+
+// Influence-function table of the BF16 form: spacing h = gamma / 2, range the centres widened
+// by 5.2565 gamma on both sides (outside it every term is below 1e-6 of its weight).
+constexpr double kTabStep = 0.5, kTabReach = 5.2565;
+int tnrd_table_intervals(double dmu, double gamma, int J);
 
 // ---- launchers (all asynchronous on `st`) ----------------------------------------------
 void launch_apply_H(const LinOp& op, const float* x, int H, int W, float* y, hipStream_t st);
@@ -218,9 +230,13 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st);
-// LDS of one MFMA stage tile (either form), and whether it fits the 64 KiB a workgroup gets.
+// LDS of one MFMA stage tile (either form) with the influence functions evaluated on the
+// window, and whether it fits in 64 KiB (the FP32 form takes the vector-ALU stage beyond; the
+// BF16 form runs up to the device's per-workgroup limit); LDS of a BF16 tile with tabulated
+// influence functions (tab_n intervals per filter), used where it fits that limit.
 size_t tnrd_mfma_smem_bytes(int F, int J);
 bool tnrd_mfma_fits(int F, int J);
+size_t tnrd_table_smem_bytes(int F, int tab_n);
 // The FP32 form's stage on the vector ALUs (tnrd.hip), for denoisers whose MFMA tile does not
 // fit; launch_tnrd_stage / launch_tnrd_stage_batch choose between the two.
 void launch_tnrd_stage_valu(const TnrdDev& d, int t, const float* w_prev, const float* f,

@@ -12,6 +12,12 @@
 // (z beyond the first or last centre) A^2K could overflow, so the terms are built by the
 // two-sided recurrence term(k+1) = term(k) R_k, R_{k+1} = R_k B^2, which stays bounded; past
 // the cut-off (K + 1/2) dmu every term is negligible and the result is 0.
+//
+// Tabulated form (BF16 stage): phi is read from a per-filter table of the cubic Hermite
+// interpolant of the exact sum (all J terms, built in FP64 from phi and phi' at knots spaced
+// gamma / 2), one interval of four coefficients per lookup: three FMAs instead of two exp2 and
+// a 2K+1 term polynomial. Its error is at most h^4 / 384 max |phi''''| (h = gamma / 2: below
+// 5e-4 of the local weight sum), an order below the 3.9e-3 of the BF16 operands.
 #pragma once
 
 #include <math.h>
@@ -29,6 +35,9 @@ struct RbfParams {
     float cutoff;  // (K + 1/2) dmu
     float ck[kMaxRbfWindow + 1];  // B^(k^2), k = 0..K
     int J, K;
+    // tabulated form: t = z t_scale + t_off = (z - lo) / h, intervals 0 .. t_last
+    float t_scale, t_off, t_last;
+    int tab_n;
 };
 
 inline RbfParams rbf_params(const TnrdDev& d) {
@@ -48,7 +57,23 @@ inline RbfParams rbf_params(const TnrdDev& d) {
     for (int k = 0; k <= kMaxRbfWindow; ++k) p.ck[k] = (float)exp2(-cd2 * k * k);
     p.J = d.nrbf;
     p.K = d.kwin;
+    p.t_scale = d.tab_scale;
+    p.t_off = d.tab_off;
+    p.t_last = (float)(d.tab_n > 0 ? d.tab_n - 1 : 0);
+    p.tab_n = d.tab_n;
     return p;
+}
+
+// Tabulated phi: tab holds the function's intervals as (a0, a1, a2, a3), 16-byte aligned.
+// z below the table's range takes interval 0, above it the last (both below 1e-6 of a weight
+// there); the index is clamped in floating point, so any z, NaN included, stays in the table.
+__device__ inline float phi_table(float z, const float* tab, const RbfParams& p) {
+    const float t = fmaf(z, p.t_scale, p.t_off);
+    const float tf = floorf(t);
+    const int k = (int)fminf(fmaxf(tf, 0.f), p.t_last);
+    const float u = t - tf;
+    const float4 c = *reinterpret_cast<const float4*>(tab + 4 * k);
+    return fmaf(fmaf(fmaf(c.w, u, c.z), u, c.y), u, c.x);
 }
 
 // wrow: the function's weights with kRbfPad zeros on each side (the layout of

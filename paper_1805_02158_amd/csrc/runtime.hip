@@ -145,6 +145,10 @@ TnrdDev redve_tnrd_dev(redve_t h) {
     d.frag32_adj = h->d_frag32 ? h->d_frag32 + (size_t)h->T * kFrag32Fwd : nullptr;
     d.precision = h->precision;
     d.kwin = h->kwin;
+    d.phi_tab = h->d_phitab;
+    d.tab_n = h->d_phitab ? h->tab_n : 0;
+    d.tab_scale = (float)(1.0 / h->tab_h);
+    d.tab_off = (float)(-h->tab_lo / h->tab_h);
     return d;
 }
 
@@ -453,6 +457,11 @@ int redve_create(redve_t* out, int device, void* hip_stream) {
     redve_t h = new redve_ctx();
     h->device = device;
     h->stream = (hipStream_t)hip_stream;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess &&
+        lds > h->lds_max)
+        h->lds_max = lds;
     if (hipHostMalloc((void**)&h->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
         delete h;
         return REDVE_E_NOMEM;
@@ -476,6 +485,7 @@ int redve_destroy(redve_t h) {
     hipFree(h->d_rbfw);
     hipFree(h->d_frag);
     hipFree(h->d_frag32);
+    hipFree(h->d_phitab);
     if (h->bstream) hipStreamDestroy(h->bstream);
     for (auto& g : h->pass)
         if (g.exec) hipGraphExecDestroy(g.exec);
@@ -591,19 +601,27 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     }
     if (p->precision != REDVE_PREC_FP32 && p->precision != REDVE_PREC_BF16)
         return fail(h, REDVE_E_ARG, "precision must be FP32 or BF16");
-    // a BF16 stage keeps a tile's per-position rows (z, v, tap sums) and the weight rows in LDS
+    // a BF16 stage keeps a tile's per-position rows (z, v, tap sums) in LDS with the weight
+    // rows (window evaluation; every image) and, on small images, with the influence-function
+    // tables instead, which are built where they fit the device's workgroup LDS
+    const int tab_n = p->stages > 0 ? tnrd_table_intervals(p->dmu, p->gamma, p->nrbf) : 0;
+    const bool use_tab = p->stages > 0 && p->precision == REDVE_PREC_BF16 &&
+                         tnrd_table_smem_bytes(p->nfilt, tab_n) <= (size_t)h->lds_max;
     if (p->stages > 0 && p->precision == REDVE_PREC_BF16 &&
-        !tnrd_mfma_fits(p->nfilt, p->nrbf))
-        return fail(h, REDVE_E_ARG, "BF16 stage: nfilt and nrbf exceed 64 KiB of LDS (use FP32)");
+        tnrd_mfma_smem_bytes(p->nfilt, p->nrbf) > (size_t)h->lds_max)
+        return fail(h, REDVE_E_ARG, "BF16 stage: nfilt and nrbf exceed the LDS of a workgroup (use FP32)");
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     hipFree(h->d_filt);
     hipFree(h->d_rbfw);
     hipFree(h->d_frag);
     hipFree(h->d_frag32);
+    hipFree(h->d_phitab);
     h->d_filt = h->d_rbfw = nullptr;
     h->d_frag = nullptr;
     h->d_frag32 = nullptr;
+    h->d_phitab = nullptr;
+    h->tab_n = 0;
     h->T = p->stages;
     h->F = p->stages > 0 ? p->nfilt : 0;
     h->J = p->stages > 0 ? p->nrbf : 0;
@@ -665,6 +683,43 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
                         if (k < 7 && kk < 25 && n < h->F) fw[o] = (float)ft[n * 25 + kk];
                         if (kk < h->F && n < 25) fa[o] = (float)ft[kk * 25 + n];
                     }
+        }
+        // influence-function tables (BF16 form): per stage and filter, the cubic Hermite
+        // interpolant of phi between knots z_k = lo + k h, from phi and h phi' at the knots
+        // (all J terms, FP64), as (a0, a1, a2, a3) with phi ~ a0 + a1 u + a2 u^2 + a3 u^3
+        if (use_tab) {
+            const double hs = kTabStep * p->gamma, lo = p->mu0 - kTabReach * p->gamma;
+            const double g2 = p->gamma * p->gamma;
+            std::vector<float> tab((size_t)h->T * h->F * tab_n * 4);
+            std::vector<double> v(tab_n + 1), dv(tab_n + 1);
+            for (size_t r = 0; r < (size_t)h->T * h->F; ++r) {
+                const double* wr = p->rbf_w + r * h->J;
+                for (int k = 0; k <= tab_n; ++k) {
+                    const double z = lo + k * hs;
+                    double s0 = 0, s1 = 0;
+                    for (int j = 0; j < h->J; ++j) {
+                        const double e = z - (p->mu0 + j * p->dmu);
+                        const double term = wr[j] * exp(-e * e / (2.0 * g2));
+                        s0 += term;
+                        s1 -= term * e / g2;
+                    }
+                    v[k] = s0;
+                    dv[k] = s1 * hs;
+                }
+                for (int k = 0; k < tab_n; ++k) {
+                    float* c = tab.data() + (r * tab_n + k) * 4;
+                    c[0] = (float)v[k];
+                    c[1] = (float)dv[k];
+                    c[2] = (float)(3.0 * (v[k + 1] - v[k]) - 2.0 * dv[k] - dv[k + 1]);
+                    c[3] = (float)(2.0 * (v[k] - v[k + 1]) + dv[k] + dv[k + 1]);
+                }
+            }
+            HIP_TRY(h, hipMalloc(&h->d_phitab, tab.size() * sizeof(float)));
+            HIP_TRY(h, hipMemcpy(h->d_phitab, tab.data(), tab.size() * sizeof(float),
+                                 hipMemcpyHostToDevice));
+            h->tab_n = tab_n;
+            h->tab_lo = lo;
+            h->tab_h = hs;
         }
         HIP_TRY(h, hipMalloc(&h->d_frag32, frag32.size() * sizeof(float)));
         HIP_TRY(h, hipMemcpy(h->d_frag32, frag32.data(), frag32.size() * sizeof(float),

@@ -17,6 +17,13 @@
 // column l % 16, rows 4 (l / 16) + 0..3. The filter fragments are prepacked on the host per
 // stage. The FP32 form's stage is also in tnrd.hip (vector ALU banks), which takes denoisers
 // whose tile would not fit 64 KiB of LDS here.
+// Influence functions: on the exact window (KC = K > 0, or 0 for any K), or, in the BF16 form
+// on images of fewer than 512 tiles where the tables fit the device's LDS, from the per-filter
+// cubic tables (KC = -1; the tables take the place of the weight rows in LDS, and the
+// workgroup has 1024 threads). The tables take 56 KiB per tile for the 24-filter denoiser, so a
+// CU holds one such tile: on larger images, where two window tiles per CU overlap their
+// phases, and in the batched engine (an image's result must not depend on the batch), the
+// window is used.
 #include <math.h>
 
 #include <type_traits>
@@ -62,14 +69,15 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
                                        const void* __restrict__ badj,
                                        const float* __restrict__ rbfw, int F, const RbfParams& rc,
                                        float theta, int out_mode) {
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     // One row per position holds z, then v = phi(z), then the 25 per-tap adjoint sums (a wave
     // overwrites the rows of its own MFMA group after loading them as an operand).
     // The weight rows come first, so a lane's window of weights is within the immediate
     // offsets of one LDS address.
     static_assert(ZS % 2 == 1 && ZS >= 25, "odd stride covering the 25 taps");
-    const int wstride = rc.J + 2 * WPAD;
-    float* sw = smem;                 // F * (J + 2 WPAD)
+    // weight rows of J + 2 WPAD, or table rows of 4 tab_n (16-byte aligned)
+    const int wstride = KC < 0 ? 4 * rc.tab_n : rc.J + 2 * WPAD;
+    float* sw = smem;                 // F * wstride
     float* su = sw + F * wstride;     // UH * UW
     float* sz = su + UH * UW;         // NPOS * ZS
     float* ss = sz;
@@ -85,7 +93,13 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
         }
         su[e] = val;
     }
-    for (int e = threadIdx.x; e < F * wstride; e += NT) sw[e] = rbfw[e];  // padded rows
+    if constexpr (KC < 0) {
+        const float4* src = reinterpret_cast<const float4*>(rbfw);
+        float4* dst = reinterpret_cast<float4*>(sw);
+        for (int e = threadIdx.x; e < F * rc.tab_n; e += NT) dst[e] = src[e];
+    } else {
+        for (int e = threadIdx.x; e < F * wstride; e += NT) sw[e] = rbfw[e];  // padded rows
+    }
     __syncthreads();
 
     const int m = lane & 15, sl = lane >> 4;  // fragment row/column, K slice
@@ -156,7 +170,10 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
         int zoff = q * ZS + threadIdx.x / NPOS, woff = (threadIdx.x / NPOS) * wstride;
         const int zstep = QSTEP * ZS + ISTEP, zwrap = NPOS * ZS - 1;
         for (int e = threadIdx.x; e < NPOS * F; e += NT) {
-            sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
+            if constexpr (KC < 0)
+                sz[zoff] = phi_table(sz[zoff], sw + woff, rc);
+            else
+                sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
             q += QSTEP;
             zoff += zstep;
             woff += ISTEP * wstride;
@@ -311,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_tnrd_stage_f32(
                                       out_mode);
 }
 
-template <int KC, int ZS, bool F32>
+template <int KC, int NT, int ZS, bool F32>
 __device__ inline void stage_batch_tile(const ImgDesc* __restrict__ desc,
                                         const TileRef* __restrict__ tiles,
                                         const float* __restrict__ w_base,
@@ -322,7 +339,7 @@ __device__ inline void stage_batch_tile(const ImgDesc* __restrict__ desc,
     const ImgDesc& d = desc[e.img];
     if (!d.active) return;
     const int t = e.t, ntx = (d.W + TW - 1) / TW;
-    stage_tile_mfma<KC, 512, ZS, F32>(w_base ? w_base + d.off : nullptr, d.x_in,
+    stage_tile_mfma<KC, NT, ZS, F32>(w_base ? w_base + d.off : nullptr, d.x_in,
                                       out_base + d.off, d.H, d.W, (t / ntx) * TH,
                                       (t % ntx) * TW, bfwd, badj, rbfw, F, rc, theta, out_mode);
 }
@@ -333,7 +350,7 @@ __global__ __launch_bounds__(512) void k_tnrd_stage_bf16_batch(
     const float* __restrict__ w_base, float* __restrict__ out_base, const void* __restrict__ bfwd,
     const void* __restrict__ badj, const float* __restrict__ rbfw, int F, RbfParams rc,
     float theta, int out_mode) {
-    stage_batch_tile<KC, ZS, false>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
+    stage_batch_tile<KC, 512, ZS, false>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
                                     theta, out_mode);
 }
 
@@ -343,11 +360,13 @@ __global__ __launch_bounds__(512) void k_tnrd_stage_f32_batch(
     const float* __restrict__ w_base, float* __restrict__ out_base, const void* __restrict__ bfwd,
     const void* __restrict__ badj, const float* __restrict__ rbfw, int F, RbfParams rc,
     float theta, int out_mode) {
-    stage_batch_tile<KC, ZS, true>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
+    stage_batch_tile<KC, 512, ZS, true>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F, rc,
                                    theta, out_mode);
 }
 
 int row_stride(int F) { return F > 25 ? 33 : 25; }
+
+constexpr int kWideStageBelow = 512;  // tiles: fewer than two per CU
 
 // Arguments of one stage launch.
 struct StageArgs {
@@ -360,6 +379,7 @@ struct StageArgs {
     RbfParams rc;
     float theta;
     int out_mode;
+    bool table;  // tabulated influence functions (BF16 form)
 };
 
 template <int KC, int ZS, bool F32>
@@ -373,9 +393,9 @@ void stage_single(bool wide, dim3 grid, size_t smem, hipStream_t st, const Stage
         else
             REDVE_STAGE(k_tnrd_stage_f32, 512);
     } else {
-        if (wide)
+        if (wide || KC < 0)
             REDVE_STAGE(k_tnrd_stage_bf16, 1024);
-        else
+        else if constexpr (KC >= 0)
             REDVE_STAGE(k_tnrd_stage_bf16, 512);
     }
 #undef REDVE_STAGE
@@ -387,12 +407,12 @@ void stage_batch(int ntiles, size_t smem, hipStream_t st, const ImgDesc* desc,
     if constexpr (F32)
         k_tnrd_stage_f32_batch<KC, ZS><<<ntiles, 512, smem, st>>>(
             desc, tiles, a.w, a.out, a.bf, a.ba, a.wf, a.F, a.rc, a.theta, a.out_mode);
-    else
+    else if constexpr (KC >= 0)  // the batched engine evaluates phi on the window
         k_tnrd_stage_bf16_batch<KC, ZS><<<ntiles, 512, smem, st>>>(
             desc, tiles, a.w, a.out, a.bf, a.ba, a.wf, a.F, a.rc, a.theta, a.out_mode);
 }
 
-// Dispatch over the window K (5, 7 or any) and the row stride.
+// Dispatch over the evaluation of phi (table, window K = 5, 7 or any) and the row stride.
 template <bool F32, typename Launch>
 void dispatch(const StageArgs& a, Launch&& go) {
     const bool z33 = row_stride(a.F) == 33;
@@ -402,6 +422,11 @@ void dispatch(const StageArgs& a, Launch&& go) {
         else
             go(kc, std::integral_constant<int, 25>{});
     };
+    if constexpr (!F32)
+        if (a.table) {
+            by_zs(std::integral_constant<int, -1>{});
+            return;
+        }
     if (a.rc.K == 5)
         by_zs(std::integral_constant<int, 5>{});
     else if (a.rc.K == 7)
@@ -412,7 +437,7 @@ void dispatch(const StageArgs& a, Launch&& go) {
 
 template <bool F32>
 StageArgs stage_args(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
-                     int H, int W, int out_mode) {
+                     int H, int W, int out_mode, bool allow_table) {
     StageArgs a;
     a.w = w_prev;
     a.f = f;
@@ -426,7 +451,9 @@ StageArgs stage_args(const TnrdDev& d, int t, const float* w_prev, const float* 
         a.bf = d.frag_fwd + (size_t)t * 2 * 64 * 8;
         a.ba = d.frag_adj + (size_t)t * 2 * 64 * 8;
     }
-    a.wf = d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
+    a.table = !F32 && allow_table && d.phi_tab;
+    a.wf = a.table ? d.phi_tab + (size_t)t * d.nfilt * d.tab_n * 4
+                   : d.rbf_w + (size_t)t * d.nfilt * (d.nrbf + 2 * kRbfPad);
     a.F = d.nfilt;
     a.rc = rbf_params(d);
     a.theta = d.theta[t];
@@ -438,10 +465,11 @@ template <bool F32>
 void launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                    int H, int W, int out_mode, hipStream_t st) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    const StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode);
-    const size_t smem = tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
-    // fewer tiles than two per CU: 1024 threads per tile
-    const bool wide = grid.x * grid.y < 512;
+    // fewer tiles than two per CU: 1024 threads per tile, and the tables where there are
+    const bool wide = grid.x * grid.y < kWideStageBelow;
+    const StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode, wide);
+    const size_t smem = a.table ? tnrd_table_smem_bytes(d.nfilt, d.tab_n)
+                                : tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
     dispatch<F32>(a, [&](auto kc, auto zs) {
         stage_single<decltype(kc)::value, decltype(zs)::value, F32>(wide, grid, smem, st, a);
     });
@@ -450,8 +478,9 @@ void launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f,
 template <bool F32>
 void launch_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
                   int ntiles, const float* w_prev, float* out, int out_mode, hipStream_t st) {
-    const StageArgs a = stage_args<F32>(d, t, w_prev, nullptr, out, 0, 0, out_mode);
-    const size_t smem = tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
+    const StageArgs a = stage_args<F32>(d, t, w_prev, nullptr, out, 0, 0, out_mode, false);
+    const size_t smem = a.table ? tnrd_table_smem_bytes(d.nfilt, d.tab_n)
+                                : tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
     dispatch<F32>(a, [&](auto kc, auto zs) {
         stage_batch<decltype(kc)::value, decltype(zs)::value, F32>(ntiles, smem, st, desc, tiles,
                                                                    a);
@@ -466,6 +495,16 @@ size_t tnrd_mfma_smem_bytes(int F, int J) {
 }
 
 bool tnrd_mfma_fits(int F, int J) { return tnrd_mfma_smem_bytes(F, J) <= 64 * 1024; }
+
+size_t tnrd_table_smem_bytes(int F, int tab_n) {
+    return sizeof(float) * ((size_t)UH * UW + (size_t)NPOS * row_stride(F)) +
+           16 * (size_t)F * tab_n;
+}
+
+int tnrd_table_intervals(double dmu, double gamma, int J) {
+    const double span = (J - 1) * dmu + 2 * kTabReach * gamma;
+    return (int)ceil(span / (kTabStep * gamma));
+}
 
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st) {

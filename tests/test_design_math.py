@@ -6,6 +6,7 @@ steps, and check them against the oracle's plain definitions.
 import math
 
 import numpy as np
+import pytest
 
 import workload as W
 
@@ -93,6 +94,70 @@ def test_rbf_window_horner_matches_full_sum(orc):
             poly = poly * a + 2.0 ** (-c * d.dmu ** 2 * (m - K) ** 2) * w[j0 - (m - K)]
         bad = max(bad, abs(pre * poly - orc.phi(np.array([v]), w, d.mu0, d.dmu, d.gamma)[0]))
     assert bad > 1e-3 * np.abs(w).max()
+
+
+def _hermite_table(w, mu0, dmu, gamma):
+    """The BF16 stage's influence-function table, in numpy: knots z_k = lo + k h (h = gamma / 2,
+    lo = mu0 - 5.2565 gamma, up to the last centre + 5.2565 gamma), phi and h phi' from the full
+    sum, and per interval the cubic (a0, a1, a2, a3) in u of the Hermite interpolant, rounded to
+    float32 as stored."""
+    J = len(w)
+    h = 0.5 * gamma
+    lo = mu0 - 5.2565 * gamma
+    n = math.ceil(((J - 1) * dmu + 2 * 5.2565 * gamma) / h)
+    zk = lo + h * np.arange(n + 1)
+    e = zk[:, None] - (mu0 + dmu * np.arange(J))[None, :]
+    g = w[None, :] * np.exp(-e * e / (2 * gamma * gamma))
+    v = g.sum(1)
+    dv = (-(e / gamma ** 2) * g).sum(1) * h
+    a0, a1 = v[:-1], dv[:-1]
+    a2 = 3 * (v[1:] - v[:-1]) - 2 * dv[:-1] - dv[1:]
+    a3 = 2 * (v[:-1] - v[1:]) + dv[:-1] + dv[1:]
+    return np.stack([a0, a1, a2, a3], 1).astype(np.float32), lo, h, n
+
+
+def _table_eval(z, tab, lo, h, n):
+    """The kernel's lookup in float32: t = z / h - lo / h, k = clamp(floor t), u = t - floor t."""
+    z = np.asarray(z, np.float32)
+    t = z * np.float32(1.0 / h) + np.float32(-lo / h)
+    tf = np.floor(t)
+    k = np.clip(tf, 0, n - 1).astype(np.int64)
+    u = (t - tf).astype(np.float64)
+    c = tab[k].astype(np.float64)
+    return ((c[:, 3] * u + c[:, 2]) * u + c[:, 1]) * u + c[:, 0]
+
+
+@pytest.mark.parametrize("ratio", [1.0 / 3.0, 1.0, 2.2])
+def test_rbf_table_within_hermite_bound(orc, ratio):
+    """The tabulated influence function is within the cubic Hermite bound h^4 / 384 max |phi^(4)|
+    of the 63-term sum (plus the tails beyond the table, below 1e-6 of the weights, and float32
+    rounding), over and beyond the centre range, for gamma / dmu from 1/3 to 2.2; at
+    gamma = dmu the error is below 1e-3 of the largest weight, under the BF16 operands'
+    3.9e-3."""
+    d = W.make_denoiser()
+    gamma = ratio * d.dmu
+    mu = d.mu0 + d.dmu * np.arange(d.nrbf)
+    z = np.concatenate([np.linspace(mu[0] - 12 * gamma - 40, mu[-1] + 12 * gamma + 40, 4001),
+                        mu, mu + 0.5 * d.dmu])
+    for t, i in [(0, 0), (2, 11), (4, 23)]:
+        w = d.rbf_w[t, i]
+        tab, lo, h, n = _hermite_table(w, d.mu0, d.dmu, gamma)
+        appx = _table_eval(z, tab, lo, h, n)
+        full = orc.phi(z, w, d.mu0, d.dmu, gamma)
+        e = z[:, None] - mu[None, :]
+        g4 = ((e ** 4 / gamma ** 8 - 6 * e ** 2 / gamma ** 6 + 3 / gamma ** 4)
+              * np.abs(w)[None, :] * np.exp(-e * e / (2 * gamma * gamma))).sum(1)
+        bound = h ** 4 / 384 * g4.max() + 1e-6 * np.abs(w).sum() + 1e-6 * np.abs(full).max()
+        err = np.abs(appx - full).max()
+        assert err <= bound, (ratio, t, i, err, bound)
+        if ratio == 1.0:
+            assert err <= 1e-3 * np.abs(w).max()
+    # a wrong cubic (a2 and a3 of each other's form) is caught
+    w = d.rbf_w[1, 3]
+    tab, lo, h, n = _hermite_table(w, d.mu0, d.dmu, d.dmu)
+    tab[:, [2, 3]] = tab[:, [3, 2]]
+    bad = np.abs(_table_eval(z, tab, lo, h, n) - orc.phi(z, w, d.mu0, d.dmu, d.dmu)).max()
+    assert bad > 1e-2 * np.abs(w).max()
 
 
 def test_correction_form_cg_equals_warm_start(orc):
