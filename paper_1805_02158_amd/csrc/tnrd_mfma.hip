@@ -112,15 +112,21 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
         for (int k = 0; k < 7; ++k)
 #pragma unroll
             for (int h = 0; h < 2; ++h) b[k][h] = fr[(k * 2 + h) * 64 + lane];
+        // the lane's tap offsets in the u region; taps past 25 read the centre (x = 0)
+        int toff[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            const int tap = 4 * k + sl;
+            toff[k] = tap < 25 ? (tap / 5) * UW + tap % 5 : 2 * UW + 2;
+        }
         for (int grp = wave; grp < NGRP; grp += NWAVE) {
             const int q = grp * 16 + m;
-            const int vr = q / VW, vc = q % VW;
-            const float centre = su[(vr + 2) * UW + vc + 2];
+            const int qb = (q / VW) * UW + q % VW;
+            const float centre = su[qb + 2 * UW + 2];
             f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 7; ++k) {
-                const int tap = 4 * k + sl;
-                const float x = tap < 25 ? su[(vr + tap / 5) * UW + vc + tap % 5] - centre : 0.f;
+                const float x = su[qb + toff[k]] - centre;
                 z0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][0], z0, 0, 0, 0);
                 z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x, b[k][1], z1, 0, 0, 0);
             }
@@ -134,46 +140,55 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
     } else {
         const bf16x8 b0 = load_frag((const uint16_t*)bfwd + (0 * 64 + lane) * 8);
         const bf16x8 b1 = load_frag((const uint16_t*)bfwd + (1 * 64 + lane) * 8);
+        // the lane's tap offsets in the u region; taps past 25 read the centre (x = 0)
+        int toff[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int tap = sl * 8 + j;
+            toff[j] = tap < 25 ? (tap / 5) * UW + tap % 5 : 2 * UW + 2;
+        }
+        // tabulated phi: the lane's two filters are fixed, so phi is applied to the
+        // accumulators here and v is stored in place of z
+        const float* tab0 = sw + m * wstride;
+        const float* tab1 = sw + (m + 16) * wstride;
         for (int grp = wave; grp < NGRP; grp += NWAVE) {
             const int q = grp * 16 + m;
-            const int vr = q / VW, vc = q % VW;
-            const float centre = su[(vr + 2) * UW + vc + 2];
+            const int qb = (q / VW) * UW + q % VW;
+            const float centre = su[qb + 2 * UW + 2];
             bf16x8 a;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int tap = sl * 8 + j;
-                float x = 0.f;
-                if (tap < 25) x = su[(vr + tap / 5) * UW + vc + tap % 5] - centre;
-                a[j] = (__bf16)x;
-            }
+            for (int j = 0; j < 8; ++j) a[j] = (__bf16)(su[qb + toff[j]] - centre);
             f32x4 z0 = {0.f, 0.f, 0.f, 0.f}, z1 = {0.f, 0.f, 0.f, 0.f};
             z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, z0, 0, 0, 0);
             z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, z1, 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int qq = grp * 16 + sl * 4 + i;
-                sz[qq * ZS + m] = z0[i];
-                if (m + 16 < F) sz[qq * ZS + m + 16] = z1[i];
+                if constexpr (KC < 0) {
+                    if (m < F) sz[qq * ZS + m] = phi_table(z0[i], tab0, rc);
+                    if (m + 16 < F) sz[qq * ZS + m + 16] = phi_table(z1[i], tab1, rc);
+                } else {
+                    sz[qq * ZS + m] = z0[i];
+                    if (m + 16 < F) sz[qq * ZS + m + 16] = z1[i];
+                }
             }
         }
     }
     __syncthreads();
-    // ---- influence functions, dense over (filter, position) pairs, FP32, at every position
+    // ---- influence functions on the window (tabulated: applied in the forward bank above),
+    // dense over (filter, position) pairs, FP32, at every position
     // (the adjoint bank zeroes those outside the image). Consecutive lanes take consecutive
     // positions of one filter: they gather weights from the same LDS row, mostly at the same
     // or nearby centres (broadcast instead of bank conflicts), and read z at the odd stride ZS
     // (conflict-free). The pair index advances by NT per step, i.e. by NT / NPOS filters and
     // NT % NPOS positions, so the offsets are stepped, not divided out.
-    {
+    if constexpr (KC >= 0) {
         constexpr int ISTEP = NT / NPOS, QSTEP = NT % NPOS;
         int q = threadIdx.x % NPOS;
         int zoff = q * ZS + threadIdx.x / NPOS, woff = (threadIdx.x / NPOS) * wstride;
         const int zstep = QSTEP * ZS + ISTEP, zwrap = NPOS * ZS - 1;
         for (int e = threadIdx.x; e < NPOS * F; e += NT) {
-            if constexpr (KC < 0)
-                sz[zoff] = phi_table(sz[zoff], sw + woff, rc);
-            else
-                sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
+            sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
             q += QSTEP;
             zoff += zstep;
             woff += ISTEP * wstride;
@@ -183,8 +198,8 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
                 woff += wstride;
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
     // ---- adjoint bank: S = V Kf^T on MFMA
     if constexpr (F32) {
         // K slices of four filters (as many as F needs, at most eight), two blocks of 16 taps
