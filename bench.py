@@ -324,20 +324,22 @@ def pmc_probe(torch, R, prob, y):
     torch.cuda.synchronize()
 
 
-# Algorithmic work of one denoiser stage per output pixel, as the method defines it:
-# two 24-filter 5x5 banks (forward and adjoint, 2 x 24 x 25 multiply-adds = 2400 FLOP) and
-# 24 influence functions of 63 Gaussian RBF terms, each term counted as 6 FLOP (difference,
-# square, scale, exp, multiply-add) = 9072 FLOP.
-STAGE_FLOP_PER_PX = 2 * 24 * 25 * 2 + 24 * 63 * 6
+# Algorithmic work of one denoiser stage per output pixel: two 24-filter 5x5 banks (forward
+# and adjoint, 2 x 24 x 25 multiply-adds = 2400 FLOP) and 24 influence functions, each the
+# Gaussian RBF sum over the 15 centres within 7.5 gamma of z (the terms beyond add less than
+# 1e-12 of a weight, so this is the sum as defined to FP32 precision; all 63 would be 4.2x
+# more), each term counted as 6 FLOP (difference, square, scale, exp, multiply-add) = 2160 FLOP.
+# The BF16 stage on small images reads phi from a table instead, which does less than this.
+STAGE_FLOP_PER_PX = 2 * 24 * 25 * 2 + 24 * 15 * 6
 # Published MI355X FP32 vector peak (256 CUs, 2.4 GHz).
 FP32_PEAK_TFLOPS = 157.3
 
 
 def roofline_stage(npx, stage_us, kernel):
     """The fused denoiser stage is bound by plain ALU arithmetic: its data stays in LDS and
-    registers (HBM traffic about 12 B per pixel) and 79% of its defined work is the RBF sum,
-    which runs on the vector ALUs in either precision. achieved = algorithmic FLOP per launch
-    / average launch time, against the FP32 vector peak."""
+    registers (HBM traffic about 12 B per pixel) and the influence functions and the banks'
+    operand staging run on the vector ALUs in either precision. achieved = algorithmic FLOP
+    per launch / average launch time, against the FP32 vector peak."""
     work = npx * STAGE_FLOP_PER_PX
     achieved = work / (stage_us * 1e-6) / 1e12
     return {"kernel": kernel, "bound": "alu", "achieved": achieved,

@@ -190,6 +190,13 @@ double sd_step(double mu, double psf_l1, double sigma, double lambda);
 // x_out = x + op.sd_mu (H^T (y - H x) / sigma^2 + lambda s): one steepest-descent step.
 void launch_sd_step(const LinOp& op, const float* x, const float* y, const float* s,
                     float* x_out, int H, int W, hipStream_t st);
+// Last CG iteration k of an FP call fused with the difference pass of column j (0..15) of
+// vector extrapolation: x_out = x_in + d + alpha p, u = x_out - x_in (stored in U unless null),
+// and the partials of u with the j earlier columns, ||u||^2, ||x_in||^2 (j + 2 values at
+// part + v kMaxRedBlocks, as launch_diff_gram). Returns the number of partials per value.
+int launch_cg_last_diff(int n, int k, const float* r_in, const float* p, const float* d,
+                        const float* x_in, float* x_out, Partials rm, const double* hist_prev,
+                        float* U, int j, double* part, hipStream_t st);
 void launch_cg_init_fp(const LinOp& op, const float* x, const float* y, const float* s, float* r,
                        int H, int W, hipStream_t st);
 // w0 = A r0; publishes r0.r0 and w0.r0.

@@ -899,6 +899,54 @@ __global__ __launch_bounds__(NTH) void k_cg_iter(
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
+// The last CG iteration of an FP call and the difference pass of vector extrapolation
+// (Algorithm 1, step 1) in one pass over the pixels: x_out = x_in + d_k + alpha_k p_k, then
+// u = x_out - x_in, stored as column NC of U (U null: not stored), its inner products with the
+// NC earlier columns, ||u||^2 and ||x_in||^2, published as per-workgroup FP64 partials. Each
+// pixel's arithmetic, the pixel order and the sums are those of the two separate passes (the
+// last iteration, then k_diff_gram on the same grid), so the results are bitwise theirs.
+template <int NC>
+__global__ __launch_bounds__(kThreads) void k_cg_last_diff(
+    int n, int k, const float* __restrict__ r_in, const float* __restrict__ p,
+    const float* __restrict__ d, const float* __restrict__ x_in, float* __restrict__ x_out,
+    Partials rm, const double* __restrict__ hist_prev, float* __restrict__ U,
+    double* __restrict__ part) {
+    constexpr int NV = NC + 2;
+    __shared__ double sred[NV * kThreads / 64];
+    __shared__ double bc[2];
+    Early2 early;
+    const bool early_ok = rm.n <= kEarlyPartials;
+    if (early_ok) consume2_issue(rm.p, kMaxRedBlocks, rm.n, early);
+    const double alpha_prev = k ? hist_prev[0] : 0.0, rho_prev = k ? hist_prev[1] : 0.0;
+    double rho, mu;
+    if (early_ok)
+        consume2_finish(early, bc, rho, mu);
+    else
+        consume2(rm.p, kMaxRedBlocks, rm.n, bc, rho, mu);
+    double alpha_d, beta_d;
+    cg_scalars(k, rho, mu, alpha_prev, rho_prev, alpha_d, beta_d);
+    const float alpha = (float)alpha_d, beta = (float)beta_d;
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    const int stride = gridDim.x * kThreads;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const float pk = k ? r_in[i] + beta * p[i] : r_in[i];
+        const float dn = k ? d[i] + alpha * pk : alpha * pk;
+        const float xo = x_in[i];
+        const float xn = xo + dn;
+        x_out[i] = xn;
+        const float uv = xn - xo;
+        if (U) U[(size_t)NC * n + i] = uv;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[j] += (double)uv * (double)U[(size_t)j * n + i];
+        acc[NC] += (double)uv * (double)uv;
+        acc[NC + 1] += (double)xo * (double)xo;
+    }
+    block_sum<NV>(acc, sred);
+    publish<NV>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
 // ---- the RED objective E(x) = ||Hx - y||^2 / (2 sigma^2) + (lambda/2) x^T (x - f(x)), eq. (4)
 
 // Per-workgroup FP64 partials of ||Hx - y||^2 (over the decimated grid; H x summed in FP64 from
@@ -1548,6 +1596,25 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
     }
 #undef REDVE_CG_ITER
     return Partials{part, g};
+}
+
+int launch_cg_last_diff(int n, int k, const float* r_in, const float* p, const float* d,
+                        const float* x_in, float* x_out, Partials rm, const double* hist_prev,
+                        float* U, int j, double* part, hipStream_t st) {
+    const int g = upd_blocks(n);
+#define REDVE_LD(J)                                                                         \
+    case J:                                                                                 \
+        k_cg_last_diff<J><<<g, kThreads, 0, st>>>(n, k, r_in, p, d, x_in, x_out, rm, hist_prev, \
+                                                  U, part);                                 \
+        break;
+    switch (j) {
+        REDVE_LD(0) REDVE_LD(1) REDVE_LD(2) REDVE_LD(3) REDVE_LD(4) REDVE_LD(5) REDVE_LD(6)
+        REDVE_LD(7) REDVE_LD(8) REDVE_LD(9) REDVE_LD(10) REDVE_LD(11) REDVE_LD(12) REDVE_LD(13)
+        REDVE_LD(14) REDVE_LD(15)
+        default: return 0;
+    }
+#undef REDVE_LD
+    return g;
 }
 
 static void init_fp_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int rs,

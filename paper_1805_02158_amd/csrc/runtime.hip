@@ -208,9 +208,19 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
     return REDVE_OK;
 }
 
+// The difference pass of vector extrapolation to fuse into the last CG iteration of an FP call:
+// column j of U (U null: the relative change only), partials at part; nblk is set when fused.
+struct DiffReq {
+    float* U;
+    int j;
+    double* part;
+    int nblk;
+};
+
 // CG iterations in single-reduction form on the correction d (A d = r0 from d = 0), r0 in
 // ws.r[0]; the last iteration writes x_out = x_in + d.
-int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int iters) {
+int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int iters,
+               DiffReq* dq = nullptr) {
     Workspace& w = h->ws;
     LinOp op = linop_of(h);
     double* slot[2] = {w.cg_part, w.cg_part + kCgSums * kMaxRedBlocks};
@@ -237,6 +247,12 @@ int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int ite
     // buffer set a, the previous step lengths in hist slot a
     for (; k < iters; ++k) {
         const int b = a ^ 1;
+        if (dq && k == iters - 1) {  // the last iteration with the difference pass
+            dq->nblk = launch_cg_last_diff(H * W, k, w.r[a], w.p, w.d, x_in, x_out, rm,
+                                           w.cg_hist + 2 * a, dq->U, dq->j, dq->part, h->stream);
+            LAUNCH_CHECK(h);
+            break;
+        }
         rm = launch_cg_iter(op, H, W, k, k == iters - 1, w.r[a], w.w[a], w.s[a], w.r[b], w.w[b],
                             w.s[b], w.p, w.d, x_in, x_out, rm, w.cg_hist + 2 * a,
                             w.cg_hist + 2 * b, slot[b], h->stream);
@@ -262,7 +278,8 @@ int run_cg(redve_t h, const float* rhs, const float* x_in, float* x_out, int H, 
 // One FP call, eq. (7): x_out = CG_{n_cg}(A, H^T y / sigma^2 + lambda f(x_in); start x_in),
 // computed as x_in + d with d the CG solution of A d = r0 from d = 0 (the same Krylov iterates),
 // r0 = H^T (y - H x_in) / sigma^2 + lambda (f(x_in) - x_in).
-int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, int W) {
+int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, int W,
+            DiffReq* dq = nullptr) {
     Workspace& w = h->ws;
     const int n = H * W;
     bool s_null = false;
@@ -286,7 +303,19 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
     }
     launch_cg_init_fp(linop_of(h), x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
     LAUNCH_CHECK(h);
-    return cg_iterate(h, x_in, x_out, H, W, h->cg_iters);
+    return cg_iterate(h, x_in, x_out, H, W, h->cg_iters, dq);
+}
+
+// One FP call and the difference pass of column j (U null: relative change only), fused into
+// its last CG iteration where it ends with one; returns the number of partials.
+int fp_call_diff(redve_t h, const float* y, const float* x_in, float* x_out, int H, int W,
+                 float* U, int j, double* part, int* nblk) {
+    DiffReq dq{U, j, part, 0};
+    int rc = fp_call(h, y, x_in, x_out, H, W, &dq);
+    if (rc) return rc;
+    *nblk = dq.nblk > 0 ? dq.nblk : launch_diff_gram(x_out, x_in, U, j, H * W, part, h->stream);
+    LAUNCH_CHECK(h);
+    return REDVE_OK;
 }
 
 int read_back(redve_t h) {
@@ -322,8 +351,8 @@ int enqueue_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float*
     int rc;
     if (h->method == REDVE_VE_NONE) {
         float* nxt = x_cur == w.xa ? w.xb : w.xa;
-        if ((rc = fp_call(h, y, x_cur, nxt, hx, wx))) return rc;
-        const int nb = launch_diff_gram(nxt, x_cur, nullptr, 0, n, w.ve_part, h->stream);
+        int nb = 0;
+        if ((rc = fp_call_diff(h, y, x_cur, nxt, hx, wx, nullptr, 0, w.ve_part, &nb))) return rc;
         launch_delta(w.ve_part, nb, w.info, h->stream);
         LAUNCH_CHECK(h);
         *next = nxt;
@@ -333,11 +362,12 @@ int enqueue_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float*
         int nblk = 1;
         for (int i = 0; i < h->m + h->L; ++i) {
             float* nxt = third(w.xa, w.xb, w.xc, cur, wbase ? wbase : cur);
-            if ((rc = fp_call(h, y, cur, nxt, hx, wx))) return rc;
             if (i >= h->m) {
-                nblk = launch_diff_gram(nxt, cur, w.U, i - h->m, n,
-                                        w.ve_part + (i - h->m) * w.win_stride, h->stream);
-                LAUNCH_CHECK(h);
+                if ((rc = fp_call_diff(h, y, cur, nxt, hx, wx, w.U, i - h->m,
+                                       w.ve_part + (i - h->m) * w.win_stride, &nblk)))
+                    return rc;
+            } else if ((rc = fp_call(h, y, cur, nxt, hx, wx))) {
+                return rc;
             }
             cur = nxt;
             if (i == h->m - 1) wbase = cur;
