@@ -8,7 +8,7 @@ import pytest
 import workload as W
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="the rocFFT linear step is disabled: its first GPU run ended the box as faulted with no "
+    reason="the rocFFT linear step is disabled: its first GPU run ended with the device reported faulted and no "
            "output, and no cause was found in the code; it stays off the GPU until one is shown")]
 
 
