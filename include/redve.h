@@ -69,8 +69,14 @@ typedef struct {
     const double* rbf_w;    /* T*nfilt*nrbf                                       */
     const double* react;    /* T reaction weights theta_t                         */
     int precision;          /* REDVE_PREC_FP32 or REDVE_PREC_BF16 (filter banks);
-                               BF16 needs 4 (576 + 400 z + nfilt (nrbf + 32)) <= 65536
-                               bytes, z = 25 (nfilt <= 25) or 33 (else)        */
+                               BF16 needs 4 (576 + 400 z + nfilt (nrbf + 32)) bytes
+                               of LDS per workgroup (the device's limit: 160 KiB on
+                               gfx950, which every size within the limits fits),
+                               z = 25 (nfilt <= 25) or 33 (else); REDVE_E_ARG if not.
+                               On images of fewer than 512 16x16 tiles the BF16
+                               stage reads phi from per-filter cubic tables (knots
+                               gamma / 2 apart; error < 1e-3 of the weights) where
+                               they fit that limit, else it sums the window   */
 } redve_tnrd_t;
 
 /* Statistics of one solve (host struct written by redve_solve). */
@@ -106,7 +112,9 @@ int redve_set_operator(redve_t h, const double* psf, int kh, int kw, int decim);
 int redve_set_noise(redve_t h, double sigma);
 /* Trade-off weight lambda > 0 (the paper's alpha, eq. (2)). */
 int redve_set_lambda(redve_t h, double lambda);
-/* Denoiser f (see redve_tnrd_t). Filters must have zero mean (|sum| <= 1e-6 sum|k|). */
+/* Denoiser f (see redve_tnrd_t). Filters must have zero mean (|sum| <= 1e-6 sum|k|);
+ * gamma / dmu in [1/3, 2.2]. Packs the MFMA operands and, for BF16, the influence-function
+ * tables on the host (FP64), and uploads them: a setup call, not for the solve loop. */
 int redve_set_denoiser(redve_t h, const redve_tnrd_t* p);
 
 /* ---- solver (Sec. III) --------------------------------------------------------------- */
