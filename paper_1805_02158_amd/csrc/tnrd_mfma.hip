@@ -83,6 +83,14 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
     float* ss = sz;
     constexpr int NWAVE = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the pixel's own w and f for the update, loaded first: the loads are in flight for the
+    // whole stage instead of after its last barrier
+    const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
+    const int gr = r0 + tr, gc = c0 + tc;
+    const bool pix = (int)threadIdx.x < TH * TW && gr < H && gc < W;
+    const size_t gi = (size_t)gr * W + gc;
+    const float wc = pix && w ? w[gi] : 0.f;
+    const float fc = pix && out_mode ? f[gi] : 0.f;
 
     for (int e = threadIdx.x; e < UH * UW; e += NT) {
         const int er = r0 - 4 + e / UW, ec = c0 - 4 + e % UW;
@@ -265,9 +273,6 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
     static_assert(NT >= 2 * TH * TW, "threads for the pixels and for the extension");
     float* st = su;
     const bool edge = r0 < 2 || c0 < 2 || r0 + TH + 2 > H || c0 + TW + 2 > W;
-    const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
-    const int gr = r0 + tr, gc = c0 + tc;
-    const bool pix = (int)threadIdx.x < TH * TW && gr < H && gc < W;
     float g = 0.f;
     if (pix) {
 #pragma unroll
@@ -283,18 +288,30 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
             if (er >= 0 && er < H && ec >= 0 && ec < W) continue;  // inside the image
             const int mr = mirror(er, H), mc = mirror(ec, W);
             if (mr < r0 || mr >= rend || mc < c0 || mc >= cend) continue;  // not onto this tile
+            // tap (a, b) reads position (lr + 2 - a, lc + 2 - b), counted where it lies in the
+            // region (S vanishes there outside the image); the row and column offsets are
+            // formed once, clamped into the region, and all 25 reads are issued before the
+            // sum, which adds them in tap order
+            int ro[5], co[5];
+            bool rok[5], cok[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int qr = lr + 2 - k, qc = lc + 2 - k;
+                rok[k] = qr >= 0 && qr < VH;
+                cok[k] = qc >= 0 && qc < VW;
+                ro[k] = (rok[k] ? qr : 0) * VW * ZS;
+                co[k] = (cok[k] ? qc : 0) * ZS;
+            }
+            float v[25];
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int b = 0; b < 5; ++b) v[a * 5 + b] = ss[ro[a] + co[b] + a * 5 + b];
             float t = 0.f;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                const int qr = lr + 2 - a;  // position row, local to the position region
+            for (int a = 0; a < 5; ++a)
 #pragma unroll
-                for (int b = 0; b < 5; ++b) {
-                    const int qc = lc + 2 - b;
-                    const bool ok = qr >= 0 && qr < VH && qc >= 0 && qc < VW;
-                    const float v = ss[((ok ? qr : 0) * VW + (ok ? qc : 0)) * ZS + a * 5 + b];
-                    t += ok ? v : 0.f;
-                }
-            }
+                for (int b = 0; b < 5; ++b) t += rok[a] && cok[b] ? v[a * 5 + b] : 0.f;
             st[e] = t;
         }
     }
@@ -315,10 +332,8 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
             for (int y = 0; y < 3; ++y)
                 if ((x || y) && vr[x] && vc[y]) g += st[lr[x] * EW + lc[y]];
     }
-    const size_t gi = (size_t)gr * W + gc;
-    const float wc = w ? w[gi] : 0.f;
     const float wn = wc - g - theta * wc;
-    out[gi] = out_mode ? f[gi] + wn : wn;
+    out[gi] = out_mode ? fc + wn : wn;
 }
 
 template <int KC, int NT, int ZS>
