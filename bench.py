@@ -158,6 +158,8 @@ def main():
             print(json.dumps({"error": f"target PSNR not reached by {name}", "trace": tr}))
             sys.exit(1)
         res_forms[name] = timed(method, prec, ns)
+        res_forms[name]["roofline_whole_solve"] = whole_solve_roofline(
+            npx * ns / (res_forms[name]["ms_per_step"] * 1e-3), prob.cg_iters)
         log(name, res_forms[name])
     ve = res_forms["ve_bf16"]
     fp = res_forms["plain_fp32"]
@@ -460,6 +462,28 @@ def observe(torch, R, probs):
     return ys
 
 
+# Whole-solve roofline: the declared work of one FP call per pixel, by kernel class, each at its
+# own roofline, summed (the classes run one after another): the denoiser's 5 stages (state
+# traffic 5 x 12 B; 5 x STAGE_FLOP_PER_PX at the FP32 vector peak, which bounds them), the CG
+# step (n_cg x 24 B: x, r, p read and written once per iteration) and the extrapolation's
+# difference and combination passes (16.8 B per FP call for L = 5: u written, the Gram reads
+# and the combination spread over a cycle of 5 calls).
+def roofline_ps_per_px_call(n_cg=15):
+    stages = max(5 * 12 / HBM_PEAK_GBS * 1e3, 5 * STAGE_FLOP_PER_PX / FP32_PEAK_TFLOPS)
+    cg = n_cg * CG_BYTES_PER_PX / HBM_PEAK_GBS * 1e3
+    ve = 16.8 / HBM_PEAK_GBS * 1e3
+    return {"stages_ps": stages, "cg_ps": cg, "ve_ps": ve, "total_ps": stages + cg + ve}
+
+
+def whole_solve_roofline(px_calls_per_s, n_cg=15):
+    """Fraction of the whole-solve roofline: declared time per pixel per FP call over the measured
+    one (pixel-FP-calls per second)."""
+    r = roofline_ps_per_px_call(n_cg)
+    measured = 1e12 / px_calls_per_s
+    return {"declared_ps_per_px_fp_call": r, "measured_ps_per_px_fp_call": measured,
+            "frac": r["total_ps"] / measured}
+
+
 def bench_batch(args, torch, np, W, Restorer, psnr):
     probs = W.batch_items(args.batch_images)
     R = Restorer(0)
@@ -502,6 +526,8 @@ def bench_batch(args, torch, np, W, Restorer, psnr):
                      / dt / 1e6,
                      "images_within_band": int(sum(abs(v) <= BAND_DB for v in dps)),
                      "worst_dpsnr_db": float(min(dps))}
+        out[name]["roofline_whole_solve"] = whole_solve_roofline(
+            out[name]["mpix_fp_calls_per_s"] * 1e6)
         log("batched", name, out[name])
     out["ve_bf16_speedup_vs_plain_fp32"] = out["plain_fp32"]["s_per_batch"] / out["ve_bf16"]["s_per_batch"]
     R.close()
