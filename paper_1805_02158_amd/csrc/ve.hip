@@ -242,6 +242,120 @@ __device__ void small_solve(const double* G, int ldG, int L, int method, double 
     info->gamma_l1 = l1;
 }
 
+// The same L x L work for MPE and RRE on a window of L <= 6 with the matrices in registers
+// (every loop has compile-time bounds): the operations and their order are small_solve's, so
+// the results are bitwise its own. Returns false, having written nothing, where the window is
+// rank deficient; small_solve then handles the breakdown rules.
+template <int L>
+__device__ bool small_solve_reg(const double* G, int ldG, int method, double rank_eps,
+                                VeInfo* __restrict__ info) {
+    double R[L][L];
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int j = 0; j < L; ++j) R[i][j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        double d = G[i * ldG + i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) d -= R[k][i] * R[k][i];
+        double rii = sqrt(fmax(d, 0.0));
+        if (i > 0 && !(rii > rank_eps * R[0][0])) rii = 0.0;
+        R[i][i] = rii;
+#pragma unroll
+        for (int j = i + 1; j < L; ++j) {
+            double sum = G[i * ldG + j];
+#pragma unroll
+            for (int k = 0; k < i; ++k) sum -= R[k][i] * R[k][j];
+            R[i][j] = rii > 0.0 ? sum / rii : 0.0;
+        }
+    }
+    // full rank of the leading n = k (MPE) or k + 1 (RRE) columns, as full_rank above
+    constexpr int k = L - 1;
+    const int n = method == 1 ? k : k + 1;
+    bool full = n == 0 || R[0][0] > 0.0;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        if (j < n && !(fabs(R[j][j]) > rank_eps * R[0][0])) full = false;
+    if (!full) return false;
+    double gamma[L];
+    if (method == 1) {  // MPE: R_{k-1} c' = -r_{k}, c = (c', 1)
+        double c[L];
+#pragma unroll
+        for (int i = k - 1; i >= 0; --i) {
+            double sum = -R[i][k];
+#pragma unroll
+            for (int j = i + 1; j < k; ++j) sum -= R[i][j] * c[j];
+            c[i] = sum / R[i][i];
+        }
+        c[k] = 1.0;
+        double sc = 0.0, ac = 0.0;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) {
+            sc += c[i];
+            ac += fabs(c[i]);
+        }
+        if (!(fabs(sc) > 1e-12 * ac)) return false;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) gamma[i] = c[i] / sc;
+    } else {  // RRE: R^T R d = 1
+        double wv[L], dv[L];
+#pragma unroll
+        for (int i = 0; i <= k; ++i) {
+            double sum = 1.0;
+#pragma unroll
+            for (int j = 0; j < i; ++j) sum -= R[j][i] * wv[j];
+            wv[i] = sum / R[i][i];
+        }
+#pragma unroll
+        for (int i = k; i >= 0; --i) {
+            double sum = wv[i];
+#pragma unroll
+            for (int j = i + 1; j <= k; ++j) sum -= R[i][j] * dv[j];
+            dv[i] = sum / R[i][i];
+        }
+        double sd = 0.0;
+#pragma unroll
+        for (int i = 0; i <= k; ++i) sd += dv[i];
+#pragma unroll
+        for (int i = 0; i <= k; ++i) gamma[i] = dv[i] / sd;
+    }
+    for (int i = 0; i < MAXL; ++i) {
+        info->xi[i] = 0.0;
+        info->gamma[i] = 0.0;
+    }
+    // Algorithm 1, step 3
+    double acc = 1.0, l1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < k; ++j) {
+        acc -= gamma[j];
+        info->xi[j] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j <= k; ++j) {
+        info->gamma[j] = gamma[j];
+        l1 += fabs(gamma[j]);
+    }
+    info->ncols = k;
+    info->breakdown = 0;
+    info->kappa_used = k;
+    info->gamma_l1 = l1;
+    return true;
+}
+
+__device__ bool small_solve_fast(const double* G, int ldG, int L, int method, double rank_eps,
+                                 VeInfo* __restrict__ info) {
+    if (method != 1 && method != 2) return false;
+    switch (L) {
+        case 2: return small_solve_reg<2>(G, ldG, method, rank_eps, info);
+        case 3: return small_solve_reg<3>(G, ldG, method, rank_eps, info);
+        case 4: return small_solve_reg<4>(G, ldG, method, rank_eps, info);
+        case 5: return small_solve_reg<5>(G, ldG, method, rank_eps, info);
+        case 6: return small_solve_reg<6>(G, ldG, method, rank_eps, info);
+        default: return false;
+    }
+}
+
 // Sums the window's published partials into the Gram matrix (fixed order, FP64; one wave per
 // entry, 16 waves), then the L x L work on one thread.
 constexpr int kSolveThreads = 1024;
@@ -256,24 +370,41 @@ __global__ __launch_bounds__(kSolveThreads) void k_ve_solve(const double* __rest
     // column j's pass published values k < j (u_j . u_k), j (u_j . u_j), j + 1 (x . x)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int npairs = L * (L + 3) / 2;  // sum over j of (j + 2)
-    for (int q = wave; q < npairs; q += kSolveThreads / 64) {
-        int j = 0, base = 0;
-        while (base + j + 2 <= q) {
-            base += j + 2;
-            ++j;
+    constexpr int NW = kSolveThreads / 64;
+    // a wave sums the published values q and q + NW together (their loads in flight at once)
+    for (int q0 = wave; q0 < npairs; q0 += 2 * NW) {
+        int jj[2], kk[2];
+        const double* pp[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int q = q0 + h * NW < npairs ? q0 + h * NW : q0;
+            int j = 0, base = 0;
+            while (base + j + 2 <= q) {
+                base += j + 2;
+                ++j;
+            }
+            jj[h] = j;
+            kk[h] = q - base;
+            pp[h] = part + (size_t)j * win_stride + (size_t)kk[h] * kMaxRedBlocks;
         }
-        const int k = q - base;
-        const double* pj = part + (size_t)j * win_stride + (size_t)k * kMaxRedBlocks;
-        double s = 0.0;
-        for (int i = lane; i < nblk; i += 64) s += pj[i];
-        s = wave_sum(s);
-        if (lane == 0) {
-            if (k <= j) {
-                G[j * MAXL + k] = s;
-                G[k * MAXL + j] = s;
-                if (k == j && j == L - 1) norms[0] = s;
-            } else if (j == L - 1) {
-                norms[1] = s;
+        double sum[2] = {0.0, 0.0};
+        for (int i = lane; i < nblk; i += 64) {
+            sum[0] += pp[0][i];
+            sum[1] += pp[1][i];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && q0 + NW >= npairs) break;
+            const double sv = wave_sum(sum[h]);
+            const int j = jj[h], k = kk[h];
+            if (lane == 0) {
+                if (k <= j) {
+                    G[j * MAXL + k] = sv;
+                    G[k * MAXL + j] = sv;
+                    if (k == j && j == L - 1) norms[0] = sv;
+                } else if (j == L - 1) {
+                    norms[1] = sv;
+                }
             }
         }
     }
@@ -281,7 +412,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_ve_solve(const double* __rest
     if (threadIdx.x != 0) return;
     info->uu = norms[0];
     info->xx = norms[1];
-    small_solve(G, MAXL, L, method, rank_eps, info, ws);
+    if (!small_solve_fast(G, MAXL, L, method, rank_eps, info))
+        small_solve(G, MAXL, L, method, rank_eps, info, ws);
 }
 
 // Algorithm 1, step 4: x_(m,kappa) = x_m + U_{kappa-1} xi (= x_m + Q_{kappa-1} eta).
