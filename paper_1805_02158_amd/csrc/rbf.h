@@ -86,13 +86,17 @@ __device__ inline float phi_eval(float z, const float* wrow, const RbfParams& p)
     const float d0r = z - (p.mu0 + p.dmu * (float)j0);
     const float* wc = wrow + kRbfPad + j0;
     if (KC > 0 && fabsf(d0r) <= p.half_dmu) {
+        // the 2K+1 weights first, so their reads are in flight together ahead of the chain
+        float wv[2 * (KC > 0 ? KC : 1) + 1];
+#pragma unroll
+        for (int m = 0; m <= 2 * KC; ++m) wv[m] = wc[m - KC];
         const float a = __builtin_amdgcn_exp2f(p.two_cd * d0r);
         const float pre = __builtin_amdgcn_exp2f(-(p.c * d0r + p.kpre) * d0r);
-        float poly = p.ck[KC] * wc[KC];
+        float poly = p.ck[KC] * wv[2 * KC];
 #pragma unroll
         for (int m = 2 * KC - 1; m >= 0; --m) {
             const int k = m - KC;
-            poly = fmaf(poly, a, p.ck[k < 0 ? -k : k] * wc[k]);
+            poly = fmaf(poly, a, p.ck[k < 0 ? -k : k] * wv[m]);
         }
         return pre * poly;
     }
