@@ -234,9 +234,22 @@ void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                   const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st);
+// The CG start an FP call's last denoiser stage can form as it finishes (single image, the
+// two-iteration CG path): r = H^T (y - H x) / sigma^2 + lambda s with s the stage's output and
+// x its input f, into r; rs the PSF radius (3 or 4, separable, no decimation).
+struct ResidualReq {
+    LinOp op;
+    const float* y;
+    float* r;
+    int rs;
+};
+// Whether the stage kernels form it for this denoiser (MFMA stage, BF16 tables or the FP32
+// K = 7 window).
+bool tnrd_fuses_residual(const TnrdDev& d);
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
-                            float* out, int H, int W, int out_mode, hipStream_t st);
+                            float* out, int H, int W, int out_mode, hipStream_t st,
+                            const ResidualReq* rq = nullptr);
 // LDS of one MFMA stage tile (either form) with the influence functions evaluated on the
 // window, and whether it fits in 64 KiB (the FP32 form takes the vector-ALU stage beyond; the
 // BF16 form runs up to the device's per-workgroup limit); LDS of a BF16 tile with tabulated
@@ -255,7 +268,8 @@ void launch_tnrd_stage_valu_batch(const TnrdDev& d, int t, const ImgDesc* desc,
 // - theta_t w_{t-1}, with w = u - f (w_prev null: w_0 = 0). out_mode 0 writes w_t, 1 writes
 // f + w_t (= u_t).
 void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
-                       int H, int W, int out_mode, hipStream_t st);
+                       int H, int W, int out_mode, hipStream_t st,
+                       const ResidualReq* rq = nullptr);
 
 // Differences, Gram row and norms of two consecutive iterates, as published partials:
 //   u = x_new - x_old (stored in U + j*n when U != nullptr),

@@ -12,12 +12,14 @@
 
 #include "internal.h"
 #include "reduce.h"
+#include "residual.h"
 
 namespace redve {
 
 namespace {
 
 constexpr int TH = 16, TW = 16;  // CG tile: 256 outputs per 256-thread workgroup
+static_assert(TH == kResTH && TW == kResTW, "the residual's tile");
 constexpr int MAXR = (kMaxPsf - 1) / 2;
 constexpr int PH = TH + 4 * MAXR, PW = TW + 4 * MAXR;
 constexpr int NO = TH * TW / kThreads;  // outputs per thread
@@ -458,96 +460,22 @@ __device__ inline void init_fp_tile_rs(const LinOp& op, const float* __restrict_
                                        const float* __restrict__ y, const float* __restrict__ s,
                                        float* __restrict__ r, int H, int W, int r0, int c0,
                                        InitFpSmem<RS>& sm, float* __restrict__ xo) {
-    static_assert(RS > 0 && NO == 1, "compile-time radius, one pixel per thread");
+    static_assert(RS > 0 && NO == 1 && kThreads == TH * TW, "compile-time radius, one pixel per thread");
+    static_assert(InitFpSmem<RS>::S == ResidualIn<RS, kThreads>::SW, "the shared layout");
     constexpr int SW = InitFpSmem<RS>::S;
-    constexpr int K = 2 * RS + 1;
-    constexpr int ph = TH + 4 * RS, pw = TW + 4 * RS;
-    constexpr int bh = TH + 2 * RS, bw = TW + 2 * RS;
-    constexpr int NX = (ph * pw + kThreads - 1) / kThreads;
-    constexpr int NY = (bh * bw + kThreads - 1) / kThreads;
-    float* sp = sm.sp;
-    double* se = sm.se;
-    double* sh = sm.sh;
-    const int dec = op.decim;
-    const int wy = (W + dec - 1) / dec;
-    float xv[NX], yv[NY];
-    bool ys[NY];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        const int e = threadIdx.x + i * kThreads;
-        xv[i] = 0.f;
-        if (e < ph * pw)
-            xv[i] = x[(size_t)wrapi(r0 - 2 * RS + e / pw, H) * W + wrapi(c0 - 2 * RS + e % pw, W)];
-    }
-#pragma unroll
-    for (int i = 0; i < NY; ++i) {
-        const int e = threadIdx.x + i * kThreads;
-        ys[i] = false;
-        yv[i] = 0.f;
-        if (e < bh * bw) {
-            const int gr = wrapi(r0 - RS + e / bw, H), gc = wrapi(c0 - RS + e % bw, W);
-            ys[i] = dec == 1 || (gr % dec == 0 && gc % dec == 0);
-            if (ys[i]) yv[i] = y[(size_t)(gr / dec) * wy + gc / dec];
-        }
-    }
+    ResidualIn<RS, kThreads> in;
+    residual_fetch<RS, kThreads>(op.decim, x, y, H, W, r0, c0, in);
     const int tr = threadIdx.x / TW, tc = threadIdx.x % TW;
     const int gr = r0 + tr, gc = c0 + tc;
     const bool pix = gr < H && gc < W;
     const float sv = (s && pix) ? s[(size_t)gr * W + gc] : 0.f;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        const int e = threadIdx.x + i * kThreads;
-        if (e < ph * pw) sp[(e / pw) * SW + e % pw] = xv[i];
-    }
-    __syncthreads();
-    // B x: row pass over the P rows, then the column pass at the B region (FP64)
-    for (int e = threadIdx.x; e < ph * bw; e += kThreads) {
-        const int pr = e / bw, bc = e % bw;
-        const float* prow = sp + pr * SW + bc + 2 * RS;
-        double a = 0.0;
-#pragma unroll
-        for (int b = 0; b < K; ++b) a += op.row_d[b] * (double)prow[-b];
-        sh[pr * SW + bc] = a;
-    }
-    __syncthreads();
-    // e = S^T (y - S B x) on the tile + r halo
-#pragma unroll
-    for (int i = 0; i < NY; ++i) {
-        const int e = threadIdx.x + i * kThreads;
-        if (e < bh * bw) {
-            const int br = e / bw, bc = e % bw;
-            double v = 0.0;
-            if (ys[i]) {
-                double bx = 0.0;
-                const double* hcol = sh + (br + 2 * RS) * SW + bc;
-#pragma unroll
-                for (int a = 0; a < K; ++a) bx += op.col_d[a] * hcol[-a * SW];
-                v = (double)yv[i] - bx;
-            }
-            se[br * SW + bc] = v;
-        }
-    }
-    __syncthreads();
-    // B^T e: row pass, then the column pass at the thread's pixel
-    for (int e = threadIdx.x; e < bh * TW; e += kThreads) {
-        const int br = e / TW, c = e % TW;
-        const double* erow = se + br * SW + c;
-        double a = 0.0;
-#pragma unroll
-        for (int b = 0; b < K; ++b) a += op.row_d[b] * erow[b];
-        sh[br * SW + c] = a;
-    }
-    __syncthreads();
-    double bt = 0.0;
-    const double* hcol = sh + tr * SW + tc;
-#pragma unroll
-    for (int a = 0; a < K; ++a) bt += op.col_d[a] * hcol[a * SW];
+    const double bt = residual_bt<RS, kThreads>(op, in, sm.sp, sm.se, sm.sh);
     if (pix) {
         const size_t g = (size_t)gr * W + gc;
         double rv = op.inv_s2_d * bt;
         if (s) rv += op.lambda_d * (double)sv;
         if (xo)  // steepest descent: x - mu g(x) = x + mu r, rounded once
-            xo[g] = (float)((double)sp[(tr + 2 * RS) * SW + tc + 2 * RS] + op.sd_mu * rv);
+            xo[g] = (float)((double)sm.sp[(tr + 2 * RS) * SW + tc + 2 * RS] + op.sd_mu * rv);
         else
             r[g] = (float)rv;
     }

@@ -180,7 +180,7 @@ int check_image(redve_t h, int hx, int wx) {
 // Denoiser f. residual = true writes f(x) - x (nothing, and *out_null = true, for T = 0);
 // otherwise f(x).
 int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool residual,
-                 bool* out_null) {
+                 bool* out_null, const ResidualReq* rq = nullptr) {
     Workspace& w = h->ws;
     const int n = H * W;
     TnrdDev d = tnrd_of(h);
@@ -198,10 +198,11 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
         const bool last = t == h->T - 1;
         float* dst = last ? out : ((t & 1) ? w.u1 : w.u0);
         const int mode = (last && !residual) ? 1 : 0;
+        const ResidualReq* q = last ? rq : nullptr;
         if (h->precision == REDVE_PREC_BF16)
-            launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream);
+            launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream, q);
         else
-            launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream);
+            launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream, q);
         LAUNCH_CHECK(h);
         wprev = dst;
     }
@@ -283,7 +284,13 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
     Workspace& w = h->ws;
     const int n = H * W;
     bool s_null = false;
-    int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null);
+    // on the two-iteration CG path the last denoiser stage also forms the CG start r_0
+    const LinOp op = linop_of(h);
+    const bool fuse = h->base == REDVE_BASE_FP && h->lin == REDVE_LIN_CG && h->cg_iters > 0 &&
+                      h->T > 0 && cg_block_ok(op, h->cg_iters, H, W) &&
+                      tnrd_fuses_residual(tnrd_of(h));
+    const ResidualReq rq{op, y, w.r[0], op.kh / 2};
+    int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null, fuse ? &rq : nullptr);
     if (rc) return rc;
     if (h->base == REDVE_BASE_SD) {  // x - mu g(x): the same residual, no linear solve
         launch_sd_step(linop_of(h), x_in, y, s_null ? nullptr : w.sres, x_out, H, W, h->stream);
@@ -301,8 +308,10 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
     }
-    launch_cg_init_fp(linop_of(h), x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
-    LAUNCH_CHECK(h);
+    if (!fuse) {
+        launch_cg_init_fp(op, x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
+        LAUNCH_CHECK(h);
+    }
     return cg_iterate(h, x_in, x_out, H, W, h->cg_iters, dq);
 }
 

@@ -28,8 +28,10 @@
 
 #include <type_traits>
 
+#include "../../include/redve.h"
 #include "internal.h"
 #include "rbf.h"
+#include "residual.h"
 
 namespace redve {
 
@@ -39,6 +41,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int TH = 16, TW = 16;
+static_assert(TH == kResTH && TW == kResTW, "the residual's tile");
 constexpr int UH = TH + 8, UW = TW + 8;  // u region: rows r0-4 .. r0+TH+3
 constexpr int VH = TH + 4, VW = TW + 4;  // positions of z / v: rows r0-2 .. r0+TH+1
 constexpr int NPOS = VH * VW;            // 400 = 25 groups of 16
@@ -62,13 +65,17 @@ __device__ inline bf16x8 load_frag(const uint16_t* p) {
 // max(F, 25): 25 for up to 25 filters, 33 for up to 32.
 // F32: FP32 operands on v_mfma_f32_16x16x4_f32 (the FP32 form) instead of BF16; bfwd / badj
 // then hold FP32 fragments (forward 7 x 2, adjoint 8 x 2 slices of 64 lanes).
-template <int KC, int NT, int ZS, bool F32>
+// RSR > 0: the last stage of an FP call also forms the CG start r = H^T (y - H x) / sigma^2 +
+// lambda s at its pixels (x = f, s its output; PSF radius RSR): the loads of x and y are issued
+// with the stage's own, the stencil passes run at the end in the freed per-position rows.
+template <int KC, int NT, int ZS, bool F32, int RSR = 0>
 __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float* __restrict__ f,
                                        float* __restrict__ out, int H, int W, int r0, int c0,
                                        const void* __restrict__ bfwd,
                                        const void* __restrict__ badj,
                                        const float* __restrict__ rbfw, int F, const RbfParams& rc,
-                                       float theta, int out_mode) {
+                                       float theta, int out_mode,
+                                       const ResidualReq* __restrict__ rq = nullptr) {
     extern __shared__ __align__(16) float smem[];
     // One row per position holds z, then v = phi(z), then the 25 per-tap adjoint sums (a wave
     // overwrites the rows of its own MFMA group after loading them as an operand).
@@ -91,6 +98,9 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
     const size_t gi = (size_t)gr * W + gc;
     const float wc = pix && w ? w[gi] : 0.f;
     const float fc = pix && out_mode ? f[gi] : 0.f;
+    constexpr int RSX = RSR > 0 ? RSR : 1;
+    ResidualIn<RSX, NT> rin;
+    if constexpr (RSR > 0) residual_fetch<RSR, NT>(1, f, rq->y, H, W, r0, c0, rin);
 
     for (int e = threadIdx.x; e < UH * UW; e += NT) {
         const int er = r0 - 4 + e / UW, ec = c0 - 4 + e % UW;
@@ -316,10 +326,10 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
         }
     }
     if (edge) __syncthreads();
-    if (!pix) return;
+    if (RSR == 0 && !pix) return;
     // rows -1-r (r <= 1) and 2H-1-r (r >= H-2) mirror onto row r, the same for columns, and the
     // corners of both (two of each on a side of 2 or 3 pixels); then the reaction update
-    if (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2) {
+    if (pix && (gr <= 1 || gr >= H - 2 || gc <= 1 || gc >= W - 2)) {
         // local rows / columns of the pixel and its mirror images, with their validity (fixed
         // indices, so the arrays stay in registers)
         const int lr[3] = {tr + 2, 1 - gr - r0, 2 * H + 1 - gr - r0};
@@ -333,7 +343,27 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
                 if ((x || y) && vr[x] && vc[y]) g += st[lr[x] * EW + lc[y]];
     }
     const float wn = wc - g - theta * wc;
-    out[gi] = out_mode ? fc + wn : wn;
+    if (pix) out[gi] = out_mode ? fc + wn : wn;
+    if constexpr (RSR > 0) {
+        // the CG start, with s = wn: the passes in the per-position rows (free once every pixel
+        // has its sum)
+        __syncthreads();
+        double* rl = reinterpret_cast<double*>(
+            (reinterpret_cast<uintptr_t>(sz) + 15) & ~static_cast<uintptr_t>(15));
+        constexpr int SW = ResidualIn<RSR, NT>::SW;
+        constexpr int PH = TH + 4 * RSR, BH = TH + 2 * RSR;
+        static_assert(residual_lds_bytes<RSR>() + 16 <= sizeof(float) * NPOS * 25,
+                      "the residual's rows fit the per-position rows");
+        double* se = rl;
+        double* sh = se + BH * SW;
+        float* sp = reinterpret_cast<float*>(sh + PH * SW);
+        const double bt = residual_bt<RSR, NT>(rq->op, rin, sp, se, sh);
+        if (pix) {
+            double rv = rq->op.inv_s2_d * bt;
+            rv += rq->op.lambda_d * (double)wn;
+            rq->r[gi] = (float)rv;
+        }
+    }
 }
 
 template <int KC, int NT, int ZS>
@@ -356,6 +386,31 @@ __global__ __launch_bounds__(NT) void k_tnrd_stage_f32(
     stage_tile_mfma<KC, NT, ZS, true>(w, f, out, H, W, (t / gridDim.x) * TH,
                                       (t % gridDim.x) * TW, bfwd, badj, rbfw, F, rc, theta,
                                       out_mode);
+}
+
+// The last stage of an FP call with the CG start (one tile per workgroup of 1024 threads).
+template <int KC, int ZS, int RSR>
+__global__ __launch_bounds__(1024) void k_tnrd_stage_bf16_res(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const void* __restrict__ bfwd, const void* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode,
+    ResidualReq rq) {
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    stage_tile_mfma<KC, 1024, ZS, false, RSR>(w, f, out, H, W, (t / gridDim.x) * TH,
+                                              (t % gridDim.x) * TW, bfwd, badj, rbfw, F, rc,
+                                              theta, out_mode, &rq);
+}
+
+template <int KC, int ZS, int RSR>
+__global__ __launch_bounds__(1024) void k_tnrd_stage_f32_res(
+    const float* __restrict__ w, const float* __restrict__ f, float* __restrict__ out, int H,
+    int W, const void* __restrict__ bfwd, const void* __restrict__ badj,
+    const float* __restrict__ rbfw, int F, RbfParams rc, float theta, int out_mode,
+    ResidualReq rq) {
+    const int t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    stage_tile_mfma<KC, 1024, ZS, true, RSR>(w, f, out, H, W, (t / gridDim.x) * TH,
+                                             (t % gridDim.x) * TW, bfwd, badj, rbfw, F, rc,
+                                             theta, out_mode, &rq);
 }
 
 template <int KC, int NT, int ZS, bool F32>
@@ -410,10 +465,32 @@ struct StageArgs {
     float theta;
     int out_mode;
     bool table;  // tabulated influence functions (BF16 form)
+    const ResidualReq* rq;  // the CG start with the last stage (or null)
 };
 
 template <int KC, int ZS, bool F32>
 void stage_single(bool wide, dim3 grid, size_t smem, hipStream_t st, const StageArgs& a) {
+    // the stage with the CG start: BF16 tables (KC = -1) or the FP32 K = 7 window
+    if constexpr ((!F32 && KC < 0) || (F32 && KC == 7)) {
+        if (a.rq) {
+#define REDVE_STAGE_RES(NAME, RS_)                                                          \
+    NAME<KC, ZS, RS_><<<grid, 1024, smem, st>>>(a.w, a.f, a.out, a.H, a.W, a.bf, a.ba, a.wf, \
+                                                a.F, a.rc, a.theta, a.out_mode, *a.rq)
+            if constexpr (F32) {
+                if (a.rq->rs == 4)
+                    REDVE_STAGE_RES(k_tnrd_stage_f32_res, 4);
+                else
+                    REDVE_STAGE_RES(k_tnrd_stage_f32_res, 3);
+            } else {
+                if (a.rq->rs == 4)
+                    REDVE_STAGE_RES(k_tnrd_stage_bf16_res, 4);
+                else
+                    REDVE_STAGE_RES(k_tnrd_stage_bf16_res, 3);
+            }
+#undef REDVE_STAGE_RES
+            return;
+        }
+    }
 #define REDVE_STAGE(NAME, NT)                                                                \
     NAME<KC, NT, ZS><<<grid, NT, smem, st>>>(a.w, a.f, a.out, a.H, a.W, a.bf, a.ba, a.wf, a.F, \
                                              a.rc, a.theta, a.out_mode)
@@ -488,16 +565,18 @@ StageArgs stage_args(const TnrdDev& d, int t, const float* w_prev, const float* 
     a.rc = rbf_params(d);
     a.theta = d.theta[t];
     a.out_mode = out_mode;
+    a.rq = nullptr;
     return a;
 }
 
 template <bool F32>
 void launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
-                   int H, int W, int out_mode, hipStream_t st) {
+                   int H, int W, int out_mode, hipStream_t st, const ResidualReq* rq) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
     // fewer tiles than two per CU: 1024 threads per tile, and the tables where there are
     const bool wide = grid.x * grid.y < kWideStageBelow;
-    const StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode, wide);
+    StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode, wide);
+    a.rq = wide ? rq : nullptr;  // the residual kernels have 1024 threads
     const size_t smem = a.table ? tnrd_table_smem_bytes(d.nfilt, d.tab_n)
                                 : tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
     dispatch<F32>(a, [&](auto kc, auto zs) {
@@ -537,8 +616,14 @@ int tnrd_table_intervals(double dmu, double gamma, int J) {
 }
 
 void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
-                            float* out, int H, int W, int out_mode, hipStream_t st) {
-    launch_single<false>(d, t, w_prev, f, out, H, W, out_mode, st);
+                            float* out, int H, int W, int out_mode, hipStream_t st,
+                            const ResidualReq* rq) {
+    launch_single<false>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
+}
+
+bool tnrd_fuses_residual(const TnrdDev& d) {
+    if (d.precision == REDVE_PREC_BF16) return d.phi_tab != nullptr;
+    return tnrd_mfma_fits(d.nfilt, d.nrbf) && d.kwin == 7;
 }
 
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
@@ -548,9 +633,9 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
 }
 
 void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
-                       int H, int W, int out_mode, hipStream_t st) {
+                       int H, int W, int out_mode, hipStream_t st, const ResidualReq* rq) {
     if (tnrd_mfma_fits(d.nfilt, d.nrbf))
-        launch_single<true>(d, t, w_prev, f, out, H, W, out_mode, st);
+        launch_single<true>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
     else
         launch_tnrd_stage_valu(d, t, w_prev, f, out, H, W, out_mode, st);
 }
