@@ -202,6 +202,28 @@ def test_fp_step(torch, orc, name):
         x = f32(xo)
 
 
+@pytest.mark.parametrize("shape", [(37, 53), (250, 490), (250, 510)])
+def test_fp_step_uniform9_at_the_tile_boundary(torch, orc, shape):
+    """One FP call of eq. (7) on a uniform 9x9 deblurring with 15 CG iterations (FP32 banks), on
+    both sides of the 512-tile boundary: below it (37x53: 12 tiles, 250x490: 496) the last
+    denoiser stage also forms the CG start and two CG iterations run per launch; at 250x510
+    (512 tiles) the start has its own kernel and one iteration runs per launch. The bar of the
+    FP32 form, two calls in a row."""
+    say("fp_step u9", shape)
+    prob = W.Problem(f"u9_{shape[0]}x{shape[1]}", W.make_image(*shape, 1003), W.psf_uniform(9), 1,
+                     W.SQRT2, 0.02, W.make_noise(shape, 2003), 15, W.make_denoiser())
+    op = orc.OracleProblem(prob, y=f32(orc.OracleProblem(prob).y))
+    r = restorer(prob)
+    x = f32(op.y)
+    for _ in range(2):
+        xg = host(r.fp_step(dev(torch, op.y), dev(torch, x)))
+        xo = op.fp(x)
+        say(f"  rel L2 {rel(xg, xo):.2e}, relative to the step {rel(xg - x, xo - x):.2e}")
+        assert rel(xg, xo) <= 2e-5
+        assert rel(xg - x, xo - x) <= 1e-4
+        x = f32(xo)
+
+
 # ------------------------------------------------------------------ extrapolation
 
 
