@@ -224,6 +224,37 @@ def test_fp_step_uniform9_at_the_tile_boundary(torch, orc, shape):
         x = f32(xo)
 
 
+# Denoisers beside the default one for the last stage forming the CG start: one stage (the last
+# stage is also the first) and 32 filters (LDS row stride 33; with FP32 banks their MFMA tile
+# exceeds 64 KiB, so that form runs the vector-ALU stage and the separate start kernel).
+FUSED_DENOISERS = {"one stage": dict(stages=1), "32 filters": dict(stages=2, nfilt=32)}
+
+
+def _fused_problem(psf, form, shape):
+    return W.Problem(f"{psf}_{form}", W.make_image(*shape, 1004), PSFS[psf], 1, W.SQRT2, 0.02,
+                     W.make_noise(shape, 2004), 15, W.make_denoiser(**FUSED_DENOISERS[form]),
+                     "rre", 5, 0, 1e-5, 400)
+
+
+@pytest.mark.parametrize("psf", ["u9", "g7"])
+@pytest.mark.parametrize("form", list(FUSED_DENOISERS))
+def test_fp_step_fused_start_forms(torch, orc, psf, form):
+    """One FP call of eq. (7) with FP32 banks on a 37x53 deblurring, 9x9 and 7x7 PSFs (halo
+    radius 4 and 3), against the oracle's, the FP32 bar, two calls in a row."""
+    say("fp_step fused start", psf, form)
+    prob = _fused_problem(psf, form, (37, 53))
+    op = orc.OracleProblem(prob, y=f32(orc.OracleProblem(prob).y))
+    r = restorer(prob)
+    x = f32(op.y)
+    for _ in range(2):
+        xg = host(r.fp_step(dev(torch, op.y), dev(torch, x)))
+        xo = op.fp(x)
+        say(f"  rel L2 {rel(xg, xo):.2e}, relative to the step {rel(xg - x, xo - x):.2e}")
+        assert rel(xg, xo) <= 2e-5
+        assert rel(xg - x, xo - x) <= 1e-4
+        x = f32(xo)
+
+
 # ------------------------------------------------------------------ extrapolation
 
 
@@ -538,6 +569,17 @@ def _converged_bf16(torch, orc, prob, method, L, tol=1e-5, calls=400):
 def test_solve_bf16_deblur(torch, orc):
     say("solve bf16 deblur 256")
     err, dp = _converged_bf16(torch, orc, W.problem("deblur256"), "rre", 5)
+    assert err <= 5e-3 and abs(dp) <= 0.05
+
+
+@pytest.mark.parametrize("psf", ["u9", "g7"])
+@pytest.mark.parametrize("form", list(FUSED_DENOISERS))
+def test_solve_bf16_fused_start_forms(torch, orc, psf, form):
+    """BF16 banks (tabulated phi) with the CG start formed by the last stage, for a 9x9 and a
+    7x7 PSF, one stage and 32 filters: converged RRE solves of a 64x64 deblurring against the
+    oracle's fixed point, the BF16 bar."""
+    say("solve bf16 fused start", psf, form)
+    err, dp = _converged_bf16(torch, orc, _fused_problem(psf, form, (64, 64)), "rre", 5)
     assert err <= 5e-3 and abs(dp) <= 0.05
 
 
