@@ -303,8 +303,9 @@ def traffic_of(kernel, npx):
 def pmc_probe(torch, R, prob, y):
     """Launches for the counter runs: 5 plain copies of 256 MiB (calibration: each moves
     exactly 256 MiB in and 256 MiB out), then at the headline size 5 CG runs of 15 iterations
-    (FP32) and 5 denoiser calls with BF16 banks, then one of each on a 2048x2048 image and one
-    denoiser call there with FP32 banks."""
+    (FP32), 5 denoiser calls with BF16 banks and 5 FP calls with them (their last stage forms
+    the CG start), then a CG run and a denoiser call on a 2048x2048 image and one denoiser
+    call there with FP32 banks."""
     src = torch.rand(64 << 20, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
@@ -316,6 +317,8 @@ def pmc_probe(torch, R, prob, y):
     R.set_denoiser(prob.denoiser, "bf16")
     for _ in range(5):
         R.denoise(y)
+    for _ in range(5):
+        R.fp_step(y, y)
     # the same kernels with every CU busy (2048x2048: 16384 tiles)
     import workload as W
     big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device="cuda")
