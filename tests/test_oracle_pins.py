@@ -157,15 +157,11 @@ def test_phi_closed_forms(orc):
         assert np.allclose(orc.phi(z, wt), -orc.phi(-z, wt), atol=1e-12)
 
 
-def test_stage_from_independent_pieces(orc):
-    """One stage u - sum_i K_i^T phi_i(K_i u) - theta (u - f), rebuilt from scipy reflect
-    correlation, a dense transpose of it, and a direct sum of Gaussians."""
-    d = W.make_denoiser()
-    den = orc.Denoiser(d)
-    shape = (6, 7)
-    u = RNG.uniform(0, 255, shape)
-    f = RNG.uniform(0, 255, shape)
-    t = 2
+def _stage_independent(d, t, u, f):
+    """One stage u - sum_i K_i^T phi_i(K_i u) - theta_t (u - f) (Sec. IV's TNRD-style
+    diffusion step), rebuilt from scipy reflect correlation, a dense transpose of it, and a
+    direct sum of Gaussians."""
+    shape = u.shape
     mu = d.mu0 + d.dmu * np.arange(d.nrbf)
     g = np.zeros(u.size)
     for i in range(d.nfilt):
@@ -175,8 +171,43 @@ def test_stage_from_independent_pieces(orc):
         v = (d.rbf_w[t, i][None, :] * np.exp(-(z[:, None] - mu[None, :]) ** 2
                                               / (2 * d.gamma ** 2))).sum(1)
         g += K.T @ v
-    ref = u.ravel() - g - d.react[t] * (u.ravel() - f.ravel())
-    assert np.allclose(orc.tnrd_stage(u, f, den, t).ravel(), ref, atol=1e-11)
+    return (u.ravel() - g - d.react[t] * (u.ravel() - f.ravel())).reshape(shape)
+
+
+def test_stage_from_independent_pieces(orc):
+    """One stage of the oracle equals the stage rebuilt from independent pieces."""
+    d = W.make_denoiser()
+    den = orc.Denoiser(d)
+    shape = (6, 7)
+    u = RNG.uniform(0, 255, shape)
+    f = RNG.uniform(0, 255, shape)
+    t = 2
+    ref = _stage_independent(d, t, u, f)
+    assert np.allclose(orc.tnrd_stage(u, f, den, t), ref, atol=1e-11)
+
+
+def test_denoiser_composes_stages_in_order_with_fixed_reaction_input(orc):
+    """D(x) = u_T with u_0 = x and u_t = stage_t(u_{t-1}; f = x): the stages run in the order
+    t = 0 .. T-1 and the reaction term of every stage pulls towards the denoiser's input x,
+    not towards the previous stage's output. Rebuilt from the independent stage above on a
+    6x7 image with T = 5; the two plausible slips (reversed stage order, reaction towards
+    u_{t-1}) are far from the result, so either would fail."""
+    d = W.make_denoiser()
+    den = orc.Denoiser(d)
+    x = RNG.uniform(0, 255, (6, 7))
+    u = x.copy()
+    for t in range(d.stages):
+        u = _stage_independent(d, t, u, x)
+    got = orc.denoise(x, den)
+    assert np.abs(got - u).max() <= 1e-11 * max(1.0, np.abs(u).max())
+    rev = x.copy()
+    for t in reversed(range(d.stages)):
+        rev = _stage_independent(d, t, rev, x)
+    prev = x.copy()
+    for t in range(d.stages):
+        prev = _stage_independent(d, t, prev, prev)
+    assert np.abs(got - rev).max() > 1e-3
+    assert np.abs(got - prev).max() > 1e-3
 
 
 @pytest.mark.parametrize("c", [0.0, 37.5, 255.0])
@@ -577,6 +608,39 @@ def test_objective_prior_vanishes_on_constants(orc):
     x = op.x0()
     prior = 0.5 * op.lam * (x.ravel() @ (x - op.denoise(x)).ravel())
     assert prior > 0
+
+
+@pytest.mark.parametrize("s", [1, 3])
+def test_objective_closed_form_one_stage_denoiser(orc, s):
+    """Eq. (4) with the data term of eq. (1): E(x) = ||Hx - y||^2 / (2 sigma^2) +
+    (lambda / 2) x^T (x - f(x)). With one stage and f's reaction input equal to x,
+    x - f(x) = sum_i K_i^T phi_i(K_i x), so the prior is (lambda / 2) sum_i <K_i x, phi_i(K_i x)>:
+    built here from scipy reflect correlation and direct Gaussian sums, with H x from an FFT
+    circular convolution (decimated for s = 3). A prior weight of lambda instead of lambda / 2
+    (or a missing 1/2 on the data term) is off by far more than the tolerance."""
+    full = W.make_denoiser()
+    d1 = W.DenoiserParams(1, full.nfilt, full.ksize, full.nrbf, full.mu0, full.dmu, full.gamma,
+                          full.filters[:1], full.rbf_w[:1], full.react[:1])
+    shape = (12, 13)
+    psf = W.psf_gaussian(7, 1.6)
+    sigma, lam = 1.7, 0.05
+    P = W.Problem("obj1", W.make_image(*shape, 1031), psf, s, sigma, lam,
+                  W.make_noise(W.lr_shape(*shape, s), 2031), 15, d1)
+    op = orc.OracleProblem(P)
+    x = W.make_image(*shape, 1032)
+    hx = np.real(np.fft.ifft2(np.fft.fft2(x) * np.fft.fft2(_psf_pad(psf, shape))))[::s, ::s]
+    data = float(((hx - op.y) ** 2).sum()) / (2 * sigma ** 2)
+    mu = d1.mu0 + d1.dmu * np.arange(d1.nrbf)
+    zphi = 0.0
+    for i in range(d1.nfilt):
+        z = ndi.correlate(x, d1.filters[0, i], mode="reflect").ravel()
+        phi = (d1.rbf_w[0, i][None, :] * np.exp(-(z[:, None] - mu[None, :]) ** 2
+                                                 / (2 * d1.gamma ** 2))).sum(1)
+        zphi += float(z @ phi)
+    prior = 0.5 * lam * zphi
+    assert prior > 1e-3 * data
+    E = op.objective(x)
+    assert abs(E - (data + prior)) <= 1e-10 * abs(data + prior)
 
 
 # ------------------------------------------------------------------ exact linear step (footnote to eq. (7))
