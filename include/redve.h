@@ -86,8 +86,10 @@ typedef struct {
     int breakdowns;      /* extrapolations that did not exist (MPE/SVD-MPE, Sec. III-B)  */
     int status;          /* REDVE_OK, or the error the solve ended with                  */
     double final_delta;  /* last ||x_{k+1} - x_k|| / ||x_k|| of two FP iterates          */
-    double max_gamma_l1; /* max over cycles of sum_i |gamma_i| (stability, eq. (21))     */
+    double max_gamma_l1; /* max over accepted cycles of sum_i |gamma_i| (eq. (21))       */
     double ms;           /* wall time of the solve on the host, milliseconds             */
+    int rejected;        /* extrapolations the stability guard rejected (redve_set_guard);
+                            each is also counted in breakdowns                          */
 } redve_stats_t;
 
 /* ---- handle ------------------------------------------------------------------------- */
@@ -136,6 +138,18 @@ int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int 
  * (computed per image in batches). Everything else (extrapolation, stopping, statistics) is
  * the same; "FP call" then counts SD steps. */
 int redve_set_base(redve_t h, int base, double mu);
+/* Stability guard (Sec. III-D, eq. (21)): VE is stable when sum_i |gamma_i| stays bounded
+ * over the cycles, and the extrapolated vector sum_i gamma_i x_{m+i} carries the iterates'
+ * errors magnified by up to that sum. An extrapolation whose sum |gamma| exceeds gamma_cap, or
+ * is not finite, is rejected: the cycle continues from its last FP iterate x_{m+L} (as on a
+ * breakdown, and counted in breakdowns and rejected). The default, +infinity, rejects only
+ * non-finite coefficients (the paper rejects none; windows with sum |gamma| near 1e8 still
+ * accelerate steepest descent); a finite cap bounds the magnification, e.g. 1e3 keeps it below
+ * the 1e-4 relative bar for iterates rounded to FP32. gamma_cap <= 0 turns the guard off (a
+ * non-finite sum then ends the solve with REDVE_E_NONFINITE). Applies to redve_solve,
+ * redve_extrapolate(_noalloc), the batched solve and servers created afterwards.
+ * NaN: REDVE_E_ARG. */
+int redve_set_guard(redve_t h, double gamma_cap);
 /* Linear step of the FP call (eq. (7); its footnote allows the Fourier domain for
  * block-circulant H, or iterative methods). REDVE_LIN_CG (default): cg_iters conjugate-
  * gradient iterations, warm-started. REDVE_LIN_FFT: the exact inverse in the Fourier domain
@@ -181,7 +195,8 @@ int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, d
 /* One extrapolation (Algorithm 1 with the configured method) from the L+1 iterates
  * xs[0..L] (device, each hx x wx, stored consecutively): out = x_(0,kappa), or xs[L] if the
  * extrapolation does not exist. gamma (host, L doubles, may be NULL) receives gamma_0..kappa
- * (zeros on breakdown); *breakdown (host, may be NULL) receives 1 on breakdown.
+ * (zeros on breakdown; the rejected values when the stability guard rejected them);
+ * *breakdown (host, may be NULL) receives 1 on breakdown or rejection.
  * Synchronises the stream. */
 int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* out,
                       double* gamma, int* breakdown);

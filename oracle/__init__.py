@@ -358,6 +358,11 @@ class SDMap:
 # Breakdown thresholds (the paper only says MPE and SVD-MPE may not exist, Sec. III-B).
 RANK_EPS = 1e-13   # R_jj <= RANK_EPS * R_00 counts as a rank-deficient column
 SUM_EPS = 1e-12    # |sum c| <= SUM_EPS * ||c||_1 counts as a vanishing normaliser
+# Stability guard (reading of Sec. III-D, eq. (21)): coefficients with sum |gamma| above a cap,
+# or not finite, are rejected and the cycle continues from its last FP iterate. The default cap
+# is infinite, so only non-finite coefficients are rejected: the paper rejects none, and windows
+# with sum |gamma| near 1e8 still accelerate steepest descent here. Callers may set a finite cap.
+GAMMA_CAP = float("inf")
 
 
 def mgs(U):
@@ -468,6 +473,7 @@ class SolveResult:
     deltas: list
     gamma_l1: list
     trace: list  # (calls, vector) when record=True, else []
+    rejected: int = 0  # extrapolations the stability guard rejected (also in breakdowns)
 
 
 def _rel_change(new, old):
@@ -475,8 +481,12 @@ def _rel_change(new, old):
     return float(np.linalg.norm(new - old) / n) if n > 0 else float("inf")
 
 
-def ve_step(xs, method):
-    """Given x_m .. x_{m+kappa+1} (flattened rows), return (x_new, gamma, broke_down)."""
+def ve_step(xs, method, gamma_cap=GAMMA_CAP):
+    """Given x_m .. x_{m+kappa+1} (flattened rows), return (x_new, gamma, broke_down).
+
+    When the coefficients exist but sum |gamma| exceeds gamma_cap (> 0), or is not finite,
+    they are rejected by the stability guard: x_new is the last iterate, broke_down is True
+    and gamma is returned for the statistics."""
     X = np.stack([np.ravel(v) for v in xs], axis=1)
     U = X[:, 1:] - X[:, :-1]                     # Algorithm 1, step 1
     Q, R = mgs(U)                                 # Algorithm 2
@@ -490,11 +500,13 @@ def ve_step(xs, method):
         raise ValueError(method)
     if g is None:
         return X[:, -1].copy(), None, True
+    if gamma_cap is not None and gamma_cap > 0 and not (np.abs(g).sum() <= gamma_cap):
+        return X[:, -1].copy(), g, True
     return extrapolate(X[:, 0], Q, R, g), g, False
 
 
 def solve(op: OracleProblem, method="none", L=5, m=0, tol=1e-5, max_calls=500, extra_fp=0,
-          x0=None, record=False, on_vector=None):
+          x0=None, record=False, on_vector=None, gamma_cap=GAMMA_CAP):
     """Plain FP (method='none') or Algorithm 3 (full cycling) with MPE/RRE/SVD-MPE.
 
     Cycle: m FP calls to reach x_m, then L = kappa+1 more to x_{m+kappa+1}; extrapolate;
@@ -502,10 +514,11 @@ def solve(op: OracleProblem, method="none", L=5, m=0, tol=1e-5, max_calls=500, e
     consecutive FP iterates drops below tol, or the total FP-call budget is spent. If the
     budget ends inside a cycle, the last FP iterate is returned. `extra_fp` FP calls follow.
     `on_vector(calls, x)` sees every vector the solve could return (FP iterates and
-    extrapolated vectors)."""
+    extrapolated vectors). gamma_cap is the stability guard of ve_step (<= 0 or None: off);
+    a rejected extrapolation counts as a breakdown and in `rejected`."""
     shape = op.shape
     x = op.x0() if x0 is None else _f64(x0).copy()
-    calls = cycles = breakdowns = 0
+    calls = cycles = breakdowns = rejected = 0
     deltas, gl1, trace = [], [], []
 
     def note(v):
@@ -541,10 +554,11 @@ def solve(op: OracleProblem, method="none", L=5, m=0, tol=1e-5, max_calls=500, e
                 x = xs[-1]
                 break
             xw = xs[m:]
-            xnew, g, broke = ve_step(xw, method)
+            xnew, g, broke = ve_step(xw, method, gamma_cap)
             cycles += 1
             if broke:
                 breakdowns += 1
+                rejected += g is not None
             else:
                 gl1.append(float(np.abs(g).sum()))
             x = xnew.reshape(shape)
@@ -555,4 +569,4 @@ def solve(op: OracleProblem, method="none", L=5, m=0, tol=1e-5, max_calls=500, e
         x = op.fp(x)
         calls += 1
         note(x)
-    return SolveResult(x, calls, cycles, breakdowns, deltas, gl1, trace)
+    return SolveResult(x, calls, cycles, breakdowns, deltas, gl1, trace, rejected)

@@ -35,6 +35,7 @@ EXPORTS = (
     "redve_apply_A", "redve_cg", "redve_denoise", "redve_fp_step", "redve_objective",
     "redve_extrapolate", "redve_solve_batch", "redve_server_create", "redve_server_submit",
     "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
+    "redve_set_guard",
 )
 
 
@@ -64,7 +65,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("fp_calls", ctypes.c_int), ("cycles", ctypes.c_int),
                 ("breakdowns", ctypes.c_int), ("status", ctypes.c_int),
                 ("final_delta", ctypes.c_double), ("max_gamma_l1", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("rejected", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "redve_server_counts": ([vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                  ctypes.POINTER(ctypes.c_longlong)], i),
         "redve_server_destroy": ([vp], i),
+        "redve_set_guard": ([vp, d], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -229,6 +231,11 @@ class Restorer:
         self._check(self._L.redve_set_base(self._h, BASES[base], float(mu)))
         return self
 
+    def set_guard(self, gamma_cap: float):
+        """Stability guard on sum |gamma| (<= 0: off)."""
+        self._check(self._L.redve_set_guard(self._h, float(gamma_cap)))
+        return self
+
     def set_linear_solver(self, kind: str = "cg"):
         """Linear step of the FP call: "cg" (cg_iters iterations) or "fft" (exact, deblurring)."""
         self._check(self._L.redve_set_linear_solver(self._h, LINEAR[kind]))
@@ -252,8 +259,12 @@ class Restorer:
         if out is None:
             out = torch.empty((hx, wx), dtype=torch.float32, device=y.device)
         st = Stats()
-        self._check(self._L.redve_solve(self._h, _dev(y, (hy, wy)), hy, wy, _dev(x0, (hx, wx)),
-                                        _dev(out, (hx, wx)), hx, wx, ctypes.byref(st)))
+        rc = self._L.redve_solve(self._h, _dev(y, (hy, wy)), hy, wy, _dev(x0, (hx, wx)),
+                                 _dev(out, (hx, wx)), hx, wx, ctypes.byref(st))
+        if rc != OK:  # the statistics of the failed solve travel with the error
+            err = RedveError(rc, self._L.redve_last_error(self._h).decode())
+            err.stats = st.as_dict()
+            raise err
         return out, st.as_dict()
 
     # -- single steps

@@ -80,7 +80,7 @@ struct Slot {
     // Algorithm 3 state
     int cur = 0, base = 0, phase = 0, extra_left = 0;
     bool extra = false;
-    int calls = 0, cycles = 0, breakdowns = 0, status = REDVE_OK;
+    int calls = 0, cycles = 0, breakdowns = 0, rejected = 0, status = REDVE_OK;
     double delta = INFINITY, gl1max = 0.0;
     Progress prog;
     // round bookkeeping
@@ -430,8 +430,8 @@ struct Engine {
     }
 
     int record_ve(int nt) {
-        launch_ve_solve_batch(d_desc, cap_img, L, h->method, h->rank_eps, d_G, d_info, d_stat,
-                              st);
+        launch_ve_solve_batch(d_desc, cap_img, L, h->method, h->rank_eps, h->gamma_cap, d_G,
+                              d_info, d_stat, st);
         launch_ve_combine_batch(d_desc, d_tile, nt, U, cap_px, d_info, st);
         return hipGetLastError() == hipSuccess ? REDVE_OK : REDVE_E_HIP;
     }
@@ -575,9 +575,10 @@ struct Engine {
                         sl.breakdowns++;
                     else
                         sl.gl1max = std::max(sl.gl1max, s.gamma_l1);
+                    if (s.guarded) sl.rejected++;
                     sl.cur = sl.base;  // x_(m,kappa) was combined into the window base
                     sl.phase = 0;
-                    if (!std::isfinite(s.gamma_l1)) sl.status = REDVE_E_NONFINITE;
+                    if (!s.guarded && !std::isfinite(s.gamma_l1)) sl.status = REDVE_E_NONFINITE;
                     else sl.status = sl.prog.check(sl.delta);
                     if (sl.status || sl.delta < h->tol || sl.calls >= h->max_fp) stop = true;
                 } else if (sl.calls >= h->max_fp) {
@@ -599,6 +600,7 @@ struct Engine {
         st->fp_calls = sl.calls;
         st->cycles = sl.cycles;
         st->breakdowns = sl.breakdowns;
+        st->rejected = sl.rejected;
         st->status = sl.status;
         st->final_delta = sl.delta;
         st->max_gamma_l1 = sl.gl1max;
@@ -828,6 +830,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.extra_fp = proto->extra_fp;
     c.tol = proto->tol;
     c.rank_eps = proto->rank_eps;
+    c.gamma_cap = proto->gamma_cap;
     c.base = proto->base;
     c.sd_mu = proto->sd_mu;
     if (hipSetDevice(c.device) != hipSuccess) return REDVE_E_HIP;

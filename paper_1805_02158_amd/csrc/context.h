@@ -2,6 +2,8 @@
 // batched / serving engine).
 #pragma once
 
+#include <math.h>
+
 #include <string>
 #include <vector>
 
@@ -91,6 +93,7 @@ struct redve_ctx {
     double sd_mu = 0.0;        // steepest-descent step (<= 0: 1 / (||H||^2/sigma^2 + 2 lambda))
     double psf_l1 = 1.0;       // sum |h|, a bound on ||H||
     double rank_eps = 1e-7;  // R_jj <= rank_eps * R_00 counts as rank deficient (FP32 data)
+    double gamma_cap = INFINITY;  // stability guard on sum |gamma| (<= 0: off)
     Workspace ws;
     HostMirror* host = nullptr;  // pinned
     // Settings generation: bumped by every setter that changes what a captured batched round

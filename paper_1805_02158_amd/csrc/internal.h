@@ -97,8 +97,8 @@ struct VeInfo;
 struct ImgStat {
     double uu, xx;     // ||x_out - x_in||^2, ||x_in||^2 of this FP call
     double gamma_l1;   // sum |gamma| of the extrapolation (0 if none)
-    int breakdown;     // 1 if the extrapolation did not exist
-    int pad;
+    int breakdown;     // 1 if the extrapolation did not exist (or was rejected)
+    int guarded;       // 1 if the stability guard rejected it
 };
 // Per-image CG scalars of the batched single-reduction CG.
 struct CgImg {
@@ -127,7 +127,8 @@ void launch_diff_gram_batch(const ImgDesc* desc, const TileRef* tiles, int ntile
 void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* part, int cap,
                            double* G, ImgStat* stat, hipStream_t st);
 void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
-                           const double* G, VeInfo* info, ImgStat* stat, hipStream_t st);
+                           double gamma_cap, const double* G, VeInfo* info, ImgStat* stat,
+                           hipStream_t st);
 void launch_ve_combine_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, const float* U,
                              size_t ustride, const VeInfo* info, hipStream_t st);
 
@@ -284,14 +285,15 @@ struct VeInfo {
     double gamma_l1;
     double uu, xx;   // ||u_last||^2, ||x_prev||^2 of the last difference (relative change)
     int ncols;       // columns of U combined (kappa, or L on breakdown)
-    int breakdown;   // 1 if the extrapolation did not exist
+    int breakdown;   // 1 if the extrapolation did not exist, or the stability guard rejected it
     int kappa_used;  // kappa after any RRE column drops
-    int pad;
+    int guarded;     // 1 if the stability guard rejected the coefficients (gamma, gamma_l1 kept)
 };
 // Sums the partials of the L difference passes (column j's at part + j * win_stride, each
-// written by nblk workgroups) into G, then Cholesky / MPE / RRE / SVD-MPE.
+// written by nblk workgroups) into G, then Cholesky / MPE / RRE / SVD-MPE; coefficients with
+// sum |gamma| above gamma_cap (or not finite) are rejected when gamma_cap > 0.
 void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int method,
-                     double rank_eps, VeInfo* info, hipStream_t st);
+                     double rank_eps, double gamma_cap, VeInfo* info, hipStream_t st);
 // Sums the partials of a single difference pass (j = 0) into info->uu, info->xx.
 void launch_delta(const double* part, int nblk, VeInfo* info, hipStream_t st);
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,

@@ -81,8 +81,9 @@ __device__ inline float phi_table(float z, const float* tab, const RbfParams& p)
 // recurrence only.
 template <int KC>
 __device__ inline float phi_eval(float z, const float* wrow, const RbfParams& p) {
-    int j0 = (int)rintf((z - p.mu0) * p.inv_dmu);
-    j0 = min(max(j0, 0), p.J - 1);
+    // nearest centre, clamped in floating point before the conversion, so that any z (NaN and
+    // infinities included) reads inside the padded weight row
+    const int j0 = (int)fminf(fmaxf(rintf((z - p.mu0) * p.inv_dmu), 0.f), (float)(p.J - 1));
     const float d0r = z - (p.mu0 + p.dmu * (float)j0);
     const float* wc = wrow + kRbfPad + j0;
     if (KC > 0 && fabsf(d0r) <= p.half_dmu) {

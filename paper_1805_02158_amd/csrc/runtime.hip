@@ -381,8 +381,8 @@ int enqueue_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float*
             cur = nxt;
             if (i == h->m - 1) wbase = cur;
         }
-        launch_ve_solve(w.ve_part, w.win_stride, nblk, h->L, h->method, h->rank_eps, w.info,
-                        h->stream);
+        launch_ve_solve(w.ve_part, w.win_stride, nblk, h->L, h->method, h->rank_eps,
+                        h->gamma_cap, w.info, h->stream);
         launch_ve_combine(wbase, w.U, n, w.info, wbase, h->stream);
         LAUNCH_CHECK(h);
         *next = wbase;
@@ -787,6 +787,15 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m) {
     return REDVE_OK;
 }
 
+int redve_set_guard(redve_t h, double gamma_cap) {
+    if (!h) return REDVE_E_ARG;
+    if (std::isnan(gamma_cap)) return fail(h, REDVE_E_ARG, "gamma_cap must not be NaN");
+    const double cap = gamma_cap > 0.0 ? gamma_cap : 0.0;
+    if (cap != h->gamma_cap) ++h->gen;  // captured passes and batched rounds record it
+    h->gamma_cap = cap;
+    return REDVE_OK;
+}
+
 int redve_set_linear_solver(redve_t h, int kind) {
     if (!h) return REDVE_E_ARG;
     if (kind != REDVE_LIN_CG && kind != REDVE_LIN_FFT) return fail(h, REDVE_E_ARG, "bad solver");
@@ -927,7 +936,8 @@ int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* 
                                 w.ve_part + j * w.win_stride, h->stream);
         LAUNCH_CHECK(h);
     }
-    launch_ve_solve(w.ve_part, w.win_stride, nblk, L, h->method, h->rank_eps, w.info, h->stream);
+    launch_ve_solve(w.ve_part, w.win_stride, nblk, L, h->method, h->rank_eps, h->gamma_cap, w.info,
+                    h->stream);
     launch_ve_combine(xs, w.U, n, w.info, out, h->stream);
     LAUNCH_CHECK(h);
     if ((rc = read_back(h))) return rc;
@@ -970,7 +980,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
                               h->stream));
     const float* yw = w.yw;
 
-    int calls = 0, cycles = 0, breakdowns = 0, status = REDVE_OK;
+    int calls = 0, cycles = 0, breakdowns = 0, rejected = 0, status = REDVE_OK;
     double delta = INFINITY, gl1max = 0.0;
     Progress prog;
     float* x_cur = w.xa;
@@ -1008,12 +1018,15 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
             calls += h->m + L;
             x_cur = next;
             ++cycles;
-            if (h->host->info.breakdown)
+            const VeInfo& vi = h->host->info;
+            if (vi.breakdown)
                 ++breakdowns;
             else
-                gl1max = std::max(gl1max, h->host->info.gamma_l1);
-            delta = sqrt(h->host->info.uu / h->host->info.xx);
-            if (!std::isfinite(h->host->info.gamma_l1)) {
+                gl1max = std::max(gl1max, vi.gamma_l1);
+            if (vi.guarded) ++rejected;
+            delta = sqrt(vi.uu / vi.xx);
+            // rejected coefficients are not used; a non-finite iterate shows in delta
+            if (!vi.guarded && !std::isfinite(vi.gamma_l1)) {
                 status = REDVE_E_NONFINITE;
                 break;
             }
@@ -1035,6 +1048,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
         st->fp_calls = calls;
         st->cycles = cycles;
         st->breakdowns = breakdowns;
+        st->rejected = rejected;
         st->status = status;
         st->final_delta = delta;
         st->max_gamma_l1 = gl1max;

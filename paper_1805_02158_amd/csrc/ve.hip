@@ -99,29 +99,40 @@ __device__ bool mpe(const double (*R)[MAXL], int k, double eps, double* gamma, S
     return true;
 }
 
-// RRE (eq. (19)): R^T R d = 1, gamma = d / sum(d). A dependent last column: MPE's null vector
-// attains ||U gamma|| = 0; if MPE does not exist either, RRE_k = RRE_{k-1} (Sec. III-B).
+// RRE on the leading k + 1 columns of a full-rank R (eq. (19)): R^T R d = 1 by forward then
+// backward substitution, gamma = d / sum(d).
+__device__ __noinline__ void rre_full(const double (*R)[MAXL], int k, double* gamma,
+                                      SolveWork& ws) {
+    double* ones = ws.t0;
+    double* w = ws.t1;
+    double* d = ws.t2;
+    for (int i = 0; i <= k; ++i) ones[i] = 1.0;
+    fwd_sub_t(R, k + 1, ones, w);
+    back_sub(R, k + 1, w, d);
+    double s = 0.0;
+    for (int i = 0; i <= k; ++i) s += d[i];
+    for (int i = 0; i <= k; ++i) gamma[i] = d[i] / s;
+}
+
+// RRE (eq. (19)). A dependent last column: MPE's null vector attains ||U gamma|| = 0; if MPE
+// does not exist either, RRE_k = RRE_{k-1} (Sec. III-B). Returns the kappa used. The column
+// count of each attempt is a loop variable of its own: the form that decremented the argument
+// in an unbounded loop was compiled for gfx950 (run-time window sizes) into code that solved
+// with one column count and returned another.
 __device__ int rre(const double (*R)[MAXL], int k, double eps, double* gamma, SolveWork& ws) {
-    while (true) {
-        if (full_rank(R, k + 1, eps)) {
-            double* ones = ws.t0;
-            double* w = ws.t1;
-            double* d = ws.t2;
-            for (int i = 0; i <= k; ++i) ones[i] = 1.0;
-            fwd_sub_t(R, k + 1, ones, w);
-            back_sub(R, k + 1, w, d);
-            double s = 0.0;
-            for (int i = 0; i <= k; ++i) s += d[i];
-            for (int i = 0; i <= k; ++i) gamma[i] = d[i] / s;
-            return k;
+    for (int kk = k; kk >= 1; --kk) {
+        if (full_rank(R, kk + 1, eps)) {
+            rre_full(R, kk, gamma, ws);
+            return kk;
         }
-        if (k == 0) {
-            gamma[0] = 1.0;
-            return 0;
-        }
-        if (mpe(R, k, eps, gamma, ws)) return k;
-        --k;
+        if (mpe(R, kk, eps, gamma, ws)) return kk;
     }
+    if (full_rank(R, 1, eps)) {
+        rre_full(R, 0, gamma, ws);
+    } else {
+        gamma[0] = 1.0;
+    }
+    return 0;
 }
 
 // SVD-MPE (Sec. III-B): gamma = v / sum(v), v the right singular vector of the smallest
@@ -217,6 +228,7 @@ __device__ void small_solve(const double* G, int ldG, int L, int method, double 
         info->xi[i] = 0.0;
         info->gamma[i] = 0.0;
     }
+    info->guarded = 0;
     if (!ok) {
         // no extrapolation: x_m + sum of all L differences = the last FP iterate
         for (int j = 0; j < L; ++j) info->xi[j] = 1.0;
@@ -340,6 +352,7 @@ __device__ bool small_solve_reg(const double* G, int ldG, int method, double ran
     info->breakdown = 0;
     info->kappa_used = k;
     info->gamma_l1 = l1;
+    info->guarded = 0;
     return true;
 }
 
@@ -356,6 +369,19 @@ __device__ bool small_solve_fast(const double* G, int ldG, int L, int method, do
     }
 }
 
+// Stability guard (Sec. III-D, eq. (21): the extrapolated vector sum_i gamma_i x_{m+i} carries
+// the iterates' errors magnified by up to sum |gamma_i|). With cap > 0, coefficients whose
+// sum |gamma| exceeds cap, or is not finite, are rejected: the cycle continues from its last FP
+// iterate x_{m+L} (xi = 1 on all L columns), counted as a breakdown; gamma and gamma_l1 keep
+// the rejected values for the statistics.
+__device__ void guard_extrapolation(VeInfo* __restrict__ info, int L, double cap) {
+    if (!(cap > 0.0) || info->breakdown || info->gamma_l1 <= cap) return;
+    for (int j = 0; j < MAXL; ++j) info->xi[j] = j < L ? 1.0 : 0.0;
+    info->ncols = L;
+    info->breakdown = 1;
+    info->guarded = 1;
+}
+
 // Sums the window's published partials into the Gram matrix (fixed order, FP64; one wave per
 // entry, 16 waves), then the L x L work on one thread.
 constexpr int kSolveThreads = 1024;
@@ -363,6 +389,7 @@ constexpr int kSolveThreads = 1024;
 __global__ __launch_bounds__(kSolveThreads) void k_ve_solve(const double* __restrict__ part,
                                                             size_t win_stride, int nblk, int L,
                                                             int method, double rank_eps,
+                                                            double gamma_cap,
                                                             VeInfo* __restrict__ info) {
     __shared__ double G[MAXL * MAXL];
     __shared__ double norms[2];
@@ -414,6 +441,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_ve_solve(const double* __rest
     info->xx = norms[1];
     if (!small_solve_fast(G, MAXL, L, method, rank_eps, info))
         small_solve(G, MAXL, L, method, rank_eps, info, ws);
+    guard_extrapolation(info, L, gamma_cap);
 }
 
 // Algorithm 1, step 4: x_(m,kappa) = x_m + U_{kappa-1} xi (= x_m + Q_{kappa-1} eta).
@@ -517,6 +545,7 @@ __global__ __launch_bounds__(256) void k_diff_fin_batch(const ImgDesc* __restric
 // Per image that completes its window this round: the L x L solve.
 __global__ __launch_bounds__(64) void k_ve_solve_batch(const ImgDesc* __restrict__ desc, int L,
                                                        int method, double rank_eps,
+                                                       double gamma_cap,
                                                        const double* __restrict__ G,
                                                        VeInfo* __restrict__ info,
                                                        ImgStat* __restrict__ stat) {
@@ -525,8 +554,10 @@ __global__ __launch_bounds__(64) void k_ve_solve_batch(const ImgDesc* __restrict
     if (!d.active || !d.do_ve || threadIdx.x != 0) return;
     VeInfo* in = info + blockIdx.x;
     small_solve(G + (size_t)blockIdx.x * MAXL * MAXL, MAXL, L, method, rank_eps, in, ws);
+    guard_extrapolation(in, L, gamma_cap);
     stat[blockIdx.x].gamma_l1 = in->gamma_l1;
     stat[blockIdx.x].breakdown = in->breakdown;
+    stat[blockIdx.x].guarded = in->guarded;
 }
 
 // x_m = x_m + U_{kappa-1} xi on one tile of an image that extrapolates this round.
@@ -575,8 +606,9 @@ void launch_delta(const double* part, int nblk, VeInfo* info, hipStream_t st) {
 }
 
 void launch_ve_solve(const double* part, size_t win_stride, int nblk, int L, int method,
-                     double rank_eps, VeInfo* info, hipStream_t st) {
-    k_ve_solve<<<1, kSolveThreads, 0, st>>>(part, win_stride, nblk, L, method, rank_eps, info);
+                     double rank_eps, double gamma_cap, VeInfo* info, hipStream_t st) {
+    k_ve_solve<<<1, kSolveThreads, 0, st>>>(part, win_stride, nblk, L, method, rank_eps,
+                                             gamma_cap, info);
 }
 
 void launch_ve_combine(const float* x_m, const float* U, int n, const VeInfo* info, float* out,
@@ -605,8 +637,9 @@ void launch_diff_fin_batch(const ImgDesc* desc, int nimg, int L, const double* p
 }
 
 void launch_ve_solve_batch(const ImgDesc* desc, int nimg, int L, int method, double rank_eps,
-                           const double* G, VeInfo* info, ImgStat* stat, hipStream_t st) {
-    k_ve_solve_batch<<<nimg, 64, 0, st>>>(desc, L, method, rank_eps, G, info, stat);
+                           double gamma_cap, const double* G, VeInfo* info, ImgStat* stat,
+                           hipStream_t st) {
+    k_ve_solve_batch<<<nimg, 64, 0, st>>>(desc, L, method, rank_eps, gamma_cap, G, info, stat);
 }
 
 void launch_ve_combine_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, const float* U,

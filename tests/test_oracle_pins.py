@@ -469,6 +469,47 @@ def test_rre_when_mpe_does_not_exist(orc):
     assert abs(g.sum() - 1) < 1e-12
 
 
+@pytest.mark.parametrize("method", ["mpe", "rre", "svd_mpe"])
+def test_stability_guard_closed_form(orc, method):
+    """Sec. III-D, eq. (21), on one geometric mode x_k = x* + v lam^k with L = 2 (kappa = 1):
+    U = [u, lam u] has rank one, every variant's coefficients are gamma = (-lam, 1) / (1 - lam)
+    (MPE: c = (-lam, 1); RRE takes MPE's null vector; SVD-MPE the null singular vector), so
+    sum |gamma| = (1 + lam) / (1 - lam) = 1999 at lam = 0.999 in closed form, and the exact
+    extrapolation is x*. A cap above that sum keeps x*; below it the guard returns the last
+    iterate, flagged as a breakdown, with the rejected coefficients. (The differences lose
+    five digits to cancellation, which 1 / (1 - lam) magnifies: gamma agrees to 1e-7.)"""
+    rng = np.random.default_rng(77)
+    lam = 0.999
+    xstar = rng.uniform(50, 200, 40)
+    v = rng.standard_normal(40)
+    xs = [xstar + v * lam ** k for k in range(3)]
+    l1 = (1 + lam) / (1 - lam)
+    x, g, broke = orc.ve_step(xs, method, gamma_cap=2500.0)
+    assert not broke and abs(np.abs(g).sum() - l1) <= 1e-7 * l1
+    assert np.allclose(g, np.array([-lam, 1.0]) / (1 - lam), rtol=1e-7)
+    assert np.linalg.norm(x - xstar) <= 1e-9 * np.linalg.norm(xstar)
+    x, g, broke = orc.ve_step(xs, method, gamma_cap=1500.0)
+    assert broke and np.array_equal(x, xs[-1]) and abs(np.abs(g).sum() - l1) <= 1e-7 * l1
+    x, g, broke = orc.ve_step(xs, method, gamma_cap=0)  # off
+    assert not broke and np.linalg.norm(x - xstar) <= 1e-9 * np.linalg.norm(xstar)
+
+
+def test_guard_rejecting_every_window_is_plain_fp(orc):
+    """sum |gamma| >= |sum gamma| = 1, so a cap below 1 rejects every extrapolation: each cycle
+    then continues from its last FP iterate and the solve is plain FP, call for call (the
+    rejected cycles count as breakdowns)."""
+    P = W.Problem("guard", W.make_image(16, 16, 1011), W.psf_gaussian(7, 1.6), 1, W.SQRT2, 0.02,
+                  W.make_noise((16, 16), 2011), 10, W.make_denoiser())
+    op = orc.OracleProblem(P)
+    plain = orc.solve(op, "none", tol=0.0, max_calls=15)
+    for method in ("mpe", "rre", "svd_mpe"):
+        r = orc.solve(op, method, L=5, m=0, tol=0.0, max_calls=15, gamma_cap=0.5)
+        assert r.cycles == 3 and r.breakdowns == 3 and r.rejected == 3
+        assert np.array_equal(r.x, plain.x)
+        free = orc.solve(op, method, L=5, m=0, tol=0.0, max_calls=15)
+        assert free.rejected == 0 and not np.array_equal(free.x, plain.x)
+
+
 # ------------------------------------------------------------------ the RED fixed point
 
 
