@@ -201,6 +201,26 @@ int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, d
 int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* out,
                       double* gamma, int* breakdown);
 
+/* ---- without device allocation -------------------------------------------------------- */
+
+/* Size of the library's fixed device scratch array (one per GPU, held until the process
+ * ends). */
+#define REDVE_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): redve_extrapolate with the same arguments, kernels,
+ * results and synchronisation, but its difference columns, Gram partials and small-solve
+ * result live in the library's fixed scratch array instead of the handle's workspace; it calls
+ * no allocating routine. Limit: L * hx * wx <= redve_extrapolate_noalloc_max(L) values
+ * (7,831,360 at REDVE_NOALLOC_SCRATCH_BYTES = 32 MiB, e.g. 1024 x 1024 with L = 7), else
+ * REDVE_E_ARG with nothing queued. All calls on one GPU share that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (several handles or host threads, or
+ * streams not ordered with each other) race and must be serialised by the caller. */
+int redve_extrapolate_noalloc(redve_t h, const float* xs, int L, int hx, int wx, float* out,
+                              double* gamma, int* breakdown);
+/* Largest hx * wx redve_extrapolate_noalloc accepts for window L (0 if L is out of range). */
+size_t redve_extrapolate_noalloc_max(int L);
+
 /* ---- batched solve (many images of different sizes in one set of launches) ------------- */
 
 /* One restoration of a batch or a serving request. Device pointers are caller-owned and must

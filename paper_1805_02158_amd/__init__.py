@@ -35,7 +35,7 @@ EXPORTS = (
     "redve_apply_A", "redve_cg", "redve_denoise", "redve_fp_step", "redve_objective",
     "redve_extrapolate", "redve_solve_batch", "redve_server_create", "redve_server_submit",
     "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
-    "redve_set_guard",
+    "redve_extrapolate_noalloc", "redve_extrapolate_noalloc_max", "redve_set_guard",
 )
 
 
@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
         "redve_server_counts": ([vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                  ctypes.POINTER(ctypes.c_longlong)], i),
         "redve_server_destroy": ([vp], i),
+        "redve_extrapolate_noalloc": ([vp, vp, i, i, i, vp, dp, ctypes.POINTER(i)], i),
+        "redve_extrapolate_noalloc_max": ([i], sz),
         "redve_set_guard": ([vp, d], i),
     }
     for name, (args, res) in sig.items():
@@ -348,6 +350,23 @@ class Restorer:
                                               g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                               ctypes.byref(bd)))
         return out, g, bool(bd.value)
+
+    def extrapolate_noalloc(self, xs, out=None):
+        """As extrapolate, through the entry point that allocates no device memory (the
+        library's fixed scratch array; h w at most extrapolate_noalloc_max(L))."""
+        n1, hx, wx = xs.shape
+        L = n1 - 1
+        if out is None:
+            out = self._empty((hx, wx), xs)
+        g = np.zeros(L)
+        bd = ctypes.c_int(0)
+        self._check(self._L.redve_extrapolate_noalloc(
+            self._h, _dev(xs), L, hx, wx, _dev(out, (hx, wx)),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(bd)))
+        return out, g, bool(bd.value)
+
+    def extrapolate_noalloc_max(self, L: int) -> int:
+        return int(self._L.redve_extrapolate_noalloc_max(int(L)))
 
 
 class Server:

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libredve.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["linear.hip", "tnrd.hip", "tnrd_mfma.hip", "ve.hip", "runtime.hip", "batch.hip",
-           "fft.hip"]
+           "noalloc.hip", "fft.hip"]
 ROCM_LIB = "/opt/rocm/lib"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

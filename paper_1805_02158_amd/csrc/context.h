@@ -119,6 +119,9 @@ struct redve_ctx {
 int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, float* d, int H,
                          int W);
 
+// Resolves the no-allocation scratch array on `device` (current) once (noalloc.hip).
+int redve_noalloc_resolve(int device);
+
 // Device view of the handle's denoiser (runtime.hip).
 redve::TnrdDev redve_tnrd_dev(redve_t h);
 

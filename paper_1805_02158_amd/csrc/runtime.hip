@@ -493,6 +493,7 @@ int redve_create(redve_t* out, int device, void* hip_stream) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return REDVE_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return REDVE_E_HIP;
+    if (redve_noalloc_resolve(device) != REDVE_OK) return REDVE_E_HIP;
     redve_t h = new redve_ctx();
     h->device = device;
     h->stream = (hipStream_t)hip_stream;
