@@ -152,11 +152,11 @@ int redve_set_base(redve_t h, int base, double mu);
 int redve_set_guard(redve_t h, double gamma_cap);
 /* Linear step of the FP call (eq. (7); its footnote allows the Fourier domain for
  * block-circulant H, or iterative methods). REDVE_LIN_CG (default): cg_iters conjugate-
- * gradient iterations, warm-started. REDVE_LIN_FFT: the exact inverse in the Fourier domain
- * (single-precision real transforms of rocFFT on the FP64-accumulated residual), for
- * deblurring only (decim = 1; solve and fp_step return REDVE_E_ARG otherwise); the batched
- * engine and the server use CG and refuse it. In this build REDVE_LIN_FFT is disabled and
- * returns REDVE_E_STATE. */
+ * gradient iterations, warm-started. REDVE_LIN_FFT: the exact inverse in the Fourier domain,
+ * d = F^-1[F(r0) / (|h_hat|^2 / sigma^2 + lambda)] on the FP64-accumulated residual r0, by the
+ * library's own FP32 mixed-radix FFT kernels (any side length; lengths with a large prime
+ * factor are slower), for deblurring only (decim = 1) and sides up to 4096: solve and fp_step
+ * return REDVE_E_ARG otherwise. The batched engine and the server use CG and refuse it. */
 int redve_set_linear_solver(redve_t h, int kind);
 
 /* Solve: y (device, hy x wy) -> x (device, hx x wx), hy = ceil(hx/decim), wy = ceil(wx/decim).

@@ -17,7 +17,6 @@ OUT = os.path.join(HERE, "libredve.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["linear.hip", "tnrd.hip", "tnrd_mfma.hip", "ve.hip", "runtime.hip", "batch.hip",
            "noalloc.hip", "fft.hip"]
-ROCM_LIB = "/opt/rocm/lib"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -40,8 +39,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-           "-L" + ROCM_LIB, "-lrocfft", "-Wl,-rpath," + ROCM_LIB]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

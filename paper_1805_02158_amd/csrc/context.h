@@ -115,6 +115,8 @@ struct redve_ctx {
     bool graphs_off = false;
 };
 
+// Whether the Fourier linear step supports an hx x wx image (fft.hip).
+bool redve_fft_size_ok(int H, int W);
 // d = F^-1[F(r0) / A_hat], x_out = x_in + d for periodic deblurring (fft.hip).
 int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, float* d, int H,
                          int W);

@@ -177,6 +177,13 @@ int check_image(redve_t h, int hx, int wx) {
     return REDVE_OK;
 }
 
+// The Fourier linear step's transforms hold a row or a block of columns in LDS.
+int check_fft_size(redve_t h, int hx, int wx) {
+    if (h->lin == REDVE_LIN_FFT && h->base == REDVE_BASE_FP && !redve_fft_size_ok(hx, wx))
+        return fail(h, REDVE_E_ARG, "the Fourier linear step supports sides up to 4096");
+    return REDVE_OK;
+}
+
 // Denoiser f. residual = true writes f(x) - x (nothing, and *out_null = true, for T = 0);
 // otherwise f(x).
 int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool residual,
@@ -800,8 +807,6 @@ int redve_set_guard(redve_t h, double gamma_cap) {
 int redve_set_linear_solver(redve_t h, int kind) {
     if (!h) return REDVE_E_ARG;
     if (kind != REDVE_LIN_CG && kind != REDVE_LIN_FFT) return fail(h, REDVE_E_ARG, "bad solver");
-    if (kind == REDVE_LIN_FFT)  // disabled until its GPU run is understood; see the design notes
-        return fail(h, REDVE_E_STATE, "the Fourier linear step is disabled in this build");
     h->lin = kind;
     return REDVE_OK;
 }
@@ -913,7 +918,9 @@ int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, flo
     if (!h) return REDVE_E_ARG;
     if (!y || !x || !out || x == out) return fail(h, REDVE_E_ARG, "bad pointers");
     int rc = check_image(h, hx, wx);
-    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h))) return rc;
+    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h)) ||
+        (rc = check_fft_size(h, hx, wx)))
+        return rc;
     HIP_TRY(h, hipSetDevice(h->device));
     if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
     return fp_call(h, y, x, out, hx, wx);
@@ -955,7 +962,9 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     if (st) memset(st, 0, sizeof(*st));
     if (!y || !x) return fail(h, REDVE_E_ARG, "null pointer");
     int rc = check_image(h, hx, wx);
-    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h))) return rc;
+    if (rc || (rc = check_ready(h, true)) || (rc = check_linear(h)) ||
+        (rc = check_fft_size(h, hx, wx)))
+        return rc;
     if (hy != (hx + h->decim - 1) / h->decim || wy != (wx + h->decim - 1) / h->decim)
         return fail(h, REDVE_E_ARG, "observation size does not match ceil(x size / decim)");
     HIP_TRY(h, hipSetDevice(h->device));

@@ -1,15 +1,15 @@
 """The exact Fourier linear step (redve_set_linear_solver(REDVE_LIN_FFT)) against the oracle's
 ExactFPMap (the FP map of eq. (7) with A inverted in the DFT basis, numpy FFT in FP64): one FP
-call, fixed-schedule solves with and without extrapolation, a converged solve on the fixed
-point shared with the CG map, and the refusals (super-resolution, batched engine)."""
+call on sizes that take every radix path of the library's FFT (powers of two, 3 and 5, and
+prime lengths 37 and 53 that take the direct-sum stage), fixed-schedule solves with and without
+extrapolation, a converged solve on the fixed point shared with the CG map, and the refusals
+(super-resolution, sides above 4096, batched engine)."""
 import numpy as np
 import pytest
 
 import workload as W
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="the rocFFT linear step is disabled: its first GPU run ended with the device reported faulted and no "
-           "output, and no cause was found in the code; it stays off the GPU until one is shown")]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -55,8 +55,16 @@ def ragged():
                      W.make_noise((37, 53), 1800), 15, W.make_denoiser())
 
 
+def sized(h, w, seed):
+    """Uniform 9x9 deblurring of an h x w image (sizes chosen for their factors)."""
+    return W.Problem(f"u9_{h}x{w}", W.make_image(h, w, seed), W.psf_uniform(9), 1, W.SQRT2, 0.02,
+                     W.make_noise((h, w), seed + 100), 15, W.make_denoiser())
+
+
 PROBLEMS = {"tiny": lambda: W.problem("tiny"), "deblur64": lambda: W.problem("deblur64"),
-            "ragged": ragged, "deblur256": lambda: W.problem("deblur256")}
+            "ragged": ragged, "deblur256": lambda: W.problem("deblur256"),
+            "45x60": lambda: sized(45, 60, 1901), "2x3": lambda: sized(2, 3, 1902),
+            "384x500": lambda: sized(384, 500, 1903), "17x1024": lambda: sized(17, 1024, 1904)}
 
 
 def restorer(prob, **kw):
@@ -125,12 +133,18 @@ def test_fft_converges_to_the_shared_fixed_point(torch, orc):
 
 
 def test_fft_refusals(torch):
-    from paper_1805_02158_amd import RedveError
+    from paper_1805_02158_amd import E_ARG, RedveError
     sr = W.problem("sr512")
     r = restorer(sr)
     y = torch.zeros(W.lr_shape(512, 512, 3), dtype=torch.float32, device="cuda")
     with pytest.raises(RedveError):
         r.solve(y, 512, 512)
+    wide = sized(2, 4100, 1905)
+    rw = restorer(wide)
+    yw = torch.zeros((2, 4100), dtype=torch.float32, device="cuda")
+    with pytest.raises(RedveError) as ei:
+        rw.solve(yw, 2, 4100)
+    assert ei.value.code == E_ARG
     p = W.problem("tiny")
     r2 = restorer(p)
     with pytest.raises(RedveError):
