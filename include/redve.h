@@ -201,6 +201,43 @@ int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, d
 int redve_extrapolate(redve_t h, const float* xs, int L, int hx, int wx, float* out,
                       double* gamma, int* breakdown);
 
+/* ---- launch configuration (autotuning) -------------------------------------------------- */
+
+/* Launch configuration of the single-image path's kernels. Every choice computes the same
+ * quantities within the stated tolerances; they differ in speed by image size. */
+typedef struct {
+    int stage_threads; /* threads per 16x16 tile of the denoiser stage: 512 or 1024           */
+    int phi_table;     /* 1: influence functions read from the per-filter cubic tables (BF16
+                          banks, 1024 stage threads, tables fitting the LDS), 2: summed on
+                          the exact window                                                   */
+    int cg_per_launch; /* CG iterations per kernel launch: 1, or 2 (separable square 7x7 or
+                          9x9 PSF without decimation, 3 or more iterations)                  */
+    int cg_threads;    /* threads per 16x16 tile of the one-iteration CG kernel: 256 or 1024
+                          (1024: separable square 7x7 or 9x9 PSF)                            */
+    int fused_start;   /* 1: the FP call's last denoiser stage also forms the CG start (needs 2
+                          iterations per launch, 1024 stage threads, and tables or FP32
+                          banks), 2: a kernel of its own                                     */
+} redve_tuning_t;
+
+enum { REDVE_TUNE_RULES = 0, REDVE_TUNE_AUTO = 1 };
+
+/* REDVE_TUNE_RULES (default): built-in rules by image size (1024-thread stages with tables,
+ * two CG iterations per launch and the fused start below 512 tiles). REDVE_TUNE_AUTO: the
+ * first redve_solve or redve_fp_step of each problem (image size, denoiser shape and precision,
+ * PSF, decimation, CG count, base iteration, linear step) times every valid configuration on
+ * one FP call (one warm-up and three timed calls each, HIP events on the handle's stream) and
+ * keeps the fastest for later calls. cache_path (may be NULL): a file of JSON lines, one per
+ * tuned problem, read now (entries for other problems are kept) and appended to as problems
+ * are tuned. */
+int redve_set_autotune(redve_t h, int mode, const char* cache_path);
+/* Forces a configuration for every later call (fields 0: the rule for that field), validated
+ * against what the kernels support (REDVE_E_ARG otherwise); NULL returns to the mode. */
+int redve_set_tuning(redve_t h, const redve_tuning_t* t);
+/* The configuration the next solve of an hx x wx image would use with the current settings,
+ * every field resolved. *us (may be NULL) receives the FP-call time it was tuned with, or -1
+ * if it comes from a forced setting or the rules (not tuned yet). */
+int redve_get_tuning(redve_t h, int hx, int wx, redve_tuning_t* out, double* us);
+
 /* ---- without device allocation -------------------------------------------------------- */
 
 /* Size of the library's fixed device scratch array (one per GPU, held until the process

@@ -36,6 +36,7 @@ EXPORTS = (
     "redve_extrapolate", "redve_solve_batch", "redve_server_create", "redve_server_submit",
     "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
     "redve_extrapolate_noalloc", "redve_extrapolate_noalloc_max", "redve_set_guard",
+    "redve_set_autotune", "redve_set_tuning", "redve_get_tuning",
 )
 
 
@@ -51,6 +52,15 @@ class _Tnrd(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("filters", ctypes.POINTER(ctypes.c_double)),
                 ("rbf_w", ctypes.POINTER(ctypes.c_double)),
                 ("react", ctypes.POINTER(ctypes.c_double)), ("precision", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("stage_threads", ctypes.c_int), ("phi_table", ctypes.c_int),
+                ("cg_per_launch", ctypes.c_int), ("cg_threads", ctypes.c_int),
+                ("fused_start", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Item(ctypes.Structure):
@@ -118,6 +128,9 @@ def load_library(path: str = LIB_PATH):
         "redve_extrapolate_noalloc": ([vp, vp, i, i, i, vp, dp, ctypes.POINTER(i)], i),
         "redve_extrapolate_noalloc_max": ([i], sz),
         "redve_set_guard": ([vp, d], i),
+        "redve_set_autotune": ([vp, i, ctypes.c_char_p], i),
+        "redve_set_tuning": ([vp, ctypes.POINTER(Tuning)], i),
+        "redve_get_tuning": ([vp, i, i, ctypes.POINTER(Tuning), dp], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -237,6 +250,30 @@ class Restorer:
         """Stability guard on sum |gamma| (<= 0: off)."""
         self._check(self._L.redve_set_guard(self._h, float(gamma_cap)))
         return self
+
+    def set_autotune(self, auto: bool = True, cache_path=None):
+        """Launch configuration: built-in rules (auto False) or timed per problem on first use."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self._L.redve_set_autotune(self._h, int(bool(auto)), path))
+        return self
+
+    def set_tuning(self, cfg=None):
+        """Force a launch configuration (dict of Tuning fields, missing ones 0 = rule); None
+        returns to the mode."""
+        if cfg is None:
+            self._check(self._L.redve_set_tuning(self._h, None))
+        else:
+            t = Tuning(**{k: int(v) for k, v in cfg.items()})
+            self._check(self._L.redve_set_tuning(self._h, ctypes.byref(t)))
+        return self
+
+    def get_tuning(self, hx: int, wx: int):
+        """(configuration dict, tuned FP-call microseconds or -1) for an hx x wx image."""
+        t = Tuning()
+        us = ctypes.c_double()
+        self._check(self._L.redve_get_tuning(self._h, int(hx), int(wx), ctypes.byref(t),
+                                             ctypes.byref(us)))
+        return t.as_dict(), us.value
 
     def set_linear_solver(self, kind: str = "cg"):
         """Linear step of the FP call: "cg" (cg_iters iterations) or "fft" (exact, deblurring)."""

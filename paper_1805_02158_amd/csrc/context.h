@@ -41,8 +41,16 @@ struct PassGraph {
     double sd_mu = 0.0;
     unsigned long long gen = 0, op_gen = 0;
     const void* arena = nullptr;
+    redve_tuning_t tune{};  // the launch configuration it recorded
 };
 constexpr int kPassGraphs = 4;
+
+// A tuned launch configuration and the problem it was measured on.
+struct TuneEntry {
+    int key[13];  // hx, wx, precision, T, F, J, kh, kw, decim, separable, cg_iters, base, linear
+    redve_tuning_t cfg;
+    double us;    // FP-call time measured for cfg
+};
 
 struct HostMirror {
     VeInfo info;
@@ -56,6 +64,7 @@ using redve_detail::Workspace;
 using redve_detail::HostMirror;
 using redve_detail::PassGraph;
 using redve_detail::kPassGraphs;
+using redve_detail::TuneEntry;
 
 struct redve_ctx {
     int device = 0;
@@ -113,6 +122,16 @@ struct redve_ctx {
     int pass_next = 0;
     hipStream_t gstream = nullptr;
     bool graphs_off = false;
+    // launch configuration of the single-image kernels: cur is applied to the launches (zero
+    // fields: the built-in rule); forced (set by redve_set_tuning) wins over the mode; in
+    // REDVE_TUNE_AUTO the first solve or FP step of a problem times the candidates and caches
+    // the fastest in tune_cache (and in the JSON lines file tune_path, if set)
+    redve_tuning_t cur{};
+    redve_tuning_t forced{};
+    bool have_forced = false;
+    int tune_mode = REDVE_TUNE_RULES;
+    std::vector<TuneEntry> tune_cache;
+    std::string tune_path;
 };
 
 // Whether the Fourier linear step supports an hx x wx image (fft.hip).

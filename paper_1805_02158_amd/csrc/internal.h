@@ -34,6 +34,9 @@ struct LinOp {
     // B^T B for a separable square PSF of side <= 9: the separable filter of the
     // autocorrelations of col and row (2 kh - 1 taps each; see set_autocorrelations)
     float acr[kMaxAc], acc[kMaxAc];
+    // launch configuration of the CG kernels (0: the built-in rule by image size):
+    // cg_pack 1 or 2 CG iterations per launch, cg_threads 256 or 1024 per single-iteration tile
+    int cg_pack, cg_threads;
 };
 
 // acr[j] = sum_b row[b] row[b + j - (kw - 1)], acc likewise from col, j = 0 .. 2 (kw - 1), in
@@ -159,6 +162,9 @@ struct TnrdDev {
     const float* phi_tab;
     int tab_n;
     float tab_scale, tab_off;
+    // launch configuration of the single-image MFMA stage (0: the built-in rule by image size):
+    // stage_threads 512 or 1024 per tile; phi_table 1 tables (BF16, 1024 threads), 2 window
+    int stage_threads, phi_table;
 };
 
 // Influence-function table of the BF16 form: spacing h = gamma / 2, range the centres widened
@@ -248,7 +254,9 @@ struct ResidualReq {
 // K = 7 window).
 bool tnrd_fuses_residual(const TnrdDev& d);
 // Mixed-precision stage (BF16 filter banks on MFMA, FP32 influence functions and update).
-void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
+// Returns whether the launch also formed the CG start of rq (the kernels with 1024 threads and
+// tabulated phi, or the FP32 K = 7 window, take it; otherwise the caller must form it).
+bool launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st,
                             const ResidualReq* rq = nullptr);
 // LDS of one MFMA stage tile (either form) with the influence functions evaluated on the
@@ -267,10 +275,17 @@ void launch_tnrd_stage_valu_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                   float* out, int out_mode, hipStream_t st);
 // One denoiser stage in residual form: w_t = w_{t-1} - sum_i K_i^T phi_i(K_i (f + w_{t-1}))
 // - theta_t w_{t-1}, with w = u - f (w_prev null: w_0 = 0). out_mode 0 writes w_t, 1 writes
-// f + w_t (= u_t).
-void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+// f + w_t (= u_t). Returns whether the CG start of rq was formed (as launch_tnrd_stage_bf16).
+bool launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st,
                        const ResidualReq* rq = nullptr);
+// The stage configuration the built-in rule picks for an H x W image: threads per tile (512 or
+// 1024) and whether phi is tabulated.
+int tnrd_rule_threads(int H, int W);
+// The CG configuration the built-in rule picks: iterations per launch and single-iteration
+// threads per tile.
+int cg_rule_pack(const LinOp& op, int iters, int H, int W);
+int cg_rule_threads(const LinOp& op, int H, int W);
 
 // Differences, Gram row and norms of two consecutive iterates, as published partials:
 //   u = x_new - x_old (stored in U + j*n when U != nullptr),

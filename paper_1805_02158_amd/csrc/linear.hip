@@ -1461,11 +1461,26 @@ Partials launch_cg_w0(const LinOp& op, const float* r, float* w, int H, int W, d
     return Partials{part, g};
 }
 
-bool cg_block_ok(const LinOp& op, int iters, int H, int W) {
+// The two-iteration kernels exist for separable square 7x7 and 9x9 PSFs without decimation.
+static bool cg_block_eligible(const LinOp& op, int iters) {
+    return op.decim == 1 && op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9) &&
+           iters >= 3;
+}
+
+int cg_rule_pack(const LinOp& op, int iters, int H, int W) {
     // small images only: there the per-kernel latency dominates; on large ones the wider
     // halos of the two-iteration kernel cost more than the launch they save
-    return op.decim == 1 && op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9) &&
-           iters >= 3 && ntiles_host(H, W) < kWideBelowTiles;
+    return cg_block_eligible(op, iters) && ntiles_host(H, W) < kWideBelowTiles ? 2 : 1;
+}
+
+int cg_rule_threads(const LinOp& op, int H, int W) {
+    const bool rs = op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9);
+    return rs && ntiles_host(H, W) < kWideBelowTiles ? kWideThreads : kThreads;
+}
+
+bool cg_block_ok(const LinOp& op, int iters, int H, int W) {
+    if (!cg_block_eligible(op, iters)) return false;
+    return op.cg_pack ? op.cg_pack == 2 : cg_rule_pack(op, iters, H, W) == 2;
 }
 
 Partials launch_cg_w0_block(const LinOp& op, const float* r, float* w, float* a, int H, int W,
@@ -1504,8 +1519,9 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
                         hipStream_t st) {
     const int g = last ? upd_blocks(H * W) : tile_blocks(H, W);
     const int rr = op.separable && op.kh == op.kw ? op.kh / 2 : 0;
-    // fewer tiles than two per CU: wide workgroups (see k_cg_iter)
-    const bool wide = !last && ntiles_host(H, W) < kWideBelowTiles;
+    // fewer tiles than two per CU: wide workgroups (see k_cg_iter), or the tuned choice
+    const bool wide = !last && (op.cg_threads ? op.cg_threads == kWideThreads
+                                              : ntiles_host(H, W) < kWideBelowTiles);
 #define REDVE_CG_ITER(RS, NTH)                                                                 \
     k_cg_iter<RS, NTH><<<g, NTH, 0, st>>>(op, H, W, k, last, r_in, w_in, s_in, r_out, w_out, \
                                           s_out, p, d, x_in, x_out, rm, hist_prev, hist_cur, part)

@@ -123,6 +123,8 @@ LinOp linop_of(redve_t h) {
         op.row[j] = (float)h->row[j];
     }
     set_autocorrelations(op);
+    op.cg_pack = h->cur.cg_per_launch;
+    op.cg_threads = h->cur.cg_threads;
     return op;
 }
 
@@ -154,7 +156,13 @@ TnrdDev redve_tnrd_dev(redve_t h) {
 
 namespace {
 
-TnrdDev tnrd_of(redve_t h) { return redve_tnrd_dev(h); }
+// The handle's denoiser with the single-image launch configuration.
+TnrdDev tnrd_of(redve_t h) {
+    TnrdDev d = redve_tnrd_dev(h);
+    d.stage_threads = h->cur.stage_threads;
+    d.phi_table = h->cur.phi_table;
+    return d;
+}
 
 int check_ready(redve_t h, bool need_den) {
     if (!h->have_op) return fail(h, REDVE_E_STATE, "redve_set_operator was not called");
@@ -185,13 +193,14 @@ int check_fft_size(redve_t h, int hx, int wx) {
 }
 
 // Denoiser f. residual = true writes f(x) - x (nothing, and *out_null = true, for T = 0);
-// otherwise f(x).
+// otherwise f(x). With rq, *rq_done tells whether the last stage also formed the CG start.
 int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool residual,
-                 bool* out_null, const ResidualReq* rq = nullptr) {
+                 bool* out_null, const ResidualReq* rq = nullptr, bool* rq_done = nullptr) {
     Workspace& w = h->ws;
     const int n = H * W;
     TnrdDev d = tnrd_of(h);
     if (out_null) *out_null = false;
+    if (rq_done) *rq_done = false;
     if (h->T == 0) {
         if (residual) {
             if (out_null) *out_null = true;
@@ -206,10 +215,10 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
         float* dst = last ? out : ((t & 1) ? w.u1 : w.u0);
         const int mode = (last && !residual) ? 1 : 0;
         const ResidualReq* q = last ? rq : nullptr;
-        if (h->precision == REDVE_PREC_BF16)
-            launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream, q);
-        else
-            launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream, q);
+        const bool done = h->precision == REDVE_PREC_BF16
+                              ? launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream, q)
+                              : launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream, q);
+        if (q && rq_done) *rq_done = done;
         LAUNCH_CHECK(h);
         wprev = dst;
     }
@@ -291,13 +300,15 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
     Workspace& w = h->ws;
     const int n = H * W;
     bool s_null = false;
-    // on the two-iteration CG path the last denoiser stage also forms the CG start r_0
+    // on the two-iteration CG path the last denoiser stage can also form the CG start r_0;
+    // the stage reports whether it did, and the start kernel runs otherwise
     const LinOp op = linop_of(h);
     const bool fuse = h->base == REDVE_BASE_FP && h->lin == REDVE_LIN_CG && h->cg_iters > 0 &&
-                      h->T > 0 && cg_block_ok(op, h->cg_iters, H, W) &&
-                      tnrd_fuses_residual(tnrd_of(h));
+                      h->T > 0 && h->cur.fused_start != 2 &&
+                      cg_block_ok(op, h->cg_iters, H, W) && tnrd_fuses_residual(tnrd_of(h));
     const ResidualReq rq{op, y, w.r[0], op.kh / 2};
-    int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null, fuse ? &rq : nullptr);
+    bool started = false;
+    int rc = run_denoiser(h, x_in, H, W, w.sres, true, &s_null, fuse ? &rq : nullptr, &started);
     if (rc) return rc;
     if (h->base == REDVE_BASE_SD) {  // x - mu g(x): the same residual, no linear solve
         launch_sd_step(linop_of(h), x_in, y, s_null ? nullptr : w.sres, x_out, H, W, h->stream);
@@ -315,7 +326,7 @@ int fp_call(redve_t h, const float* y, const float* x_in, float* x_out, int H, i
         HIP_TRY(h, hipMemcpyAsync(x_out, x_in, sizeof(float) * n, hipMemcpyDeviceToDevice, h->stream));
         return REDVE_OK;
     }
-    if (!fuse) {
+    if (!started) {
         launch_cg_init_fp(op, x_in, y, s_null ? nullptr : w.sres, w.r[0], H, W, h->stream);
         LAUNCH_CHECK(h);
     }
@@ -437,6 +448,7 @@ int capture_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, PassGr
     g.gen = h->gen;
     g.op_gen = h->op_gen;
     g.arena = h->ws.arena;
+    g.tune = h->cur;
     return REDVE_OK;
 }
 
@@ -448,7 +460,7 @@ int run_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float** ne
         for (auto& e : h->pass)
             if (e.exec && e.from == x_cur && e.hx == hx && e.wx == wx && e.m == h->m &&
                 e.sd_mu == h->sd_mu && e.gen == h->gen && e.op_gen == h->op_gen &&
-                e.arena == h->ws.arena)
+                e.arena == h->ws.arena && !memcmp(&e.tune, &h->cur, sizeof(h->cur)))
                 g = &e;
         if (!g) {
             PassGraph& slot = h->pass[h->pass_next];
@@ -471,6 +483,177 @@ int run_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float** ne
         if (rc) return rc;
     }
     return wait_stream(h);
+}
+
+// ---- launch configuration: rules, candidates, autotuning ------------------------------------
+
+void tune_key(redve_t h, int hx, int wx, int (&k)[13]) {
+    const int v[13] = {hx, wx, h->precision, h->T, h->F, h->J, h->kh, h->kw, h->decim,
+                       h->separable, h->cg_iters, h->base, h->lin};
+    for (int i = 0; i < 13; ++i) k[i] = v[i];
+}
+
+// Whether the denoiser's last stage can form the CG start with 1024-thread tiles.
+bool stage_forms_start(redve_t h, int phi_table) {
+    if (h->T == 0) return false;
+    if (h->precision == REDVE_PREC_BF16) return h->d_phitab && phi_table == 1;
+    return tnrd_mfma_fits(h->F, h->J) && h->kwin == 7;
+}
+
+// Every field of c resolved to what the launches do for an hx x wx image (0: the rule).
+redve_tuning_t resolve_tuning(redve_t h, int hx, int wx, redve_tuning_t c) {
+    redve_tuning_t r{};
+    const LinOp op = linop_of(h);  // cur's CG fields are overridden below
+    r.stage_threads = c.stage_threads ? c.stage_threads : tnrd_rule_threads(hx, wx);
+    const bool tables = h->precision == REDVE_PREC_BF16 && h->d_phitab && r.stage_threads == 1024;
+    r.phi_table = tables && c.phi_table != 2 ? 1 : 2;
+    LinOp o2 = op;
+    o2.cg_pack = c.cg_per_launch;
+    const bool cg = h->base == REDVE_BASE_FP && h->lin == REDVE_LIN_CG && h->cg_iters > 0;
+    r.cg_per_launch = cg && cg_block_ok(o2, h->cg_iters, hx, wx) ? 2 : 1;
+    const int rule_threads = cg_rule_threads(op, hx, wx);
+    const bool wide_ok = op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9);
+    r.cg_threads = c.cg_threads ? (c.cg_threads == 1024 && wide_ok ? 1024 : 256) : rule_threads;
+    r.fused_start = cg && c.fused_start != 2 && r.cg_per_launch == 2 &&
+                            r.stage_threads == 1024 && stage_forms_start(h, r.phi_table)
+                        ? 1
+                        : 2;
+    return r;
+}
+
+const TuneEntry* find_tuned(redve_t h, const int (&k)[13]) {
+    for (const TuneEntry& e : h->tune_cache)
+        if (!memcmp(e.key, k, sizeof(k))) return &e;
+    return nullptr;
+}
+
+void put_tuned(redve_t h, const TuneEntry& t) {
+    for (TuneEntry& e : h->tune_cache)
+        if (!memcmp(e.key, t.key, sizeof(t.key))) {
+            e = t;
+            return;
+        }
+    h->tune_cache.push_back(t);
+}
+
+// One JSON line per tuned problem.
+void write_tuned(const std::string& path, const TuneEntry& t) {
+    FILE* f = fopen(path.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": [");
+    for (int i = 0; i < 13; ++i) fprintf(f, i ? ", %d" : "%d", t.key[i]);
+    fprintf(f,
+            "], \"stage_threads\": %d, \"phi_table\": %d, \"cg_per_launch\": %d, "
+            "\"cg_threads\": %d, \"fused_start\": %d, \"us\": %.3f}\n",
+            t.cfg.stage_threads, t.cfg.phi_table, t.cfg.cg_per_launch, t.cfg.cg_threads,
+            t.cfg.fused_start, t.us);
+    fclose(f);
+}
+
+void read_tuned(redve_t h, const std::string& path) {
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        TuneEntry t{};
+        int* k = t.key;
+        const int n = sscanf(line,
+                             "{\"key\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d], "
+                             "\"stage_threads\": %d, \"phi_table\": %d, \"cg_per_launch\": %d, "
+                             "\"cg_threads\": %d, \"fused_start\": %d, \"us\": %lf}",
+                             &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9],
+                             &k[10], &k[11], &k[12], &t.cfg.stage_threads, &t.cfg.phi_table,
+                             &t.cfg.cg_per_launch, &t.cfg.cg_threads, &t.cfg.fused_start, &t.us);
+        if (n == 19) put_tuned(h, t);
+    }
+    fclose(f);
+}
+
+// The distinct valid configurations for an hx x wx image.
+std::vector<redve_tuning_t> tuning_candidates(redve_t h, int hx, int wx) {
+    std::vector<redve_tuning_t> out;
+    for (int st : {512, 1024})
+        for (int tab : {1, 2})
+            for (int pk : {1, 2})
+                for (int ct : {256, 1024})
+                    for (int fs : {1, 2}) {
+                        const redve_tuning_t r = resolve_tuning(h, hx, wx, {st, tab, pk, ct, fs});
+                        if (r.stage_threads != st || r.phi_table != tab || r.cg_per_launch != pk ||
+                            r.fused_start != fs)
+                            continue;  // not valid as asked
+                        // the one-iteration kernel's threads only matter without pairs
+                        if (pk == 2 && ct != r.cg_threads) continue;
+                        if (r.cg_threads != ct && pk == 1) continue;
+                        bool dup = false;
+                        for (const auto& o : out) dup = dup || !memcmp(&o, &r, sizeof(r));
+                        if (!dup) out.push_back(r);
+                    }
+    return out;
+}
+
+// Times every candidate on FP calls from x_in (into x_out, a scratch buffer) and keeps the
+// fastest: one warm-up call, then three timed calls between HIP events on the handle's stream.
+int autotune(redve_t h, const float* y, const float* x_in, float* x_out, int hx, int wx,
+             TuneEntry& best) {
+    const auto cands = tuning_candidates(h, hx, wx);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    int rc = REDVE_OK;
+    best.us = -1.0;
+    for (const redve_tuning_t& c : cands) {
+        h->cur = c;
+        if ((rc = fp_call(h, y, x_in, x_out, hx, wx, nullptr))) break;
+        if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = REDVE_E_HIP; break; }
+        for (int i = 0; i < 3 && !rc; ++i) rc = fp_call(h, y, x_in, x_out, hx, wx, nullptr);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = REDVE_E_HIP;
+            break;
+        }
+        const double us = ms * 1e3 / 3.0;
+        if (best.us < 0 || us < best.us) {
+            best.cfg = c;
+            best.us = us;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return fail(h, rc, "autotuning failed: " + h->err);
+    tune_key(h, hx, wx, best.key);
+    return REDVE_OK;
+}
+
+// Sets h->cur for an hx x wx problem: the forced configuration, else (AUTO) the cached or
+// newly tuned one (tuning needs y, x_in and a scratch x_out; without them the rules), else the
+// rules.
+int select_tuning(redve_t h, int hx, int wx, const float* y = nullptr, const float* x_in = nullptr,
+                  float* x_out = nullptr) {
+    if (h->have_forced) {
+        h->cur = h->forced;
+        return REDVE_OK;
+    }
+    h->cur = redve_tuning_t{};
+    if (h->tune_mode != REDVE_TUNE_AUTO) return REDVE_OK;
+    int k[13];
+    tune_key(h, hx, wx, k);
+    if (const TuneEntry* e = find_tuned(h, k)) {
+        h->cur = e->cfg;
+        return REDVE_OK;
+    }
+    if (!y || !x_in || !x_out) return REDVE_OK;
+    TuneEntry best{};
+    const int rc = autotune(h, y, x_in, x_out, hx, wx, best);
+    if (rc) {
+        h->cur = redve_tuning_t{};
+        return rc;
+    }
+    put_tuned(h, best);
+    if (!h->tune_path.empty()) write_tuned(h->tune_path, best);
+    h->cur = best.cfg;
+    return REDVE_OK;
 }
 
 struct Progress {
@@ -804,6 +987,60 @@ int redve_set_guard(redve_t h, double gamma_cap) {
     return REDVE_OK;
 }
 
+int redve_set_autotune(redve_t h, int mode, const char* cache_path) {
+    if (!h) return REDVE_E_ARG;
+    if (mode != REDVE_TUNE_RULES && mode != REDVE_TUNE_AUTO)
+        return fail(h, REDVE_E_ARG, "mode must be REDVE_TUNE_RULES or REDVE_TUNE_AUTO");
+    h->tune_mode = mode;
+    h->tune_path = cache_path ? cache_path : "";
+    if (cache_path) read_tuned(h, h->tune_path);
+    return REDVE_OK;
+}
+
+int redve_set_tuning(redve_t h, const redve_tuning_t* t) {
+    if (!h) return REDVE_E_ARG;
+    if (!t) {
+        h->have_forced = false;
+        return REDVE_OK;
+    }
+    const bool ok = (t->stage_threads == 0 || t->stage_threads == 512 || t->stage_threads == 1024) &&
+                    t->phi_table >= 0 && t->phi_table <= 2 && t->cg_per_launch >= 0 &&
+                    t->cg_per_launch <= 2 &&
+                    (t->cg_threads == 0 || t->cg_threads == 256 || t->cg_threads == 1024) &&
+                    t->fused_start >= 0 && t->fused_start <= 2;
+    if (!ok) return fail(h, REDVE_E_ARG, "tuning field out of range");
+    if (t->phi_table == 1 && t->stage_threads == 512)
+        return fail(h, REDVE_E_ARG, "tabulated influence functions need 1024 stage threads");
+    if (t->fused_start == 1 && (t->cg_per_launch == 1 || t->stage_threads == 512))
+        return fail(h, REDVE_E_ARG,
+                    "the fused CG start needs two CG iterations per launch and 1024 stage threads");
+    h->forced = *t;
+    h->have_forced = true;
+    return REDVE_OK;
+}
+
+int redve_get_tuning(redve_t h, int hx, int wx, redve_tuning_t* out, double* us) {
+    if (!h) return REDVE_E_ARG;
+    if (!out) return fail(h, REDVE_E_ARG, "null pointer");
+    int rc = check_image(h, hx, wx);
+    if (rc) return rc;
+    redve_tuning_t c{};
+    double u = -1.0;
+    if (h->have_forced) {
+        c = h->forced;
+    } else if (h->tune_mode == REDVE_TUNE_AUTO) {
+        int k[13];
+        tune_key(h, hx, wx, k);
+        if (const TuneEntry* e = find_tuned(h, k)) {
+            c = e->cfg;
+            u = e->us;
+        }
+    }
+    *out = resolve_tuning(h, hx, wx, c);
+    if (us) *us = u;
+    return REDVE_OK;
+}
+
 int redve_set_linear_solver(redve_t h, int kind) {
     if (!h) return REDVE_E_ARG;
     if (kind != REDVE_LIN_CG && kind != REDVE_LIN_FFT) return fail(h, REDVE_E_ARG, "bad solver");
@@ -876,7 +1113,7 @@ int redve_cg(redve_t h, const float* rhs, float* x, int hx, int wx, int iters) {
     int rc = check_image(h, hx, wx);
     if (rc || (rc = check_ready(h, false))) return rc;
     HIP_TRY(h, hipSetDevice(h->device));
-    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    if ((rc = ensure_workspace(h, hx, wx, h->L)) || (rc = select_tuning(h, hx, wx))) return rc;
     const size_t n = (size_t)hx * wx;
     HIP_TRY(h, hipMemcpyAsync(h->ws.xa, x, n * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
     return run_cg(h, rhs, h->ws.xa, x, hx, wx, iters);
@@ -888,7 +1125,7 @@ int redve_objective(redve_t h, const float* y, const float* x, int hx, int wx, d
     int rc = check_image(h, hx, wx);
     if (rc || (rc = check_ready(h, true))) return rc;
     HIP_TRY(h, hipSetDevice(h->device));
-    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    if ((rc = ensure_workspace(h, hx, wx, h->L)) || (rc = select_tuning(h, hx, wx))) return rc;
     Workspace& w = h->ws;
     bool s_null = false;
     if ((rc = run_denoiser(h, x, hx, wx, w.sres, true, &s_null))) return rc;
@@ -910,7 +1147,7 @@ int redve_denoise(redve_t h, const float* x, int hx, int wx, float* out) {
     if (rc) return rc;
     if (!h->have_den) return fail(h, REDVE_E_STATE, "redve_set_denoiser was not called");
     HIP_TRY(h, hipSetDevice(h->device));
-    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    if ((rc = ensure_workspace(h, hx, wx, h->L)) || (rc = select_tuning(h, hx, wx))) return rc;
     return run_denoiser(h, x, hx, wx, out, false, nullptr);
 }
 
@@ -922,7 +1159,9 @@ int redve_fp_step(redve_t h, const float* y, const float* x, int hx, int wx, flo
         (rc = check_fft_size(h, hx, wx)))
         return rc;
     HIP_TRY(h, hipSetDevice(h->device));
-    if ((rc = ensure_workspace(h, hx, wx, h->L))) return rc;
+    if ((rc = ensure_workspace(h, hx, wx, h->L)) ||
+        (rc = select_tuning(h, hx, wx, y, x, h->ws.xb)))
+        return rc;
     return fp_call(h, y, x, out, hx, wx);
 }
 
@@ -989,6 +1228,8 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     HIP_TRY(h, hipMemcpyAsync(w.yw, y, sizeof(float) * (size_t)hy * wy, hipMemcpyDeviceToDevice,
                               h->stream));
     const float* yw = w.yw;
+    // the launch configuration (AUTO: tuned on FP calls from x0 on first use of this problem)
+    if ((rc = select_tuning(h, hx, wx, yw, w.xa, w.xb))) return rc;
 
     int calls = 0, cycles = 0, breakdowns = 0, rejected = 0, status = REDVE_OK;
     double delta = INFINITY, gl1max = 0.0;

@@ -569,19 +569,25 @@ StageArgs stage_args(const TnrdDev& d, int t, const float* w_prev, const float* 
     return a;
 }
 
+// Returns whether the launch formed the CG start of rq.
 template <bool F32>
-void launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+bool launch_single(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                    int H, int W, int out_mode, hipStream_t st, const ResidualReq* rq) {
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH);
-    // fewer tiles than two per CU: 1024 threads per tile, and the tables where there are
-    const bool wide = grid.x * grid.y < kWideStageBelow;
-    StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode, wide);
-    a.rq = wide ? rq : nullptr;  // the residual kernels have 1024 threads
+    // rule: fewer tiles than two per CU take 1024 threads per tile, and the tables where there
+    // are; a tuned configuration may choose otherwise (tables need 1024 threads)
+    const bool wide = d.stage_threads ? d.stage_threads == 1024 : grid.x * grid.y < kWideStageBelow;
+    const bool table = wide && d.phi_table != 2;
+    StageArgs a = stage_args<F32>(d, t, w_prev, f, out, H, W, out_mode, table);
+    // the residual kernels have 1024 threads and exist for the tables (BF16) or the K = 7
+    // window (FP32)
+    a.rq = wide && (F32 ? a.rc.K == 7 : a.table) ? rq : nullptr;
     const size_t smem = a.table ? tnrd_table_smem_bytes(d.nfilt, d.tab_n)
                                 : tnrd_mfma_smem_bytes(d.nfilt, d.nrbf);
     dispatch<F32>(a, [&](auto kc, auto zs) {
         stage_single<decltype(kc)::value, decltype(zs)::value, F32>(wide, grid, smem, st, a);
     });
+    return a.rq != nullptr;
 }
 
 template <bool F32>
@@ -615,10 +621,14 @@ int tnrd_table_intervals(double dmu, double gamma, int J) {
     return (int)ceil(span / (kTabStep * gamma));
 }
 
-void launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
+bool launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const float* f,
                             float* out, int H, int W, int out_mode, hipStream_t st,
                             const ResidualReq* rq) {
-    launch_single<false>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
+    return launch_single<false>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
+}
+
+int tnrd_rule_threads(int H, int W) {
+    return ((W + TW - 1) / TW) * ((H + TH - 1) / TH) < kWideStageBelow ? 1024 : 512;
 }
 
 bool tnrd_fuses_residual(const TnrdDev& d) {
@@ -632,12 +642,12 @@ void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
     launch_batch<false>(d, t, desc, tiles, ntiles, w_prev, out, out_mode, st);
 }
 
-void launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
+bool launch_tnrd_stage(const TnrdDev& d, int t, const float* w_prev, const float* f, float* out,
                        int H, int W, int out_mode, hipStream_t st, const ResidualReq* rq) {
     if (tnrd_mfma_fits(d.nfilt, d.nrbf))
-        launch_single<true>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
-    else
-        launch_tnrd_stage_valu(d, t, w_prev, f, out, H, W, out_mode, st);
+        return launch_single<true>(d, t, w_prev, f, out, H, W, out_mode, st, rq);
+    launch_tnrd_stage_valu(d, t, w_prev, f, out, H, W, out_mode, st);
+    return false;
 }
 
 void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const TileRef* tiles,
