@@ -312,6 +312,11 @@ int redve_server_poll(redve_server_t s, unsigned long long ticket, int* done, re
 int redve_server_wait(redve_server_t s, unsigned long long ticket, redve_stats_t* st);
 /* Requests queued, running, finished so far, and rounds executed. */
 int redve_server_counts(redve_server_t s, int* queued, int* active, int* finished, long long* rounds);
+/* Admission record: the pixel capacity the budget buys (hbm_budget / (4 (14 + L)) bytes),
+ * the most pixels admitted at once so far (each request's range rounded up to 64), which
+ * never exceeds it, and the rounds run while a request waited in the queue. */
+int redve_server_occupancy(redve_server_t s, size_t* capacity_px, size_t* peak_px,
+                           long long* waited_rounds);
 /* Waits for every submitted request, stops the scheduler, frees everything. */
 int redve_server_destroy(redve_server_t s);
 

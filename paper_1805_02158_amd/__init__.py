@@ -36,7 +36,7 @@ EXPORTS = (
     "redve_extrapolate", "redve_solve_batch", "redve_server_create", "redve_server_submit",
     "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
     "redve_extrapolate_noalloc", "redve_extrapolate_noalloc_max", "redve_set_guard",
-    "redve_set_autotune", "redve_set_tuning", "redve_get_tuning",
+    "redve_set_autotune", "redve_set_tuning", "redve_get_tuning", "redve_server_occupancy",
 )
 
 
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH):
         "redve_extrapolate_noalloc_max": ([i], sz),
         "redve_set_guard": ([vp, d], i),
         "redve_set_autotune": ([vp, i, ctypes.c_char_p], i),
+        "redve_server_occupancy": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                    ctypes.POINTER(ctypes.c_longlong)], i),
         "redve_set_tuning": ([vp, ctypes.POINTER(Tuning)], i),
         "redve_get_tuning": ([vp, i, i, ctypes.POINTER(Tuning), dp], i),
     }
@@ -450,6 +452,13 @@ class Server:
         self._L.redve_server_counts(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(f),
                                     ctypes.byref(r))
         return {"queued": q.value, "active": a.value, "finished": f.value, "rounds": r.value}
+
+    def occupancy(self):
+        """Pixel capacity of the budget, most pixels admitted at once, rounds with a request
+        waiting."""
+        c, p, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_longlong()
+        self._L.redve_server_occupancy(self._h, ctypes.byref(c), ctypes.byref(p), ctypes.byref(w))
+        return {"capacity_px": c.value, "peak_px": p.value, "waited_rounds": w.value}
 
     def close(self):
         if getattr(self, "_h", None) is not None:

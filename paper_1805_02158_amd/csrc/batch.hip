@@ -732,6 +732,8 @@ struct redve_server {
     int active = 0;  // running requests (the worker's count, published under mu)
     long long rounds = 0;
     int error = REDVE_OK;
+    size_t peak_px = 0;       // most pixels admitted at once (allocated ranges, 64-aligned)
+    long long waited = 0;     // rounds run while a request waited in the queue
 
     // The worker: admits queued requests in arrival order while the head fits (slots, device
     // memory, tiles), runs one round, publishes finished requests. Engine state is touched by
@@ -753,6 +755,11 @@ struct redve_server {
                     queue.pop_front();
                     ++active;
                 }
+                size_t px = 0;
+                for (const auto& sl : eng.slots)
+                    if (sl.used) px += (sl.npx + 63) / 64 * 64;
+                peak_px = std::max(peak_px, px);
+                if (!queue.empty() && active > 0) ++waited;
             }
             if (active == 0) continue;  // cannot happen: an empty engine admits any queued head
             const int rc = eng.round();
@@ -918,6 +925,16 @@ extern "C" int redve_server_counts(redve_server_t s, int* queued, int* active, i
     if (active) *active = s->active;
     if (finished) *finished = (int)s->results.size();
     if (rounds) *rounds = s->rounds;
+    return REDVE_OK;
+}
+
+extern "C" int redve_server_occupancy(redve_server_t s, size_t* capacity_px, size_t* peak_px,
+                                      long long* waited_rounds) {
+    if (!s) return REDVE_E_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (capacity_px) *capacity_px = s->eng.cap_px;
+    if (peak_px) *peak_px = s->peak_px;
+    if (waited_rounds) *waited_rounds = s->waited;
     return REDVE_OK;
 }
 

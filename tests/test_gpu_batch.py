@@ -260,6 +260,7 @@ def _serve(torch, r, reqs, budget, max_active, stagger=0.0):
             time.sleep(stagger)
     stats = [srv.wait(t) for t, _ in tickets]
     counts = srv.counts()
+    counts.update(srv.occupancy())
     srv.close()
     return [o for _, o in tickets], stats, counts
 
@@ -288,14 +289,20 @@ def test_server_same_alone_and_in_mix(torch, orc):
 
 def test_server_admission_respects_budget(torch, orc):
     """A budget that holds about two of the images: requests queue and are admitted in order
-    as memory frees up; all finish."""
+    as memory frees up (rounds run with a request waiting), the pixels admitted at once never
+    exceed what the budget buys, and all finish with the oracle's result."""
     say("server budget")
     probs = mixed_problems(orc, 6, seed=3)
     r = restorer("rre", 5, 1e-5, 200)
     per_px = 4 * (14 + 5)
     budget = per_px * (2 * 128 * 128 + 4096)
     outs, stats, counts = _serve(torch, r, as_dicts(torch, probs), budget, 8)
+    say(f"  counts {counts}, sizes {[p.hr_shape for p, _ in probs]}")
     assert counts["finished"] == 6
+    assert counts["capacity_px"] == budget // per_px
+    assert 0 < counts["peak_px"] <= counts["capacity_px"]
+    assert counts["waited_rounds"] >= 1
+    assert counts["peak_px"] < sum(-(-p.hr_shape[0] * p.hr_shape[1] // 64) * 64 for p, _ in probs)
     for (prob, y32), xo in zip(probs, outs):
         ref = orc.solve(orc.OracleProblem(prob, y=y32), "rre", L=5, m=0, tol=1e-9, max_calls=400)
         assert rel(host(xo), ref.x) <= 1e-4

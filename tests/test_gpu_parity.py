@@ -505,8 +505,8 @@ def test_errors(torch):
 @pytest.mark.parametrize("shape", [(64, 64), (37, 53), (3, 5), (256, 256)])
 def test_denoiser_bf16(torch, orc, shape):
     """BF16 filter banks (per-window centred operands, FP32 accumulation): the denoiser update
-    f(x) - x matches the oracle's to 2e-2 relative L2 (BF16 keeps 8 significant bits, 3.9e-3 of
-    each operand)."""
+    f(x) - x matches the oracle's to the BF16 bar, 5e-3 relative L2 (BF16 keeps 8 significant
+    bits, 3.9e-3 of each operand; the centred operands keep the update's error near 5e-4)."""
     say("denoiser bf16", shape)
     d = W.make_denoiser()
     r = restorer()
@@ -516,7 +516,7 @@ def test_denoiser_bf16(torch, orc, shape):
     o = orc.denoise(x, orc.Denoiser(d))
     err = rel(g - x, o - x)
     say(f"  update rel L2 {err:.2e}")
-    assert err <= 2e-2
+    assert err <= 5e-3
     c = np.full((24, 40), 88.0)
     assert np.abs(host(r.denoise(dev(torch, c))) - 88.0).max() <= 1e-3
 
@@ -552,10 +552,10 @@ def test_denoiser_bf16_forms(torch, orc, form):
         assert err <= 5e-3
 
 
-def _converged_bf16(torch, orc, prob, method, L, tol=1e-5, calls=400):
+def _converged_bf16(torch, orc, prob, method, L, tol=1e-5, calls=400, precision="bf16"):
     y32 = f32(orc.OracleProblem(prob).y)
     op = orc.OracleProblem(prob, y=y32)
-    r = restorer(prob, precision="bf16", method=method, L=L, tol=tol, max_fp_calls=calls)
+    r = restorer(prob, precision=precision, method=method, L=L, tol=tol, max_fp_calls=calls)
     x, st = r.solve(dev(torch, y32), *prob.hr_shape)
     xg = host(x)
     ref = orc.solve(op, method, L=L, m=0, tol=1e-8, max_calls=calls)
@@ -589,3 +589,74 @@ def test_solve_bf16_sr_512(torch, orc):
     say("solve bf16 sr 512")
     err, dp = _converged_bf16(torch, orc, W.problem("sr512"), "rre", 8, calls=300)
     assert err <= 5e-3 and abs(dp) <= 0.05
+
+
+def test_solve_fp32_sr_512(torch, orc):
+    """The same workload with FP32 banks, converged, against the oracle's fixed point: the FP32
+    bar, 1e-4."""
+    say("solve fp32 sr 512")
+    err, dp = _converged_bf16(torch, orc, W.problem("sr512"), "rre", 8, calls=300,
+                              precision="fp32")
+    assert err <= 1e-4 and abs(dp) <= 0.05
+
+
+@pytest.mark.parametrize("name,L,calls", [("deblur256", 5, 5), ("deblur256", 5, 10),
+                                          ("sr512", 8, 16)])
+def test_solve_bf16_fixed_schedule(torch, orc, name, L, calls):
+    """BF16 banks at the same schedule as the FP64 oracle (the benchmark's 5 FP calls of RRE
+    at 256x256, two cycles, and two cycles of the 3x SR workload): the BF16 bar, 5e-3 relative
+    L2 and 0.05 dB."""
+    say("solve bf16 fixed schedule", name, L, calls)
+    prob = W.problem(name)
+    y32 = f32(orc.OracleProblem(prob).y)
+    ref = orc.solve(orc.OracleProblem(prob, y=y32), "rre", L=L, m=0, tol=0.0, max_calls=calls)
+    r = restorer(prob, precision="bf16", method="rre", L=L, m=0, tol=0.0, max_fp_calls=calls)
+    x, st = r.solve(dev(torch, y32), *prob.hr_shape)
+    assert st["fp_calls"] == ref.calls and st["cycles"] == ref.cycles
+    xg = host(x)
+    err = rel(xg, ref.x)
+    dp = orc.psnr(xg, prob.x_true) - orc.psnr(ref.x, prob.x_true)
+    say(f"  rel L2 vs oracle {err:.2e}, dPSNR {dp:+.4f} dB")
+    assert err <= 5e-3 and abs(dp) <= 0.05
+
+
+@pytest.mark.parametrize("name,method,L,cycles", [("deblur64", "rre", 5, 3), ("deblur64", "mpe", 5, 3),
+                                                  ("deblur64", "svd_mpe", 5, 2), ("tiny", "rre", 3, 4)])
+def test_solve_stepwise_on_the_gpu_trajectory(torch, orc, name, method, L, cycles):
+    """Each step of a fixed-schedule VE solve checked where it happens: every FP call against
+    the oracle's FP map started from the GPU's own FP32 iterate (the FP32 bars: 2e-5 relative,
+    and 1e-4 of the step, where the step is larger than the output's own FP32 rounding: the
+    error may be 1e-4 ||step|| + 2^-22 ||x||), and every extrapolation against the oracle's
+    (Algorithm 1 / eq. (19) / SVD-MPE) on the GPU's own FP32 window (2e-6; the breakdown flag
+    equal). The solve's result is that trajectory's (the same kernels as the single steps)."""
+    say("stepwise", name, method, L, cycles)
+    prob = W.problem(name)
+    y32 = f32(orc.OracleProblem(prob).y)
+    op = orc.OracleProblem(prob, y=y32)
+    r = restorer(prob, method=method, L=L, m=0, tol=0.0, max_fp_calls=cycles * L)
+    y = dev(torch, y32)
+    x = dev(torch, op.x0())
+    worst_fp = worst_step = worst_ve = 0.0
+    for c in range(cycles):
+        win = [x]
+        for _ in range(L):
+            xin = win[-1]
+            xg = r.fp_step(y, xin)
+            xi, xo = host(xin), op.fp(host(xin))
+            worst_fp = max(worst_fp, rel(host(xg), xo))
+            bar = 1e-4 * np.linalg.norm(xo - xi) + 2.0 ** -22 * np.linalg.norm(xo)
+            worst_step = max(worst_step, float(np.linalg.norm(host(xg) - xo)) / bar)
+            win.append(xg)
+        stack = torch.stack(win)
+        xe, g, bd = r.extrapolate(stack)
+        xo, go, bo = orc.ve_step([host(v).ravel() for v in win], method)
+        assert bd == bo
+        worst_ve = max(worst_ve, rel(host(xe).ravel(), xo))
+        x = xe
+    say(f"  worst FP call {worst_fp:.2e} (of its step bar {worst_step:.2f}), worst extrapolation "
+        f"{worst_ve:.2e}")
+    assert worst_fp <= 2e-5 and worst_step <= 1.0 and worst_ve <= 2e-6
+    xs, st = r.solve(y, *prob.hr_shape)
+    e = rel(host(xs), host(x))
+    say(f"  solve vs the stepwise trajectory {e:.2e}")
+    assert st["fp_calls"] == cycles * L and e <= 1e-6
