@@ -138,6 +138,13 @@ int redve_set_solver(redve_t h, int cg_iters, int max_fp_calls, double tol, int 
  * (computed per image in batches). Everything else (extrapolation, stopping, statistics) is
  * the same; "FP call" then counts SD steps. */
 int redve_set_base(redve_t h, int base, double mu);
+/* BF16 form only: once the relative change of two FP iterates falls below delta (> 0), the
+ * remaining FP calls of that solve (of that image, in batches and servers) take the FP32 banks
+ * and the FP32 window of the influence functions, so that the last cycles run above the BF16
+ * operands' noise and stop at tolerances below it in fewer calls. 0 (default): BF16 banks
+ * throughout. The batched engine switches only for denoisers whose FP32 MFMA stage fits 64 KiB
+ * of LDS. Negative or non-finite: REDVE_E_ARG. */
+int redve_set_precision_switch(redve_t h, double delta);
 /* Stability guard (Sec. III-D, eq. (21)): VE is stable when sum_i |gamma_i| stays bounded
  * over the cycles, and the extrapolated vector sum_i gamma_i x_{m+i} carries the iterates'
  * errors magnified by up to that sum. An extrapolation whose sum |gamma| exceeds gamma_cap, or
@@ -217,6 +224,9 @@ typedef struct {
     int fused_start;   /* 1: the FP call's last denoiser stage also forms the CG start (needs 2
                           iterations per launch, 1024 stage threads, and tables or FP32
                           banks), 2: a kernel of its own                                     */
+    int cg_tile;       /* one-iteration CG kernel: 16 (16x16 tiles, r, A r, A p, p, d kept in
+                          HBM) or 32 (32x32 tiles, only r, p, d kept: A r and A p recomputed;
+                          separable square 7x7 or 9x9 PSF without decimation)               */
 } redve_tuning_t;
 
 enum { REDVE_TUNE_RULES = 0, REDVE_TUNE_AUTO = 1 };

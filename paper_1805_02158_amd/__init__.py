@@ -37,6 +37,7 @@ EXPORTS = (
     "redve_server_poll", "redve_server_wait", "redve_server_counts", "redve_server_destroy",
     "redve_extrapolate_noalloc", "redve_extrapolate_noalloc_max", "redve_set_guard",
     "redve_set_autotune", "redve_set_tuning", "redve_get_tuning", "redve_server_occupancy",
+    "redve_set_precision_switch",
 )
 
 
@@ -57,7 +58,7 @@ class _Tnrd(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("stage_threads", ctypes.c_int), ("phi_table", ctypes.c_int),
                 ("cg_per_launch", ctypes.c_int), ("cg_threads", ctypes.c_int),
-                ("fused_start", ctypes.c_int)]
+                ("fused_start", ctypes.c_int), ("cg_tile", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -128,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "redve_extrapolate_noalloc": ([vp, vp, i, i, i, vp, dp, ctypes.POINTER(i)], i),
         "redve_extrapolate_noalloc_max": ([i], sz),
         "redve_set_guard": ([vp, d], i),
+        "redve_set_precision_switch": ([vp, d], i),
         "redve_set_autotune": ([vp, i, ctypes.c_char_p], i),
         "redve_server_occupancy": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz),
                                     ctypes.POINTER(ctypes.c_longlong)], i),
@@ -246,6 +248,11 @@ class Restorer:
     def set_base(self, base: str = "fp", mu: float = 0.0):
         """Base iteration: "fp" (eq. (7)) or "sd" (steepest descent, step mu; <= 0: default)."""
         self._check(self._L.redve_set_base(self._h, BASES[base], float(mu)))
+        return self
+
+    def set_precision_switch(self, delta: float):
+        """BF16 form: FP32 banks once the relative change falls below delta (0: never)."""
+        self._check(self._L.redve_set_precision_switch(self._h, float(delta)))
         return self
 
     def set_guard(self, gamma_cap: float):

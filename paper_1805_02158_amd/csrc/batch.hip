@@ -82,6 +82,7 @@ struct Slot {
     bool extra = false;
     int calls = 0, cycles = 0, breakdowns = 0, rejected = 0, status = REDVE_OK;
     double delta = INFINITY, gl1max = 0.0;
+    bool finish_fp32 = false;  // BF16 form: this image has switched to FP32 banks
     Progress prog;
     // round bookkeeping
     int next = 0;
@@ -394,6 +395,12 @@ struct Engine {
                    : REDVE_E_HIP;
     }
 
+    // The BF16 form with the switch to FP32 banks (one kernel takes each image's form).
+    bool mixed() const {
+        return h->precision == REDVE_PREC_BF16 && h->prec_switch > 0 && h->T > 0 &&
+               tnrd_mfma_fits(h->F, h->J);
+    }
+
     // The launches of one round (captured): denoiser stages, CG, differences + Gram, over the
     // first nt entries of the tile list.
     int record_fp(int rs, int nt) {
@@ -403,10 +410,18 @@ struct Engine {
             const float* wprev = nullptr;
             for (int t = 0; t < h->T; ++t) {
                 float* dst = (t == h->T - 1) ? sres() : ((t & 1) ? u1() : u0());
-                if (h->precision == REDVE_PREC_BF16)
+                if (mixed()) {
+                    TnrdDev df = d;
+                    df.precision = REDVE_PREC_FP32;
+                    df.kwin = h->kwin32;
+                    df.phi_tab = nullptr;
+                    df.tab_n = 0;
+                    launch_tnrd_stage_mixed_batch(d, df, t, d_desc, d_tile, nt, wprev, dst, 0, st);
+                } else if (h->precision == REDVE_PREC_BF16) {
                     launch_tnrd_stage_bf16_batch(d, t, d_desc, d_tile, nt, wprev, dst, 0, st);
-                else
+                } else {
                     launch_tnrd_stage_batch(d, t, d_desc, d_tile, nt, wprev, dst, 0, st);
+                }
                 wprev = dst;
             }
             s_in = sres();
@@ -523,6 +538,7 @@ struct Engine {
             d.x_out = x(sl.next) + sl.off;
             d.x_m = x(sl.base) + sl.off;
             d.op = sl.op;
+            d.fp32_banks = sl.finish_fp32 ? 1 : 0;
         }
         const int rs = all_padded ? 4 : 0;
         int rc;
@@ -554,6 +570,10 @@ struct Engine {
             const ImgStat& s = h_stat[i];
             sl.calls++;
             sl.delta = sqrt(s.uu / s.xx);
+            // BF16 form: FP32 banks once the relative change falls below the switch (tested
+            // at every call without extrapolation, at cycle ends with it, as in the solve)
+            const bool test_now = !ve || sl.do_ve;
+            if (test_now && mixed() && sl.delta < h->prec_switch) sl.finish_fp32 = true;
             sl.cur = sl.next;
             bool stop = false;
             if (sl.extra) {
@@ -838,6 +858,8 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     c.tol = proto->tol;
     c.rank_eps = proto->rank_eps;
     c.gamma_cap = proto->gamma_cap;
+    c.prec_switch = proto->prec_switch;
+    c.kwin32 = proto->kwin32;
     c.base = proto->base;
     c.sd_mu = proto->sd_mu;
     if (hipSetDevice(c.device) != hipSuccess) return REDVE_E_HIP;

@@ -42,6 +42,7 @@ struct PassGraph {
     unsigned long long gen = 0, op_gen = 0;
     const void* arena = nullptr;
     redve_tuning_t tune{};  // the launch configuration it recorded
+    bool finish_fp32 = false;  // the filter banks it recorded (BF16 form: FP32 finishing)
 };
 constexpr int kPassGraphs = 4;
 
@@ -85,6 +86,9 @@ struct redve_ctx {
     // denoiser
     bool have_den = false;
     int T = 0, F = 0, J = 0, precision = REDVE_PREC_FP32, kwin = 7;
+    int kwin32 = 7;            // the window of the FP32 banks (the BF16 form's finishing calls)
+    double prec_switch = 0.0;  // BF16 form: FP32 banks once the relative change is below this
+    bool finish_fp32 = false;  // the current solve has switched (single image)
     double mu0 = 0, dmu = 0, gamma = 1;
     std::vector<float> theta;
     float* d_filt = nullptr;

@@ -35,8 +35,9 @@ struct LinOp {
     // autocorrelations of col and row (2 kh - 1 taps each; see set_autocorrelations)
     float acr[kMaxAc], acc[kMaxAc];
     // launch configuration of the CG kernels (0: the built-in rule by image size):
-    // cg_pack 1 or 2 CG iterations per launch, cg_threads 256 or 1024 per single-iteration tile
-    int cg_pack, cg_threads;
+    // cg_pack 1 or 2 CG iterations per launch, cg_threads 256 or 1024 per single-iteration tile,
+    // cg_tile 16 (k_cg_iter: r, w, s, p, d in HBM) or 32 (k_cg_iter32: r, p, d only)
+    int cg_pack, cg_threads, cg_tile;
 };
 
 // acr[j] = sum_b row[b] row[b + j - (kw - 1)], acc likewise from col, j = 0 .. 2 (kw - 1), in
@@ -67,7 +68,7 @@ struct ImgDesc {
     int active;        // 0: every batched kernel skips the image
     int wj;            // window column the difference pass of this FP call writes (-1: none)
     int do_ve;         // 1: this round completes the image's window: extrapolate
-    int pad0;
+    int fp32_banks;    // 1: this image's denoiser stages take FP32 banks (BF16 form, finishing)
     size_t off;        // element offset of the image in every per-image workspace array
     const float* y;    // observation (caller-owned device memory)
     const float* x_in; // this FP call's input iterate
@@ -225,6 +226,15 @@ Partials launch_cg_block(const LinOp& op, int H, int W, int k, const float* cons
 // One single-reduction CG iteration k (see linear.hip); hist_prev holds (alpha, rho) of
 // iteration k-1, hist_cur receives those of iteration k. The last iteration writes
 // x_out = x_in + d only.
+// One CG iteration (not the last) on 32x32 tiles keeping only r, p and d in HBM: reads r_in and
+// p_in (p_{k-1}) on halos, writes r_out, p_out (p_k) and d in place; separable square 7x7 or
+// 9x9 PSF without decimation. cg_iter32_ok: whether the FP call takes it (the rule: images of
+// 512 or more 16x16 tiles; or the tuned cg_tile).
+bool cg_iter32_ok(const LinOp& op, int iters, int H, int W);
+Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_in,
+                          const float* p_in, float* r_out, float* p_out, float* d, Partials rm,
+                          const double* hist_prev, double* hist_cur, double* part,
+                          hipStream_t st);
 Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const float* r_in,
                         const float* w_in, const float* s_in, float* r_out, float* w_out,
                         float* s_out, float* p, float* d, const float* x_in, float* x_out,
@@ -241,6 +251,12 @@ void launch_tnrd_stage_batch(const TnrdDev& d, int t, const ImgDesc* desc, const
 void launch_tnrd_stage_bf16_batch(const TnrdDev& d, int t, const ImgDesc* desc,
                                   const TileRef* tiles, int ntiles, const float* w_prev, float* out,
                                   int out_mode, hipStream_t st);
+// The BF16 form with a per-image switch to FP32 banks (ImgDesc::fp32_banks): one launch, each
+// tile's workgroup takes its image's form (db: the BF16 denoiser, df: the same denoiser with
+// FP32 banks and its window).
+void launch_tnrd_stage_mixed_batch(const TnrdDev& db, const TnrdDev& df, int t,
+                                   const ImgDesc* desc, const TileRef* tiles, int ntiles,
+                                   const float* w_prev, float* out, int out_mode, hipStream_t st);
 // The CG start an FP call's last denoiser stage can form as it finishes (single image, the
 // two-iteration CG path): r = H^T (y - H x) / sigma^2 + lambda s with s the stage's output and
 // x its input f, into r; rs the PSF radius (3 or 4, separable, no decimation).

@@ -827,6 +827,138 @@ __global__ __launch_bounds__(NTH) void k_cg_iter(
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
 }
 
+// ---- CG iteration on 32x32 tiles keeping only r, p and d in HBM (large images) ------------
+//
+// The single-reduction iteration above stores w = A r and s = A p beside r, p, d (40 B per pixel
+// and iteration). Here they are recomputed instead: with r_k and p_{k-1} read on the tile + 2R
+// halo (R = 2 RS, the radius of A = B^T B / sigma^2 + lambda I),
+//   p_k = r_k + beta p_{k-1}                on the tile + 2R,
+//   s_k = A p_k,  r_{k+1} = r_k - alpha s_k  on the tile + R,
+//   w_{k+1} = A r_{k+1}                      on the tile,
+//   d_{k+1} = d_k + alpha p_k,  rho_{k+1} = r.r,  mu_{k+1} = w.r   at the tile's pixels,
+// storing r_{k+1}, p_k (double-buffered: neighbours read p_{k-1} on their halos) and d_{k+1}:
+// 24 B per pixel and iteration, the algorithm's own traffic, for two applications of A on
+// regions 2.25x and 1x the tile. The scalars alpha_k, beta_k come from rho_k, mu_k as in
+// k_cg_iter, so the iterates are those of the single-reduction form in exact arithmetic.
+constexpr int T32 = 32;
+constexpr int kCg32Threads = 512;
+
+template <int RS>
+struct __align__(16) Cg32Smem {
+    static constexpr int R = 2 * RS;        // radius of A
+    static constexpr int PS = T32 + 4 * R;  // side of the P region (tile + 2R halo)
+    static constexpr int SS = T32 + 2 * R;  // side of the S region (tile + R halo)
+    float r[PS * PS];    // r_k on the P region, then the second row pass
+    float p[PS * PS];    // p_k on the P region
+    float h[PS * SS];    // the first row pass, then r_{k+1} on the S region
+    float s[SS * SS];    // s_k = A p_k on the S region, then w_{k+1} on the tile
+};
+
+template <int RS>
+__global__ __launch_bounds__(kCg32Threads) void k_cg_iter32(
+    const LinOp op, int H, int W, int k, const float* __restrict__ r_in,
+    const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ p_out,
+    float* __restrict__ d, Partials rm, const double* __restrict__ hist_prev,
+    double* __restrict__ hist_cur, double* __restrict__ part) {
+    using M = Cg32Smem<RS>;
+    constexpr int NT = kCg32Threads, R = M::R, PS = M::PS, SS = M::SS;
+    constexpr int NE = (PS * PS + NT - 1) / NT;  // P-region values per thread
+    constexpr int NOUT = T32 * T32 / NT;         // tile pixels per thread
+    __shared__ M sm;
+    __shared__ double sred[2 * NT / 64];
+    __shared__ double bc[2];
+    const int ntx = (W + T32 - 1) / T32, nt = ntx * ((H + T32 - 1) / T32);
+    // the published partials and the previous step lengths first, then the first tile's
+    // inputs, so that these loads overlap the reduction
+    Early2 early;
+    const bool early_ok = rm.n <= kEarlyPartials;
+    if (early_ok) consume2_issue(rm.p, kMaxRedBlocks, rm.n, early);
+    const double alpha_prev = k ? hist_prev[0] : 0.0, rho_prev = k ? hist_prev[1] : 0.0;
+    float fr[NE], fp[NE];
+    int r0 = 0, c0 = 0;
+    auto fetch = [&](int t) {
+        const int tt = xcd_tile(t, nt);
+        r0 = (tt / ntx) * T32;
+        c0 = (tt % ntx) * T32;
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int e = threadIdx.x + i * NT;
+            fr[i] = fp[i] = 0.f;
+            if (e < PS * PS) {
+                const size_t g =
+                    (size_t)wrapi(r0 - 2 * R + e / PS, H) * W + wrapi(c0 - 2 * R + e % PS, W);
+                fr[i] = r_in[g];
+                if (k) fp[i] = p_in[g];
+            }
+        }
+    };
+    if ((int)blockIdx.x < nt) fetch(blockIdx.x);
+    double rho, mu;
+    if (early_ok)
+        consume2_finish(early, bc, rho, mu);
+    else
+        consume2(rm.p, kMaxRedBlocks, rm.n, bc, rho, mu);
+    double alpha_d, beta_d;
+    cg_scalars(k, rho, mu, alpha_prev, rho_prev, alpha_d, beta_d);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hist_cur[0] = alpha_d;
+        hist_cur[1] = rho;
+    }
+    const float alpha = (float)alpha_d, beta = (float)beta_d;
+    double acc[2] = {0.0, 0.0};
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int tr0 = r0, tc0 = c0;  // this tile (fetch below moves r0, c0 to the next)
+        float dk[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            const int idx = threadIdx.x + o * NT, gr = tr0 + idx / T32, gc = tc0 + idx % T32;
+            dk[o] = k && gr < H && gc < W ? d[(size_t)gr * W + gc] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (e < PS * PS) {
+                sm.r[e] = fr[i];
+                sm.p[e] = k ? fr[i] + beta * fp[i] : fr[i];
+            }
+        }
+        __syncthreads();
+        // the next tile's loads are in flight while this one computes
+        if (t + (int)gridDim.x < nt) fetch(t + gridDim.x);
+        ac_rows<RS, NT>(op, sm.p, PS, PS, SS, sm.h);
+        __syncthreads();
+        ac_cols<RS, NT>(op, sm.h, sm.p, PS, SS, SS, sm.s);  // s_k = A p_k
+        __syncthreads();
+        float* rn = sm.h;  // r_{k+1} on the S region
+        for (int e = threadIdx.x; e < SS * SS; e += NT)
+            rn[e] = sm.r[(e / SS + R) * PS + e % SS + R] - alpha * sm.s[e];
+        __syncthreads();
+        ac_rows<RS, NT>(op, rn, SS, SS, T32, sm.r);
+        __syncthreads();
+        ac_cols<RS, NT>(op, sm.r, rn, SS, T32, T32, sm.s);  // w_{k+1} = A r_{k+1}
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            const int idx = threadIdx.x + o * NT, tr = idx / T32, tc = idx % T32;
+            const int gr = tr0 + tr, gc = tc0 + tc;
+            if (gr < H && gc < W) {
+                const size_t g = (size_t)gr * W + gc;
+                const float rv = rn[(tr + R) * SS + tc + R];
+                const float wv = sm.s[tr * T32 + tc];
+                const float pv = sm.p[(tr + 2 * R) * PS + tc + 2 * R];
+                r_out[g] = rv;
+                p_out[g] = pv;
+                d[g] = k ? dk[o] + alpha * pv : alpha * pv;
+                acc[0] += (double)rv * (double)rv;
+                acc[1] += (double)wv * (double)rv;
+            }
+        }
+        __syncthreads();
+    }
+    block_sum<2, NT>(acc, sred);
+    publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
 // The last CG iteration of an FP call and the difference pass of vector extrapolation
 // (Algorithm 1, step 1) in one pass over the pixels: x_out = x_in + d_k + alpha_k p_k, then
 // u = x_out - x_in, stored as column NC of U (U null: not stored), its inner products with the
@@ -1539,6 +1671,32 @@ Partials launch_cg_iter(const LinOp& op, int H, int W, int k, int last, const fl
         REDVE_CG_ITER(0, kThreads);
     }
 #undef REDVE_CG_ITER
+    return Partials{part, g};
+}
+
+bool cg_iter32_ok(const LinOp& op, int iters, int H, int W) {
+    const bool eligible = op.decim == 1 && op.separable && op.kh == op.kw &&
+                          (op.kh == 7 || op.kh == 9) && iters >= 2;
+    if (!eligible) return false;
+    const int nt16 = ntiles_host(H, W);
+    // rule (measured at 512^2 to 4096^2): the 32x32 form up to 4095 16x16 tiles (1024 x 1024)
+    // and from 32768 (about 2900 x 2900); the 16x16 form between
+    return op.cg_tile ? op.cg_tile == 32
+                      : nt16 >= kWideBelowTiles && (nt16 < 4096 || nt16 >= 32768);
+}
+
+Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_in,
+                          const float* p_in, float* r_out, float* p_out, float* d, Partials rm,
+                          const double* hist_prev, double* hist_cur, double* part,
+                          hipStream_t st) {
+    const int nt = ((H + T32 - 1) / T32) * ((W + T32 - 1) / T32);
+    const int g = nt < kMaxRedBlocks ? nt : kMaxRedBlocks;
+    if (op.kh == 9)
+        k_cg_iter32<4><<<g, kCg32Threads, 0, st>>>(op, H, W, k, r_in, p_in, r_out, p_out, d, rm,
+                                                   hist_prev, hist_cur, part);
+    else
+        k_cg_iter32<3><<<g, kCg32Threads, 0, st>>>(op, H, W, k, r_in, p_in, r_out, p_out, d, rm,
+                                                   hist_prev, hist_cur, part);
     return Partials{part, g};
 }
 

@@ -125,6 +125,7 @@ LinOp linop_of(redve_t h) {
     set_autocorrelations(op);
     op.cg_pack = h->cur.cg_per_launch;
     op.cg_threads = h->cur.cg_threads;
+    op.cg_tile = h->cur.cg_tile;
     return op;
 }
 
@@ -156,11 +157,18 @@ TnrdDev redve_tnrd_dev(redve_t h) {
 
 namespace {
 
-// The handle's denoiser with the single-image launch configuration.
+// The handle's denoiser with the single-image launch configuration; in the BF16 form's
+// finishing FP calls, the same denoiser with FP32 banks and the FP32 window.
 TnrdDev tnrd_of(redve_t h) {
     TnrdDev d = redve_tnrd_dev(h);
     d.stage_threads = h->cur.stage_threads;
     d.phi_table = h->cur.phi_table;
+    if (h->finish_fp32 && d.precision == REDVE_PREC_BF16) {
+        d.precision = REDVE_PREC_FP32;
+        d.kwin = h->kwin32;
+        d.phi_tab = nullptr;
+        d.tab_n = 0;
+    }
     return d;
 }
 
@@ -215,7 +223,7 @@ int run_denoiser(redve_t h, const float* x, int H, int W, float* out, bool resid
         float* dst = last ? out : ((t & 1) ? w.u1 : w.u0);
         const int mode = (last && !residual) ? 1 : 0;
         const ResidualReq* q = last ? rq : nullptr;
-        const bool done = h->precision == REDVE_PREC_BF16
+        const bool done = d.precision == REDVE_PREC_BF16
                               ? launch_tnrd_stage_bf16(d, t, wprev, x, dst, H, W, mode, h->stream, q)
                               : launch_tnrd_stage(d, t, wprev, x, dst, H, W, mode, h->stream, q);
         if (q && rq_done) *rq_done = done;
@@ -256,6 +264,29 @@ int cg_iterate(redve_t h, const float* x_in, float* x_out, int H, int W, int ite
             LAUNCH_CHECK(h);
             a = b;
         }
+    } else if (cg_iter32_ok(op, iters, H, W)) {
+        // 32x32 tiles keeping only r, p, d: p double-buffered in the s buffers, which this
+        // form does not otherwise use; the last iteration below reads p_{n-2} from pb[a]
+        rm = launch_cg_w0(op, w.r[0], w.w[0], H, W, slot[0], h->stream);
+        LAUNCH_CHECK(h);
+        float* pb[2] = {w.s[0], w.s[1]};
+        for (; k < iters - 1; ++k) {
+            const int b = a ^ 1;
+            rm = launch_cg_iter32(op, H, W, k, w.r[a], pb[a], w.r[b], pb[b], w.d, rm,
+                                  w.cg_hist + 2 * a, w.cg_hist + 2 * b, slot[b], h->stream);
+            LAUNCH_CHECK(h);
+            a = b;
+        }
+        if (dq) {
+            dq->nblk = launch_cg_last_diff(H * W, k, w.r[a], pb[a], w.d, x_in, x_out, rm,
+                                           w.cg_hist + 2 * a, dq->U, dq->j, dq->part, h->stream);
+        } else {
+            launch_cg_iter(op, H, W, k, 1, w.r[a], w.w[a], w.s[a], w.r[a ^ 1], w.w[a ^ 1],
+                           w.s[a ^ 1], pb[a], w.d, x_in, x_out, rm, w.cg_hist + 2 * a,
+                           w.cg_hist + 2 * (a ^ 1), slot[a ^ 1], h->stream);
+        }
+        LAUNCH_CHECK(h);
+        return REDVE_OK;
     } else {
         rm = launch_cg_w0(op, w.r[0], w.w[0], H, W, slot[0], h->stream);
         LAUNCH_CHECK(h);
@@ -449,6 +480,7 @@ int capture_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, PassGr
     g.op_gen = h->op_gen;
     g.arena = h->ws.arena;
     g.tune = h->cur;
+    g.finish_fp32 = h->finish_fp32;
     return REDVE_OK;
 }
 
@@ -460,7 +492,8 @@ int run_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, float** ne
         for (auto& e : h->pass)
             if (e.exec && e.from == x_cur && e.hx == hx && e.wx == wx && e.m == h->m &&
                 e.sd_mu == h->sd_mu && e.gen == h->gen && e.op_gen == h->op_gen &&
-                e.arena == h->ws.arena && !memcmp(&e.tune, &h->cur, sizeof(h->cur)))
+                e.arena == h->ws.arena && !memcmp(&e.tune, &h->cur, sizeof(h->cur)) &&
+                e.finish_fp32 == h->finish_fp32)
                 g = &e;
         if (!g) {
             PassGraph& slot = h->pass[h->pass_next];
@@ -514,6 +547,11 @@ redve_tuning_t resolve_tuning(redve_t h, int hx, int wx, redve_tuning_t c) {
     const int rule_threads = cg_rule_threads(op, hx, wx);
     const bool wide_ok = op.separable && op.kh == op.kw && (op.kh == 7 || op.kh == 9);
     r.cg_threads = c.cg_threads ? (c.cg_threads == 1024 && wide_ok ? 1024 : 256) : rule_threads;
+    LinOp o3 = op;
+    o3.cg_pack = 1;
+    o3.cg_tile = c.cg_tile;
+    r.cg_tile = cg && r.cg_per_launch == 1 && cg_iter32_ok(o3, h->cg_iters, hx, wx) ? 32 : 16;
+    if (r.cg_tile == 32) r.cg_threads = 256;  // the 32x32 kernel has its own; the last is 256
     r.fused_start = cg && c.fused_start != 2 && r.cg_per_launch == 2 &&
                             r.stage_threads == 1024 && stage_forms_start(h, r.phi_table)
                         ? 1
@@ -544,9 +582,9 @@ void write_tuned(const std::string& path, const TuneEntry& t) {
     for (int i = 0; i < 13; ++i) fprintf(f, i ? ", %d" : "%d", t.key[i]);
     fprintf(f,
             "], \"stage_threads\": %d, \"phi_table\": %d, \"cg_per_launch\": %d, "
-            "\"cg_threads\": %d, \"fused_start\": %d, \"us\": %.3f}\n",
+            "\"cg_threads\": %d, \"fused_start\": %d, \"cg_tile\": %d, \"us\": %.3f}\n",
             t.cfg.stage_threads, t.cfg.phi_table, t.cfg.cg_per_launch, t.cfg.cg_threads,
-            t.cfg.fused_start, t.us);
+            t.cfg.fused_start, t.cfg.cg_tile, t.us);
     fclose(f);
 }
 
@@ -560,11 +598,13 @@ void read_tuned(redve_t h, const std::string& path) {
         const int n = sscanf(line,
                              "{\"key\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d], "
                              "\"stage_threads\": %d, \"phi_table\": %d, \"cg_per_launch\": %d, "
-                             "\"cg_threads\": %d, \"fused_start\": %d, \"us\": %lf}",
+                             "\"cg_threads\": %d, \"fused_start\": %d, \"cg_tile\": %d, "
+                             "\"us\": %lf}",
                              &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &k[6], &k[7], &k[8], &k[9],
                              &k[10], &k[11], &k[12], &t.cfg.stage_threads, &t.cfg.phi_table,
-                             &t.cfg.cg_per_launch, &t.cfg.cg_threads, &t.cfg.fused_start, &t.us);
-        if (n == 19) put_tuned(h, t);
+                             &t.cfg.cg_per_launch, &t.cfg.cg_threads, &t.cfg.fused_start,
+                             &t.cfg.cg_tile, &t.us);
+        if (n == 20) put_tuned(h, t);
     }
     fclose(f);
 }
@@ -576,18 +616,17 @@ std::vector<redve_tuning_t> tuning_candidates(redve_t h, int hx, int wx) {
         for (int tab : {1, 2})
             for (int pk : {1, 2})
                 for (int ct : {256, 1024})
-                    for (int fs : {1, 2}) {
-                        const redve_tuning_t r = resolve_tuning(h, hx, wx, {st, tab, pk, ct, fs});
-                        if (r.stage_threads != st || r.phi_table != tab || r.cg_per_launch != pk ||
-                            r.fused_start != fs)
-                            continue;  // not valid as asked
-                        // the one-iteration kernel's threads only matter without pairs
-                        if (pk == 2 && ct != r.cg_threads) continue;
-                        if (r.cg_threads != ct && pk == 1) continue;
-                        bool dup = false;
-                        for (const auto& o : out) dup = dup || !memcmp(&o, &r, sizeof(r));
-                        if (!dup) out.push_back(r);
-                    }
+                    for (int fs : {1, 2})
+                        for (int tl : {16, 32}) {
+                            const redve_tuning_t r =
+                                resolve_tuning(h, hx, wx, {st, tab, pk, ct, fs, tl});
+                            if (r.stage_threads != st || r.phi_table != tab ||
+                                r.cg_per_launch != pk || r.fused_start != fs)
+                                continue;  // not valid as asked
+                            bool dup = false;
+                            for (const auto& o : out) dup = dup || !memcmp(&o, &r, sizeof(r));
+                            if (!dup) out.push_back(r);
+                        }
     return out;
 }
 
@@ -864,6 +903,7 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
     // 1e-6 for the BF16 form (5.2565), far below the BF16 operands' own 3.9e-3
     const double reach = p->precision == REDVE_PREC_BF16 ? 5.2565 : 7.4338;
     h->kwin = p->stages > 0 ? std::max(1, (int)ceil(reach * p->gamma / p->dmu - 0.5)) : 1;
+    h->kwin32 = p->stages > 0 ? std::max(1, (int)ceil(7.4338 * p->gamma / p->dmu - 0.5)) : 1;
     h->theta.assign(h->T, 0.f);
     if (h->T > 0) {
         // weights as rows of J + 2 kRbfPad, zero-padded both sides (the stage kernels copy
@@ -978,6 +1018,15 @@ int redve_set_extrapolation(redve_t h, int method, int L, int m) {
     return REDVE_OK;
 }
 
+int redve_set_precision_switch(redve_t h, double delta) {
+    if (!h) return REDVE_E_ARG;
+    if (!(delta >= 0) || !std::isfinite(delta))
+        return fail(h, REDVE_E_ARG, "the switch must be finite and >= 0");
+    if (delta != h->prec_switch) ++h->gen;  // the batched rounds record their stage kernel
+    h->prec_switch = delta;
+    return REDVE_OK;
+}
+
 int redve_set_guard(redve_t h, double gamma_cap) {
     if (!h) return REDVE_E_ARG;
     if (std::isnan(gamma_cap)) return fail(h, REDVE_E_ARG, "gamma_cap must not be NaN");
@@ -1007,7 +1056,8 @@ int redve_set_tuning(redve_t h, const redve_tuning_t* t) {
                     t->phi_table >= 0 && t->phi_table <= 2 && t->cg_per_launch >= 0 &&
                     t->cg_per_launch <= 2 &&
                     (t->cg_threads == 0 || t->cg_threads == 256 || t->cg_threads == 1024) &&
-                    t->fused_start >= 0 && t->fused_start <= 2;
+                    t->fused_start >= 0 && t->fused_start <= 2 &&
+                    (t->cg_tile == 0 || t->cg_tile == 16 || t->cg_tile == 32);
     if (!ok) return fail(h, REDVE_E_ARG, "tuning field out of range");
     if (t->phi_table == 1 && t->stage_threads == 512)
         return fail(h, REDVE_E_ARG, "tabulated influence functions need 1024 stage threads");
@@ -1235,6 +1285,13 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
     double delta = INFINITY, gl1max = 0.0;
     Progress prog;
     float* x_cur = w.xa;
+    // BF16 form: FP32 banks for the FP calls after the relative change first falls below the
+    // switch (prec_switch > 0)
+    h->finish_fp32 = false;
+    auto maybe_switch = [&] {
+        if (h->prec_switch > 0 && h->precision == REDVE_PREC_BF16 && delta < h->prec_switch)
+            h->finish_fp32 = true;
+    };
 
     if (h->method == REDVE_VE_NONE) {
         while (calls < h->max_fp) {
@@ -1245,6 +1302,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
             x_cur = nxt;
             if ((status = prog.check(delta))) break;
             if (delta < h->tol) break;
+            maybe_switch();
         }
     } else {
         // Algorithm 3 (full cycling): m FP calls, then L = kappa+1 more whose differences form
@@ -1283,6 +1341,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
             }
             if ((status = prog.check(delta))) break;
             if (delta < h->tol) break;
+            maybe_switch();
         }
     }
     if (status == REDVE_OK) {
@@ -1293,6 +1352,7 @@ int redve_solve(redve_t h, const float* y, int hy, int wy, const float* x0, floa
             x_cur = nxt;
         }
     }
+    h->finish_fp32 = false;
     // the result is queued in stream order; the statistics are already on the host
     HIP_TRY(h, hipMemcpyAsync(x, x_cur, bytes, hipMemcpyDeviceToDevice, h->stream));
     if (st) {

@@ -449,6 +449,22 @@ __global__ __launch_bounds__(512) void k_tnrd_stage_f32_batch(
                                    theta, out_mode);
 }
 
+// Per tile, the image's form: BF16 banks on the KB window, or FP32 banks on the KF window.
+template <int KB, int KF, int ZS>
+__global__ __launch_bounds__(512) void k_tnrd_stage_mixed_batch(
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles,
+    const float* __restrict__ w_base, float* __restrict__ out_base, const void* __restrict__ bfwd,
+    const void* __restrict__ badj, const void* __restrict__ ffwd, const void* __restrict__ fadj,
+    const float* __restrict__ rbfw, int F, RbfParams rcb, RbfParams rcf, float theta,
+    int out_mode) {
+    if (desc[tiles[blockIdx.x].img].fp32_banks)
+        stage_batch_tile<KF, 512, ZS, true>(desc, tiles, w_base, out_base, ffwd, fadj, rbfw, F,
+                                            rcf, theta, out_mode);
+    else
+        stage_batch_tile<KB, 512, ZS, false>(desc, tiles, w_base, out_base, bfwd, badj, rbfw, F,
+                                             rcb, theta, out_mode);
+}
+
 int row_stride(int F) { return F > 25 ? 33 : 25; }
 
 constexpr int kWideStageBelow = 512;  // tiles: fewer than two per CU
@@ -629,6 +645,25 @@ bool launch_tnrd_stage_bf16(const TnrdDev& d, int t, const float* w_prev, const 
 
 int tnrd_rule_threads(int H, int W) {
     return ((W + TW - 1) / TW) * ((H + TH - 1) / TH) < kWideStageBelow ? 1024 : 512;
+}
+
+void launch_tnrd_stage_mixed_batch(const TnrdDev& db, const TnrdDev& df, int t,
+                                   const ImgDesc* desc, const TileRef* tiles, int ntiles,
+                                   const float* w_prev, float* out, int out_mode, hipStream_t st) {
+    const StageArgs b = stage_args<false>(db, t, w_prev, nullptr, out, 0, 0, out_mode, false);
+    const StageArgs f = stage_args<true>(df, t, w_prev, nullptr, out, 0, 0, out_mode, false);
+    const size_t smem = tnrd_mfma_smem_bytes(db.nfilt, db.nrbf);
+    const bool z33 = row_stride(db.nfilt) == 33;
+#define REDVE_MIXED(KB, KF, ZS)                                                                \
+    k_tnrd_stage_mixed_batch<KB, KF, ZS><<<ntiles, 512, smem, st>>>(                             \
+        desc, tiles, b.w, b.out, b.bf, b.ba, f.bf, f.ba, b.wf, b.F, b.rc, f.rc, b.theta, b.out_mode)
+    const int kb = b.rc.K == 5 ? 5 : 0, kf = f.rc.K == 7 ? 7 : 0;
+    if (kb == 5 && kf == 7) {
+        if (z33) REDVE_MIXED(5, 7, 33); else REDVE_MIXED(5, 7, 25);
+    } else {
+        if (z33) REDVE_MIXED(0, 0, 33); else REDVE_MIXED(0, 0, 25);
+    }
+#undef REDVE_MIXED
 }
 
 bool tnrd_fuses_residual(const TnrdDev& d) {

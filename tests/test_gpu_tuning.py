@@ -51,14 +51,14 @@ def host(t):
     return t.detach().cpu().double().numpy()
 
 
-FIELDS = ("stage_threads", "phi_table", "cg_per_launch", "cg_threads", "fused_start")
+FIELDS = ("stage_threads", "phi_table", "cg_per_launch", "cg_threads", "fused_start", "cg_tile")
 
 
 def valid_configs(r, hx, wx):
     """Every configuration the library accepts and resolves to itself for this image."""
     from paper_1805_02158_amd import RedveError
     out = []
-    for v in itertools.product((512, 1024), (1, 2), (1, 2), (256, 1024), (1, 2)):
+    for v in itertools.product((512, 1024), (1, 2), (1, 2), (256, 1024), (1, 2), (16, 32)):
         cfg = dict(zip(FIELDS, v))
         try:
             r.set_tuning(cfg)
@@ -139,3 +139,29 @@ def test_autotune_picks_caches_and_reuses(torch, orc, tmp_path):
     x2, _ = r2.solve(dev(torch, y32), hx, wx)
     assert len(cache.read_text().splitlines()) == 1
     assert np.array_equal(host(x2), host(x))
+
+
+@pytest.mark.parametrize("shape", [(37, 53), (100, 70), (2, 3), (400, 330), (520, 512)])
+@pytest.mark.parametrize("psf", ["u9", "g7"])
+@pytest.mark.parametrize("tile", [16, 32])
+def test_cg_forms_match_the_oracle(torch, orc, shape, psf, tile):
+    """CG on A x = rhs against the oracle's CG with the one-iteration kernel forced to 16x16
+    tiles (r, A r, A p, p, d in HBM) or 32x32 tiles (r, p, d only; A r and A p recomputed on
+    halos of 2 x 8 or 2 x 6 pixels): images smaller than one tile and than the halo (periodic
+    wrap), ragged tiles, and images of more than 512 16x16 tiles, 1 to 15 iterations."""
+    from paper_1805_02158_amd import Restorer
+    k = W.psf_uniform(9) if psf == "u9" else W.psf_gaussian(7, 1.6)
+    r = Restorer(0)
+    r.set_operator(k, 1).set_noise(2 ** 0.5).set_lambda(0.02)
+    r.set_tuning({"cg_per_launch": 1, "cg_tile": tile})
+    got, _ = r.get_tuning(*shape)
+    assert got["cg_tile"] == tile
+    rng = np.random.default_rng(9)
+    x0 = f32(rng.uniform(0, 255, shape))
+    rhs = f32(orc.apply_A(rng.uniform(0, 255, shape), k, 1, 2 ** 0.5, 0.02))
+    for iters in (1, 2, 3, 15):
+        xg = host(r.cg(dev(torch, rhs), dev(torch, x0), iters))
+        xo = orc.cg(rhs, x0, f32(k), 1, 2 ** 0.5, 0.02, iters)
+        e = rel(xg, xo)
+        say(f"  {shape} {psf} tile {tile} iters {iters}: rel L2 {e:.2e}")
+        assert e <= 2e-5, iters
