@@ -52,7 +52,16 @@ def parse():
     ap.add_argument("--batch-images", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-sd", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=160)
+    ap.add_argument("--no-torch-profiler", action="store_true",
+                    help="skip the per-kernel splits taken with torch's profiler (for runs under "
+                         "rocprofv3, which records the kernels itself)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="timed requests of the serving trace (after --serve-warmup more)")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-distinct", type=int, default=200,
+                    help="distinct seeded problems the trace's requests cycle through")
+    ap.add_argument("--no-sr", action="store_true",
+                    help="skip the 512x512 3x super-resolution workload")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--cost-protocol", action="store_true",
@@ -68,8 +77,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+NO_TORCH_PROFILER = False
+
+
 def main():
+    global NO_TORCH_PROFILER
     args = parse()
+    NO_TORCH_PROFILER = args.no_torch_profiler
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the restoration of one image runs on one device and "
               "this build has no multi-GPU path (--gpus 1 only).", file=sys.stderr)
@@ -109,21 +123,24 @@ def main():
 
     out = torch.empty((H, Wd), dtype=torch.float32, device=dev)
 
-    state = {"prec": "fp32"}  # configure() above loaded the FP32 banks
+    state = {"prec": "fp32", "lin": "cg"}  # configure() above loaded the FP32 banks
 
-    def solve(method, prec, calls):
+    def solve(method, prec, calls, lin="cg"):
         if state["prec"] != prec:
             R.set_denoiser(prob.denoiser, prec)
             state["prec"] = prec
+        if state["lin"] != lin:
+            R.set_linear_solver(lin)
+            state["lin"] = lin
         R.set_extrapolation(method, prob.L, 0)
         R.set_solver(prob.cg_iters, calls, 0.0, 0)
         _, st = R.solve(y, H, Wd, out=out)
         return st
 
-    def n_star(method, prec):
+    def n_star(method, prec, lin="cg"):
         trace = []
         for n in range(1, args.nmax + 1):
-            solve(method, prec, n)
+            solve(method, prec, n, lin)
             trace.append((n, psnr(out)))
         ns = None
         for n, p in trace:
@@ -133,15 +150,15 @@ def main():
                 ns = None
         return ns, trace
 
-    def timed(method, prec, calls):
+    def timed(method, prec, calls, lin="cg"):
         for _ in range(args.warmup):
-            solve(method, prec, calls)
+            solve(method, prec, calls, lin)
         torch.cuda.synchronize()
         lat = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ts = time.perf_counter()
-            st = solve(method, prec, calls)
+            st = solve(method, prec, calls, lin)
             lat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
@@ -150,17 +167,22 @@ def main():
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "fp_calls_to_target": calls, "cycles": st["cycles"], "psnr_db": psnr(out)}
 
-    forms = {"plain_fp32": ("none", "fp32"), "ve_fp32": ("rre", "fp32"), "ve_bf16": ("rre", "bf16")}
+    # the three forms of the configuration (15 CG iterations per FP call), then, beside them,
+    # RRE + BF16 with the exact Fourier linear step (F4) in place of CG
+    forms = {"plain_fp32": ("none", "fp32", "cg"), "ve_fp32": ("rre", "fp32", "cg"),
+             "ve_bf16": ("rre", "bf16", "cg"), "ve_bf16_fft": ("rre", "bf16", "fft")}
     res_forms = {}
-    for name, (method, prec) in forms.items():
-        ns, tr = n_star(method, prec)
+    for name, (method, prec, lin) in forms.items():
+        ns, tr = n_star(method, prec, lin)
         if ns is None:
             print(json.dumps({"error": f"target PSNR not reached by {name}", "trace": tr}))
             sys.exit(1)
-        res_forms[name] = timed(method, prec, ns)
+        res_forms[name] = timed(method, prec, ns, lin)
+        res_forms[name]["linear_step"] = lin
         res_forms[name]["roofline_whole_solve"] = whole_solve_roofline(
-            npx * ns / (res_forms[name]["ms_per_step"] * 1e-3), prob.cg_iters)
+            npx * ns / (res_forms[name]["ms_per_step"] * 1e-3), prec, prob.cg_iters, lin)
         log(name, res_forms[name])
+    solve("rre", "bf16", 1, "cg")  # back to the CG linear step
     ve = res_forms["ve_bf16"]
     fp = res_forms["plain_fp32"]
 
@@ -173,7 +195,7 @@ def main():
     R.set_denoiser(prob.denoiser, "bf16")
     stage_us = time_stage(torch, R, y, prob.denoiser.stages)
     blk_us = 2 * time_cg_iter(torch, R, y)  # 30 iterations = 15 launches of two
-    roof_stage = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16")
+    roof_stage = roofline_stage(npx, stage_us, "k_tnrd_stage_bf16", "bf16")
     roof_cg = roofline_cg(npx, blk_us, "k_cg_block<4>", 2)
     share = {"k_tnrd_stage_bf16": prob.denoiser.stages * stage_us,
              "k_cg_block<4>": (prob.cg_iters // 2) * blk_us}
@@ -181,12 +203,14 @@ def main():
     roof["share_of_fp_call_us"] = share
     big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device=dev)
     stage_big_us = time_stage(torch, R, big, prob.denoiser.stages)
-    roof_big = roofline_stage(big.numel(), stage_big_us, "k_tnrd_stage_bf16")
+    roof_big = roofline_stage(big.numel(), stage_big_us, "k_tnrd_stage_bf16", "bf16")
     cg_big_us = time_cg_iter(torch, R, big)
-    roof_cg_big = roofline_cg(big.numel(), cg_big_us, "k_cg_iter<4>", 1)
+    # the one-iteration kernel the rules pick there: 32x32 tiles keeping r, p, d only
+    cg_big_kernel = "k_cg_iter32<4>" if R.get_tuning(2048, 2048)[0]["cg_tile"] == 32 else "k_cg_iter<4>"
+    roof_cg_big = roofline_cg(big.numel(), cg_big_us, cg_big_kernel, 1)
     R.set_denoiser(prob.denoiser, "fp32")
     stage32_big_us = time_stage(torch, R, big, prob.denoiser.stages)
-    roof32_big = roofline_stage(big.numel(), stage32_big_us, "k_tnrd_stage_f32")
+    roof32_big = roofline_stage(big.numel(), stage32_big_us, "k_tnrd_stage_f32", "fp32")
     del big
 
     res = {
@@ -207,6 +231,12 @@ def main():
                    "method": "FP + RRE (L=5)",
                    "precision": "BF16 filter-bank operands on MFMA with FP32 accumulation; "
                                 "RBF influence, update and CG in FP32; VE Gram/solve in FP64",
+                   "forms": {"value (ve_bf16)": "the mixed-precision form (BF16 banks) of this "
+                                                "workload, RRE L=5",
+                             "ve_fp32": "the FP32 form of this workload, RRE L=5",
+                             "plain_fp32": "plain FP, FP32",
+                             "ve_bf16_fft": "RRE L=5, BF16 banks, exact Fourier linear step "
+                                            "instead of 15 CG iterations"},
                    "fp_calls_to_target": ve["fp_calls_to_target"],
                    "psnr_target_db": psnr_star, "band_db": BAND_DB},
         "p50_ms": ve["p50_ms"],
@@ -217,10 +247,13 @@ def main():
         "roofline": roof,
         "roofline_kernels": {"k_tnrd_stage_bf16": roof_stage, "k_cg_block<4>": roof_cg},
         "roofline_2048x2048": {"k_tnrd_stage_bf16": roof_big, "k_tnrd_stage_f32": roof32_big,
-                               "k_cg_iter<4>": roof_cg_big},
+                               cg_big_kernel: roof_cg_big},
     }
     if not args.no_sd:
         res["steepest_descent"] = bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star)
+    res["ve_kernels_2048x2048"] = bench_ve_kernels(torch, W, Restorer, prob)
+    if not args.no_sr:
+        res["sr512"] = bench_sr(args, torch, np, W, Restorer)
     if not args.no_batch:
         res["batched"] = bench_batch(args, torch, np, W, Restorer, psnr)
     if not args.no_serve:
@@ -305,7 +338,10 @@ def pmc_probe(torch, R, prob, y):
     exactly 256 MiB in and 256 MiB out), then at the headline size 5 CG runs of 15 iterations
     (FP32), 5 denoiser calls with BF16 banks and 5 FP calls with them (their last stage forms
     the CG start), then a CG run and a denoiser call on a 2048x2048 image and one denoiser
-    call there with FP32 banks."""
+    call there with FP32 banks; CG runs with the one-iteration kernel forced to 32x32 tiles at
+    2048x2048 and to either tile at 4096x4096; an FP call with the Fourier linear step and an
+    RRE solve of 7 FP calls (one extrapolation) at 2048x2048; 3 rounds of the batched engine on
+    the 64-image workload."""
     src = torch.rand(64 << 20, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
@@ -326,32 +362,91 @@ def pmc_probe(torch, R, prob, y):
     R.denoise(big)
     R.set_denoiser(prob.denoiser, "fp32")
     R.denoise(big)
+    R.set_tuning({"cg_per_launch": 1, "cg_tile": 32})
+    R.cg(big, big, prob.cg_iters)
+    huge = torch.tensor(W.make_image(4096, 4096, 78), dtype=torch.float32, device="cuda")
+    R.cg(huge, huge, prob.cg_iters)
+    R.set_tuning({"cg_per_launch": 1, "cg_tile": 16})
+    R.cg(huge, huge, prob.cg_iters)
+    R.set_tuning(None)
+    del huge
+    R.set_denoiser(prob.denoiser, "bf16").set_linear_solver("fft")
+    R.fp_step(big, big)
+    R.set_linear_solver("cg")
+    out = torch.empty_like(big)
+    R.set_extrapolation("rre", prob.L, 0).set_solver(prob.cg_iters, prob.L + 2, 0.0, 0)
+    R.solve(big, 2048, 2048, out=out)
+    torch.cuda.synchronize()
+    probs = W.batch_items(64)
+    items = [dict(y=torch.tensor(p.x_true, dtype=torch.float32, device="cuda"), hx=p.hr_shape[0],
+                  wx=p.hr_shape[1], psf=p.psf, decim=p.decim, sigma=p.sigma, lam=p.lam)
+             for p in probs]
+    R.set_solver(prob.cg_iters, 3, 0.0, 0)
+    R.solve_batch(items)
     torch.cuda.synchronize()
 
 
-# Algorithmic work of one denoiser stage per output pixel: two 24-filter 5x5 banks (forward
-# and adjoint, 2 x 24 x 25 multiply-adds = 2400 FLOP) and 24 influence functions, each the
-# Gaussian RBF sum over the 15 centres within 7.5 gamma of z (the terms beyond add less than
-# 1e-12 of a weight, so this is the sum as defined to FP32 precision; all 63 would be 4.2x
-# more), each term counted as 6 FLOP (difference, square, scale, exp, multiply-add) = 2160 FLOP.
-# The BF16 stage on small images reads phi from a table instead, which does less than this.
-STAGE_FLOP_PER_PX = 2 * 24 * 25 * 2 + 24 * 15 * 6
-# Published MI355X FP32 vector peak (256 CUs, 2.4 GHz).
-FP32_PEAK_TFLOPS = 157.3
+# Algorithmic work of one denoiser stage per output pixel, and the roofline that bounds each
+# part (the stage runs them in one kernel, so its time is bounded by the slowest of the three):
+#  * filter banks: forward and adjoint, F filters of 25 taps: 2 x F x 25 multiply-adds = 2400
+#    FLOP for F = 24, on MFMA (BF16 operands: 2.5 PFLOP/s dense; FP32 operands: 157.3 TFLOP/s).
+#    The MFMA tiles issue more than that (positions of the tile + halo, taps and filters padded):
+#    per 16x16 tile 25 groups of 16 positions x (forward 32 taps x 32 filters + adjoint 32 x 32)
+#    in BF16 = 6400 FLOP per pixel; in FP32 the K-steps stop at the last real tap or filter
+#    (7 x 4 taps, 6 x 4 filters): 5200 FLOP per pixel.
+#  * influence functions: F evaluations of the Gaussian RBF sum over the 2K + 1 centres nearest
+#    z (K = 5 in the BF16 form, 7 in the FP32 form; the terms beyond add less than 1e-6 / 1e-12
+#    of a weight, so this is the defined sum to the form's precision; all 63 centres would be
+#    4.2x to 5.7x more), each term 8 vector-ALU slots (difference, square, scale; exp at a
+#    quarter rate: 4; multiply-add), i.e. 16 FLOP-equivalents at the unpacked FP32 vector peak
+#    (256 CUs x 64 lanes x 2.4 GHz x 2 = 78.6 TFLOP/s; packed FP32 is off in this build, so the
+#    published 157.3 is not reachable).
+#  * state: read u and f, write u: 12 B at 8 TB/s.
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+VALU_PEAK_TFLOPS = 78.6
+TERM_FLOP_EQ = 16
+STAGE_STATE_BYTES = 12
 
 
-def roofline_stage(npx, stage_us, kernel):
-    """The fused denoiser stage is bound by plain ALU arithmetic: its data stays in LDS and
-    registers (HBM traffic about 12 B per pixel) and the influence functions and the banks'
-    operand staging run on the vector ALUs in either precision. achieved = algorithmic FLOP
-    per launch / average launch time, against the FP32 vector peak."""
-    work = npx * STAGE_FLOP_PER_PX
-    achieved = work / (stage_us * 1e-6) / 1e12
-    return {"kernel": kernel, "bound": "alu", "achieved": achieved,
-            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+def stage_work(prec, nfilt=24, nrbf=63):
+    K = 5 if prec == "bf16" else 7
+    terms = nfilt * min(2 * K + 1, nrbf)
+    return {"bank_flop_px": 2 * nfilt * 25 * 2,
+            "bank_issued_flop_px": 6400 if prec == "bf16" else 5200,
+            "phi_terms_px": terms, "phi_flop_eq_px": terms * TERM_FLOP_EQ,
+            "state_bytes_px": STAGE_STATE_BYTES, "window_K": K}
+
+
+def stage_bound_ps(prec, nfilt=24, nrbf=63):
+    """Roofline time of one stage per pixel (ps): the slowest of banks, phi and state."""
+    w = stage_work(prec, nfilt, nrbf)
+    return max(w["bank_flop_px"] / MFMA_PEAK_TFLOPS[prec], w["phi_flop_eq_px"] / VALU_PEAK_TFLOPS,
+               w["state_bytes_px"] / HBM_PEAK_GBS * 1e3)
+
+
+def roofline_stage(npx, stage_us, kernel, prec, nfilt=24, nrbf=63):
+    """The fused denoiser stage: bound by the influence functions on the vector ALUs (their
+    roofline time is 30-50x the banks' on MFMA and 35-50x the state traffic's). achieved = the
+    influence functions' FLOP-equivalents per launch / average launch time, against the unpacked
+    vector peak; the banks' MFMA utilisation (algorithmic and issued FLOP against the MFMA peak
+    of their operand type) and the state traffic are reported beside it."""
+    w = stage_work(prec, nfilt, nrbf)
+    t = stage_us * 1e-6
+    achieved = npx * w["phi_flop_eq_px"] / t / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS,
             "traffic": traffic_of(kernel, npx), "avg_launch_us": stage_us,
-            "flop_per_launch": work,
-            "flop_per_px": STAGE_FLOP_PER_PX, "pixels_per_launch": npx}
+            "flop_per_launch": npx * w["phi_flop_eq_px"], "pixels_per_launch": npx,
+            "work_per_px": w,
+            "banks_mfma": {"bound": "mfma", "peak": MFMA_PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                           "achieved_algorithmic": npx * w["bank_flop_px"] / t / 1e12,
+                           "frac_algorithmic": npx * w["bank_flop_px"] / t / 1e12
+                           / MFMA_PEAK_TFLOPS[prec],
+                           "achieved_issued": npx * w["bank_issued_flop_px"] / t / 1e12,
+                           "frac_issued": npx * w["bank_issued_flop_px"] / t / 1e12
+                           / MFMA_PEAK_TFLOPS[prec]},
+            "state_hbm": {"achieved_gbs": npx * STAGE_STATE_BYTES / t / 1e9,
+                          "frac": npx * STAGE_STATE_BYTES / t / 1e9 / HBM_PEAK_GBS}}
 
 
 def bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star, nmax=2000, nmax_ve=300):
@@ -466,25 +561,58 @@ def observe(torch, R, probs):
 
 
 # Whole-solve roofline: the declared work of one FP call per pixel, by kernel class, each at its
-# own roofline, summed (the classes run one after another): the denoiser's 5 stages (state
-# traffic 5 x 12 B; 5 x STAGE_FLOP_PER_PX at the FP32 vector peak, which bounds them), the CG
-# step (n_cg x 24 B: x, r, p read and written once per iteration) and the extrapolation's
-# difference and combination passes (16.8 B per FP call for L = 5: u written, the Gram reads
-# and the combination spread over a cycle of 5 calls).
-def roofline_ps_per_px_call(n_cg=15):
-    stages = max(5 * 12 / HBM_PEAK_GBS * 1e3, 5 * STAGE_FLOP_PER_PX / FP32_PEAK_TFLOPS)
-    cg = n_cg * CG_BYTES_PER_PX / HBM_PEAK_GBS * 1e3
+# own roofline, summed (the classes run one after another): the denoiser's 5 stages (each the
+# slowest of its banks on MFMA, its influence functions on the vector ALUs and its 12 B of
+# state, see stage_bound_ps), the linear step (CG: n_cg x 24 B, x, r, p read and written once
+# per iteration; the exact Fourier step: 36 B, see fft.hip) and the extrapolation's difference
+# and combination passes (16.8 B per FP call for L = 5: u written, the Gram reads and the
+# combination spread over a cycle of 5 calls).
+FFT_BYTES_PER_PX = 36
+
+
+def roofline_ps_per_px_call(prec="bf16", n_cg=15, linear="cg"):
+    stages = 5 * stage_bound_ps(prec)
+    lin = (n_cg * CG_BYTES_PER_PX if linear == "cg" else FFT_BYTES_PER_PX) / HBM_PEAK_GBS * 1e3
     ve = 16.8 / HBM_PEAK_GBS * 1e3
-    return {"stages_ps": stages, "cg_ps": cg, "ve_ps": ve, "total_ps": stages + cg + ve}
+    return {"stages_ps": stages, "linear_ps": lin, "ve_ps": ve, "total_ps": stages + lin + ve,
+            "precision": prec, "linear_step": linear}
 
 
-def whole_solve_roofline(px_calls_per_s, n_cg=15):
+def whole_solve_roofline(px_calls_per_s, prec="bf16", n_cg=15, linear="cg"):
     """Fraction of the whole-solve roofline: declared time per pixel per FP call over the measured
     one (pixel-FP-calls per second)."""
-    r = roofline_ps_per_px_call(n_cg)
+    r = roofline_ps_per_px_call(prec, n_cg, linear)
     measured = 1e12 / px_calls_per_s
     return {"declared_ps_per_px_fp_call": r, "measured_ps_per_px_fp_call": measured,
             "frac": r["total_ps"] / measured}
+
+
+def batch_kernels(torch, run, prec, px_calls, n_cg=15):
+    """Per kernel class of one batched solve (profiler device times): launches, total time,
+    share, and for the two dominant classes the achieved rate over the whole solve: the stage
+    (5 per FP call; influence-function FLOP-equivalents against the unpacked vector peak) and
+    the CG iteration (15 per FP call; 24 B per pixel and iteration against HBM)."""
+    kt = kernel_times(torch, run)
+    by = {}
+    for name, (c, us) in kt.items():
+        base = name.split("<")[0]
+        bc, bu = by.get(base, (0, 0.0))
+        by[base] = (bc + c, bu + us)
+    total = sum(us for _, us in by.values())
+    out = {k: {"launches": c, "total_ms": us / 1e3, "share": us / total}
+           for k, (c, us) in sorted(by.items(), key=lambda kv: -kv[1][1])}
+    w = stage_work(prec)
+    for k in out:
+        t = out[k]["total_ms"] * 1e-3
+        if k.startswith("k_tnrd_stage"):
+            a = 5 * px_calls * w["phi_flop_eq_px"] / t / 1e12
+            out[k].update({"bound": "alu", "achieved_tflops": a, "peak": VALU_PEAK_TFLOPS,
+                           "frac": a / VALU_PEAK_TFLOPS})
+        elif k == "k_cg_iter_batch":
+            a = n_cg * px_calls * CG_BYTES_PER_PX / t / 1e9
+            out[k].update({"bound": "hbm", "achieved_gbs": a, "peak": HBM_PEAK_GBS,
+                           "frac": a / HBM_PEAK_GBS})
+    return out
 
 
 def bench_batch(args, torch, np, W, Restorer, psnr):
@@ -497,8 +625,9 @@ def bench_batch(args, torch, np, W, Restorer, psnr):
     mpix = sum(p.x_true.size for p in probs) / 1e6
     d = W.make_denoiser()
 
-    def run(method, prec, tol, max_calls):
+    def run(method, prec, tol, max_calls, switch=0.0):
         R.set_denoiser(d, prec).set_extrapolation(method, 5, 0).set_solver(15, max_calls, tol, 0)
+        R.set_precision_switch(switch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         outs, st = R.solve_batch(items)
@@ -513,12 +642,16 @@ def bench_batch(args, torch, np, W, Restorer, psnr):
            "stop": "per image: relative change < 1e-5",
            "reference": "per image: plain FP (FP32) to relative change < 1e-6",
            "mpix": mpix}
-    for name, method, prec, reps in (("ve_bf16", "rre", "bf16", 3), ("ve_fp32", "rre", "fp32", 1),
-                                     ("plain_fp32", "none", "fp32", 1)):
-        run(method, prec, 1e-5, 500)  # warm-up: workspace and graphs
+    # ve_bf16_switch: the BF16 form whose images move to FP32 banks once their relative change
+    # falls below 1e-4 (the last cycles, where BF16 rounding slows the approach to 1e-5)
+    for name, method, prec, reps, sw in (("ve_bf16", "rre", "bf16", 3, 0.0),
+                                         ("ve_bf16_switch", "rre", "bf16", 3, 1e-4),
+                                         ("ve_fp32", "rre", "fp32", 1, 0.0),
+                                         ("plain_fp32", "none", "fp32", 1, 0.0)):
+        run(method, prec, 1e-5, 500, sw)  # warm-up: workspace and graphs
         times = []
         for _ in range(reps):
-            dt, outs, st = run(method, prec, 1e-5, 500)
+            dt, outs, st = run(method, prec, 1e-5, 500, sw)
             times.append(dt)
         dt = float(np.median(times))
         dps = [psnr(o, xt) - rp for o, xt, rp in zip(outs, xts, ref_psnr)]
@@ -530,32 +663,51 @@ def bench_batch(args, torch, np, W, Restorer, psnr):
                      "images_within_band": int(sum(abs(v) <= BAND_DB for v in dps)),
                      "worst_dpsnr_db": float(min(dps))}
         out[name]["roofline_whole_solve"] = whole_solve_roofline(
-            out[name]["mpix_fp_calls_per_s"] * 1e6)
+            out[name]["mpix_fp_calls_per_s"] * 1e6, prec)
+        out[name]["kernels"] = batch_kernels(
+            torch, lambda: run(method, prec, 1e-5, 500, sw), prec,
+            sum(c * p.x_true.size for c, p in zip(calls, probs)))
+        if sw:
+            out[name]["switch_rel_change"] = sw
+            out[name]["note"] = ("stage work counted at the BF16 window (K=5) for every call, "
+                                 "also those on FP32 banks (K=7): a lower bound of the rate")
         log("batched", name, out[name])
     out["ve_bf16_speedup_vs_plain_fp32"] = out["plain_fp32"]["s_per_batch"] / out["ve_bf16"]["s_per_batch"]
+    out["ve_bf16_switch_speedup_vs_plain_fp32"] = (out["plain_fp32"]["s_per_batch"]
+                                                   / out["ve_bf16_switch"]["s_per_batch"])
+    R.set_precision_switch(0.0)
     R.close()
     return out
 
 
 def bench_serve(args, torch, np, W, Restorer):
+    """Continuous-batching server on the serving trace: requests with sides log-uniform in
+    128..2048, deblurring (9x9 uniform) or 3x SR (Gaussian 7x7), sigma sqrt(2) or 5. The
+    requests cycle through `serve_distinct` seeded problems of that distribution (their
+    observations made once on the GPU); arrivals are a Poisson process. Saturation: every
+    request queued at once (throughput). Then the same requests at 0.7 x that rate (latency
+    p50 / p99 from submission to completion), `serve_warmup` requests first, untimed."""
     from paper_1805_02158_amd import Server
-    trace = W.serve_trace(args.serve_requests, 1.0)
+    trace = W.serve_trace(args.serve_distinct, 1.0)
     probs = [p for _, p in trace]
     R = Restorer(0)
     ys = observe(torch, R, probs)
-    reqs = [dict(y=y, hx=p.hr_shape[0], wx=p.hr_shape[1], psf=p.psf, decim=p.decim,
+    base = [dict(y=y, hx=p.hr_shape[0], wx=p.hr_shape[1], psf=p.psf, decim=p.decim,
                  sigma=p.sigma, lam=p.lam) for p, y in zip(probs, ys)]
-    mpix = sum(p.x_true.size for p in probs) / 1e6
+    nw, nt = args.serve_warmup, args.serve_requests
+    reqs = [base[i % len(base)] for i in range(nw + nt)]
+    px = [base[i % len(base)]["hx"] * base[i % len(base)]["wx"] for i in range(nw + nt)]
+    gaps = np.random.default_rng(4001).exponential(1.0, nw + nt)  # Poisson arrivals at rate 1
     R.set_denoiser(W.make_denoiser(), "bf16").set_extrapolation("rre", 5, 0).set_solver(15, 500, 1e-5, 0)
     budget = int(args.serve_budget_gb * (1 << 30))
 
     srv = Server(R, budget, args.serve_max_active)
 
-    def serve(arrivals):
+    def serve(arrivals, rq):
         rounds0 = srv.counts()["rounds"]
         t0 = time.perf_counter()
         tickets = []
-        for a, d in zip(arrivals, reqs):
+        for a, d in zip(arrivals, rq):
             now = time.perf_counter() - t0
             if a > now:
                 time.sleep(a - now)
@@ -566,17 +718,23 @@ def bench_serve(args, torch, np, W, Restorer):
         bad = sum(s["status"] != 0 for s in st)
         return makespan, lat, srv.counts()["rounds"] - rounds0, bad
 
-    serve([0.0] * 16)  # warm-up: the graphs of the first tile-list lengths
-    mk, lat_sat, rounds_sat, bad = serve([0.0] * len(reqs))
-    rate_sat = len(reqs) / mk
+    serve([0.0] * nw, reqs[:nw])  # warm-up: the graphs of the tile-list lengths
+    mk, lat_sat, rounds_sat, bad = serve([0.0] * nt, reqs[nw:])
+    mpix = sum(px[nw:]) / 1e6
+    rate_sat = nt / mk
+    log("serving saturation", f"{rate_sat:.1f} req/s, {mpix / mk:.1f} MPix/s")
     rate = 0.7 * rate_sat
-    arrivals = [a / rate for a, _ in trace]  # the trace's arrivals (drawn at rate 1) at `rate`
-    mk2, lat, rounds2, bad2 = serve(arrivals)
+    arr = np.cumsum(gaps) / rate
+    serve(arr[:nw] - arr[0], reqs[:nw])  # warm-up at the trace's rate
+    mk2, lat, rounds2, bad2 = serve(arr[nw:] - arr[nw], reqs[nw:])
+    occ = srv.occupancy()
     srv.close()
-    res = {"workload": f"{len(reqs)} requests, sides log-uniform 128..2048 ({mpix:.1f} MPix), "
+    res = {"workload": f"{nt} requests after {nw} warm-up, cycling through {len(base)} seeded "
+                       f"problems with sides log-uniform 128..2048 ({mpix:.1f} MPix timed), "
                        "deblur 9x9 uniform or 3x SR Gaussian 7x7, sigma sqrt(2) or 5, RRE L=5, "
                        "BF16 banks, stop at relative change < 1e-5",
            "hbm_budget_gb": args.serve_budget_gb, "max_active": args.serve_max_active,
+           "occupancy": occ,
            "saturation": {"req_s": rate_sat, "mpix_s": mpix / mk, "rounds": rounds_sat,
                           "p50_ms": float(np.percentile(lat_sat, 50)),
                           "p99_ms": float(np.percentile(lat_sat, 99)), "failed": bad},
@@ -588,12 +746,171 @@ def bench_serve(args, torch, np, W, Restorer):
     return res
 
 
+def bench_sr(args, torch, np, W, Restorer, steps=10):
+    """The 512x512 3x super-resolution workload (Gaussian 7x7, sigma 5, lambda 0.02, 15 CG,
+    RRE with L = 8): restored MPix/s to its oracle-converged PSNR (tests/golden/
+    bench_target_sr512.json, written by a script that calls only the oracle), by the protocol
+    of the headline workload: n* from untimed solves of n = 1, 2, ... FP calls (plain FP: from
+    the FP iterates themselves), then `steps` timed solves of n* calls."""
+    path = os.path.join(ROOT, "tests", "golden", "bench_target_sr512.json")
+    if not os.path.exists(path):
+        return {"skipped": "no oracle target for the 512x512 SR workload"}
+    psnr_star = json.load(open(path))["psnr_star_db"]
+    prob = W.problem("sr512")
+    H, Wd = prob.hr_shape
+    npx = H * Wd
+    R = Restorer(0)
+    R.configure(prob, method="rre", L=prob.L, m=0, tol=0.0)
+    xt = torch.tensor(prob.x_true, dtype=torch.float32, device="cuda")
+    y = R.apply_H(xt) + float(prob.sigma) * torch.tensor(prob.noise, dtype=torch.float32,
+                                                            device="cuda")
+    out = torch.empty((H, Wd), dtype=torch.float32, device="cuda")
+
+    def psnr(x):
+        mse = torch.mean((x.double() - xt.double()) ** 2).item()
+        return 10.0 * math.log10(255.0 ** 2 / mse)
+
+    def band_start(trace):
+        ns = None
+        for n, p in trace:
+            if abs(p - psnr_star) <= BAND_DB:
+                ns = n if ns is None else ns
+            else:
+                ns = None
+        return ns
+
+    res = {"workload": "512x512 3x super-resolution (171x171 observation), Gaussian 7x7 std 1.6, "
+                       "sigma 5, lambda 0.02, 15 CG/FP call, TNRD-style D 5x24x(5x5), RRE L=8",
+           "psnr_target_db": psnr_star}
+    for name, method, prec, nmax in (("ve_bf16", "rre", "bf16", 80), ("ve_fp32", "rre", "fp32", 80),
+                                     ("plain_fp32", "none", "fp32", 400)):
+        R.set_denoiser(prob.denoiser, prec).set_extrapolation(method, prob.L, 0)
+        trace = []
+        if method == "none":
+            R.set_solver(prob.cg_iters, 0, 0.0, 0)
+            x = R.solve(y, H, Wd)[0]  # the initial vector (no FP call)
+            for n in range(1, nmax + 1):
+                x = R.fp_step(y, x)
+                trace.append((n, psnr(x)))
+        else:
+            for n in range(1, nmax + 1):
+                R.set_solver(prob.cg_iters, n, 0.0, 0)
+                R.solve(y, H, Wd, out=out)
+                trace.append((n, psnr(out)))
+        ns = band_start(trace)
+        if ns is None:
+            res[name] = {"fp_calls_to_target": None, "searched_up_to": nmax}
+            continue
+        R.set_solver(prob.cg_iters, ns, 0.0, 0)
+        R.solve(y, H, Wd, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            R.solve(y, H, Wd, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"fp_calls_to_target": ns, "mpix_s": npx / dt / 1e6, "ms_per_solve": dt * 1e3,
+                     "psnr_db": psnr(out),
+                     "roofline_whole_solve": whole_solve_roofline(npx * ns / dt, prec,
+                                                                  prob.cg_iters)}
+        log("sr512", name, res[name])
+    R.close()
+    return res
+
+
+def kernel_times(torch, fn):
+    """Device time of each kernel `fn` launches, from torch's profiler (it records the HIP
+    kernels of every library in the process): {name: (launches, total microseconds)}."""
+    if NO_TORCH_PROFILER:
+        fn()
+        torch.cuda.synchronize()
+        return {}
+    from torch.profiler import ProfilerActivity, profile
+    torch.cuda.synchronize()
+    with profile(activities=[ProfilerActivity.CUDA]) as prof:
+        fn()
+        torch.cuda.synchronize()
+    import re
+    out = {}
+    for e in prof.key_averages():
+        us = getattr(e, "device_time_total", None)
+        if us is None:
+            us = getattr(e, "cuda_time_total", 0.0)
+        m = re.search(r"(k_[A-Za-z0-9_]+(<[^>(]*>)?)\(", e.key)
+        if "redve::" not in e.key or us <= 0 or not m:
+            continue
+        name = m.group(1)
+        c, t = out.get(name, (0, 0.0))
+        out[name] = (c + e.count, t + us)
+    return out
+
+
+# Algorithmic HBM bytes per pixel of the extrapolation passes (window column j, L = 5):
+# the difference pass reads x_new and x_old and the j earlier columns and writes u (12 + 4 j);
+# the last CG iteration fused with it also reads r, p, d and x_in (another 16: 28 + 4 j); the
+# combination reads x_m and kappa columns and writes the result (4 (kappa + 2)).
+def ve_bytes_per_px(kernel, L=5):
+    if kernel.startswith("k_diff_gram<"):
+        return 12 + 4 * int(kernel[len("k_diff_gram<"):-1])
+    if kernel.startswith("k_cg_last_diff<"):
+        return 28 + 4 * int(kernel[len("k_cg_last_diff<"):-1])
+    if kernel == "k_ve_combine":
+        return 4 * (L - 1 + 2)
+    return None
+
+
+def bench_ve_kernels(torch, W, Restorer, prob):
+    """The extrapolation's streaming passes on a 2048 x 2048 image (4.19 M pixels, every CU
+    busy), device times from the profiler: five extrapolations of a six-iterate window (L = 5)
+    and one RRE cycle of five FP calls; achieved GB/s = algorithmic bytes / average duration."""
+    npx = 2048 * 2048
+    R = Restorer(0)
+    R.configure(prob, precision="bf16", method="rre", L=5, m=0, tol=0.0, max_fp_calls=5)
+    big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device="cuda")
+    xs = torch.stack([big + 0.01 * k * k for k in range(6)]).contiguous()
+    R.extrapolate(xs)
+    R.solve(big, 2048, 2048)
+
+    def run():
+        for _ in range(5):
+            R.extrapolate(xs)
+        R.solve(big, 2048, 2048)
+
+    times = kernel_times(torch, run)
+    out = {}
+    for name, (count, us) in sorted(times.items()):
+        b = ve_bytes_per_px(name)
+        if b is None and name != "k_ve_solve":
+            continue
+        avg = us / count
+        e = {"launches": count, "avg_us": avg}
+        if b is not None:
+            gbs = npx * b / (avg * 1e-6) / 1e9
+            e.update({"bytes_per_px": b, "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS})
+        out[name] = e
+    R.close()
+    log("ve kernels 2048x2048", out)
+    return {"pixels": npx, "peak_gbs": HBM_PEAK_GBS, "kernels": out}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, calls, min_seconds):
     """The FP64 oracle (plain C, OpenMP over rows/filters) on the host: whole RRE solves
     (L = 5, the GPU's FP-call count to the target) of the same image, repeated until at least
-    `min_seconds` have passed (at most 50 solves)."""
+    `min_seconds` have passed (at most 50 solves), on all the threads OpenMP takes; then one
+    FP call of the same solve on one thread (a bounded sample, scaled to a whole solve)."""
     import oracle
     op = oracle.OracleProblem(prob)
+    threads = oracle.num_threads()
     n, t0 = 0, time.perf_counter()
     while True:
         oracle.solve(op, "rre", L=prob.L, m=0, tol=0.0, max_calls=calls)
@@ -602,10 +919,19 @@ def cpu_baseline(prob, calls, min_seconds):
         if dt >= min_seconds or n >= 50:
             break
     npx = prob.x_true.size
-    return {"value": npx * n / dt / 1e6, "unit": "MPix/s", "cores": oracle.num_threads(),
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    op.fp(op.x0())
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(threads)
+    return {"value": npx * n / dt / 1e6, "unit": "MPix/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n} whole RRE solves ({calls} FP calls each, FP64) of the same 256x256 "
-                      f"image, {dt:.1f} s"}
+                      f"image, {dt:.1f} s",
+            "one_core": {"value": npx / (dt1 * calls) / 1e6, "unit": "MPix/s", "cores": 1,
+                         "sample": f"one FP call on one thread, {dt1:.1f} s, scaled to a "
+                                   f"{calls}-call solve"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 if __name__ == "__main__":

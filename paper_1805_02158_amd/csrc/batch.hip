@@ -22,6 +22,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -77,6 +78,7 @@ struct Slot {
     int tile0 = 0, ntiles = 0;  // tile0: start in the packed tile list (set at each repack)
     LinOp op{};
     int padded = 0;        // the operator fits the radius-4 separable fast path
+    int cg32 = 0;          // ... without decimation: CG on the 32x32 tile list (r, p, d only)
     // Algorithm 3 state
     int cur = 0, base = 0, phase = 0, extra_left = 0;
     bool extra = false;
@@ -101,11 +103,13 @@ struct Engine {
     RangeAlloc px_alloc;
     int tiles_used = 0;    // tiles of the admitted images
     int launch_tiles = 0;  // length of the packed, padded tile list
+    int launch_tiles32 = 0;  // length of the 32x32 tile list (0: no image takes that form)
     void* arena = nullptr;
     float* vec[kVecs] = {};
     float* U = nullptr;
     ImgDesc* d_desc = nullptr;
     TileRef* d_tile = nullptr;
+    TileRef* d_tile32 = nullptr;  // 32x32 tiles of the cg32 images (at most cap_tiles)
     CgImg* d_cg = nullptr;
     double* d_part = nullptr;
     double* d_G = nullptr;
@@ -116,11 +120,13 @@ struct Engine {
     ImgDesc* h_desc = nullptr;  // pinned
     ImgStat* h_stat = nullptr;  // pinned
     TileRef* h_tile = nullptr;  // pinned
-    std::vector<TileRef> live;  // live tiles in partial-index order (repack scratch)
+    TileRef* h_tile32 = nullptr;  // pinned
+    std::vector<TileRef> live, live32;  // live tiles in partial-index order (repack scratch)
     bool tiles_dirty = true;
     std::vector<Slot> slots;
-    // graphs keyed by (stencil radius class, tile list length)
-    std::map<std::pair<int, int>, hipGraphExec_t> fp_graph, ve_graph;
+    // graphs keyed by (stencil radius class, tile list length, 32x32 tile list length)
+    using GraphKey = std::tuple<int, int, int>;
+    std::map<GraphKey, hipGraphExec_t> fp_graph, ve_graph;
     int part_vals = 2;
 
     float* x(int b) { return vec[b]; }
@@ -144,10 +150,12 @@ struct Engine {
         if (h_desc) hipHostFree(h_desc);
         if (h_stat) hipHostFree(h_stat);
         if (h_tile) hipHostFree(h_tile);
+        if (h_tile32) hipHostFree(h_tile32);
         arena = nullptr;
         h_desc = nullptr;
         h_stat = nullptr;
         h_tile = nullptr;
+        h_tile32 = nullptr;
     }
 
     // Allocates capacity for cap_img images, cap_px pixels, cap_tiles tiles.
@@ -173,6 +181,7 @@ struct Engine {
         const size_t o_U = take(vbytes * L);
         const size_t o_desc = take(sizeof(ImgDesc) * (cap_img + 1));
         const size_t o_tile = take(sizeof(TileRef) * cap_tiles);
+        const size_t o_tile32 = take(sizeof(TileRef) * cap_tiles);
         const size_t o_cg = take(sizeof(CgImg) * (cap_img + 1));
         const size_t o_part = take(sizeof(double) * (size_t)part_vals * cap_tiles);
         const size_t o_G = take(sizeof(double) * 256 * (cap_img + 1));
@@ -189,6 +198,7 @@ struct Engine {
         U = (float*)(b + o_U);
         d_desc = (ImgDesc*)(b + o_desc);
         d_tile = (TileRef*)(b + o_tile);
+        d_tile32 = (TileRef*)(b + o_tile32);
         d_cg = (CgImg*)(b + o_cg);
         d_part = (double*)(b + o_part);
         d_G = (double*)(b + o_G);
@@ -201,6 +211,8 @@ struct Engine {
             hipHostMalloc((void**)&h_stat, sizeof(ImgStat) * (cap_img + 1), hipHostMallocDefault) !=
                 hipSuccess ||
             hipHostMalloc((void**)&h_tile, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void**)&h_tile32, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
                 hipSuccess)
             return REDVE_E_NOMEM;
         memset(h_desc, 0, sizeof(ImgDesc) * (cap_img + 1));
@@ -266,6 +278,7 @@ struct Engine {
             for (int b = 0; b < kw; ++b) err = fmax(err, fabs(it.psf[a * kw + b] - col[a] * row[b]));
         op.separable = (amax > 0 && err <= 1e-12 * amax) ? 1 : 0;
         sl.padded = op.separable && kh <= 9 && kw <= 9;
+        sl.cg32 = sl.padded && op.decim == 1;
         if (sl.padded) {
             op.kh = op.kw = 9;
             const int oh = 4 - kh / 2, ow = 4 - kw / 2;
@@ -370,15 +383,35 @@ struct Engine {
     // 0..pos-1 (each image a contiguous range from its tile0); the list length B is a power of
     // two (at least 64, at most the capacity; both multiples of 8). Workgroup b runs on XCD
     // b mod 8; XCD x's workgroups take the x-th contiguous chunk of the live tiles, then padding.
+    // The images on the 32x32 CG form get a second list of their 32x32 tiles, built the same
+    // way (length 0 when there are none).
     int repack() {
         live.clear();
+        live32.clear();
         for (int i = 0; i < cap_img; ++i) {
             Slot& sl = slots[i];
             if (!sl.running) continue;
             sl.tile0 = (int)live.size();
             for (int t = 0; t < sl.ntiles; ++t) live.push_back(TileRef{i, t});
+            if (takes_cg32(sl)) {
+                const int n32 = tiles32_of(sl.item.hx, sl.item.wx);
+                for (int t = 0; t < n32; ++t) live32.push_back(TileRef{i, t});
+            }
         }
-        const int pos = (int)live.size();
+        launch_tiles = pack(live, h_tile);
+        launch_tiles32 = live32.empty() ? 0 : pack(live32, h_tile32);
+        if (hipMemcpyAsync(d_tile, h_tile, sizeof(TileRef) * launch_tiles, hipMemcpyHostToDevice,
+                           st) != hipSuccess ||
+            (launch_tiles32 && hipMemcpyAsync(d_tile32, h_tile32, sizeof(TileRef) * launch_tiles32,
+                                              hipMemcpyHostToDevice, st) != hipSuccess))
+            return REDVE_E_HIP;
+        return REDVE_OK;
+    }
+
+    // Dispatch order of a list of n live tiles padded to B (a power of two, at least 64, at most
+    // the capacity): returns B.
+    int pack(const std::vector<TileRef>& lv, TileRef* out) const {
+        const int pos = (int)lv.size();
         int B = 64;
         while (B < pos) B *= 2;
         B = std::min(B, cap_tiles);
@@ -386,13 +419,17 @@ struct Engine {
         for (int x = 0; x < kXcds; ++x) {
             const int start = x * q + std::min(x, r), len = q + (x < r ? 1 : 0);
             for (int i = 0; i < nb; ++i)
-                h_tile[x + kXcds * i] = i < len ? live[start + i] : TileRef{cap_img, 0};
+                out[x + kXcds * i] = i < len ? lv[start + i] : TileRef{cap_img, 0};
         }
-        launch_tiles = B;
-        return hipMemcpyAsync(d_tile, h_tile, sizeof(TileRef) * B, hipMemcpyHostToDevice, st) ==
-                       hipSuccess
-                   ? REDVE_OK
-                   : REDVE_E_HIP;
+        return B;
+    }
+
+    static int tiles32_of(int H, int W) { return ((H + 31) / 32) * ((W + 31) / 32); }
+
+    // CG on the 32x32 tile list: a padded, undecimated operator, and at least one iteration
+    // before the last (which runs on the 16x16 list for every image)
+    bool takes_cg32(const Slot& sl) const {
+        return sl.cg32 && h->base != REDVE_BASE_SD && h->cg_iters >= 2;
     }
 
     // The BF16 form with the switch to FP32 banks (one kernel takes each image's form).
@@ -403,7 +440,7 @@ struct Engine {
 
     // The launches of one round (captured): denoiser stages, CG, differences + Gram, over the
     // first nt entries of the tile list.
-    int record_fp(int rs, int nt) {
+    int record_fp(int rs, int nt, int nt32) {
         TnrdDev d = redve_tnrd_dev(h);
         const float* s_in = nullptr;
         if (h->T > 0) {
@@ -437,6 +474,11 @@ struct Engine {
                 launch_cg_fin_batch(d_desc, cap_img, k, d_part, cap_tiles, d_cg, st);
                 launch_cg_iter_batch(d_desc, d_tile, nt, rs, k, k == n - 1 ? 1 : 0, d_cg, r(a),
                                      w(a), s(b), r(b), w(b), s(a), p(), dd(), d_part, cap_tiles, st);
+                // the cg32 images (skipped above but in the last iteration): p_{k-1} in s(a),
+                // p_k to s(b), which the next call's 16x16 kernel passes on as its s_out
+                if (nt32 > 0 && k < n - 1)
+                    launch_cg_iter32_batch(d_desc, d_tile32, nt32, k, d_cg, r(a), s(a), r(b), s(b),
+                                           dd(), d_part, cap_tiles, st);
             }
         }
         launch_diff_gram_batch(d_desc, d_tile, nt, L, U, cap_px, d_part, cap_tiles, st);
@@ -451,13 +493,13 @@ struct Engine {
         return hipGetLastError() == hipSuccess ? REDVE_OK : REDVE_E_HIP;
     }
 
-    int graph(std::map<std::pair<int, int>, hipGraphExec_t>& cache, std::pair<int, int> key,
-              bool fp) {
+    int graph(std::map<GraphKey, hipGraphExec_t>& cache, GraphKey key, bool fp) {
         if (cache.count(key)) return REDVE_OK;
         hipGraph_t g;
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return REDVE_E_HIP;
-        const int rc = fp ? record_fp(key.first, key.second) : record_ve(key.second);
+        const int rc = fp ? record_fp(std::get<0>(key), std::get<1>(key), std::get<2>(key))
+                          : record_ve(std::get<1>(key));
         if (hipStreamEndCapture(st, &g) != hipSuccess || rc) return REDVE_E_HIP;
         hipGraphExec_t ex;
         const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -500,6 +542,25 @@ struct Engine {
         }
         for (char c : seen)
             if (!c) return false;
+        // the 32x32 list: every 32x32 tile of the cg32 images exactly once, nothing else
+        if (launch_tiles32 > cap_tiles || launch_tiles32 % kXcds) return false;
+        std::fill(seen.begin(), seen.end(), 0);
+        int want32 = 0, got32 = 0;
+        for (int i = 0; i < cap_img; ++i)
+            if (slots[i].running && h_desc[i].cg32) want32 += tiles32_of(h_desc[i].H, h_desc[i].W);
+        if ((want32 > 0) != (launch_tiles32 > 0) || want32 > launch_tiles32) return false;
+        for (int b = 0; b < launch_tiles32; ++b) {
+            const TileRef e = h_tile32[b];
+            if (e.img == cap_img) continue;
+            if (e.img < 0 || e.img > cap_img || !slots[e.img].running || !h_desc[e.img].cg32 ||
+                e.t < 0 || e.t >= tiles32_of(h_desc[e.img].H, h_desc[e.img].W))
+                return false;
+            const int pi = h_desc[e.img].tile0 + e.t;  // n32 <= ntiles: inside the image's range
+            if (seen[pi]) return false;
+            seen[pi] = 1;
+            ++got32;
+        }
+        if (got32 != want32) return false;
         return !h_desc[cap_img].active;
     }
 
@@ -539,6 +600,7 @@ struct Engine {
             d.x_m = x(sl.base) + sl.off;
             d.op = sl.op;
             d.fp32_banks = sl.finish_fp32 ? 1 : 0;
+            d.cg32 = takes_cg32(sl) ? 1 : 0;
         }
         const int rs = all_padded ? 4 : 0;
         int rc;
@@ -552,7 +614,7 @@ struct Engine {
         if (hipMemcpyAsync(d_desc, h_desc, sizeof(ImgDesc) * (cap_img + 1), hipMemcpyHostToDevice,
                            st) != hipSuccess)
             return REDVE_E_HIP;
-        const std::pair<int, int> kf{rs, launch_tiles}, kv{0, launch_tiles};
+        const GraphKey kf{rs, launch_tiles, launch_tiles32}, kv{0, launch_tiles, 0};
         if ((rc = graph(fp_graph, kf, true))) return rc;
         if (hipGraphLaunch(fp_graph[kf], st) != hipSuccess) return REDVE_E_HIP;
         if (any_ve) {

@@ -69,6 +69,7 @@ struct ImgDesc {
     int wj;            // window column the difference pass of this FP call writes (-1: none)
     int do_ve;         // 1: this round completes the image's window: extrapolate
     int fp32_banks;    // 1: this image's denoiser stages take FP32 banks (BF16 form, finishing)
+    int cg32;          // 1: this image's CG iterations but the last run on the 32x32 tile list
     size_t off;        // element offset of the image in every per-image workspace array
     const float* y;    // observation (caller-owned device memory)
     const float* x_in; // this FP call's input iterate
@@ -125,6 +126,11 @@ void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
                           int last, const CgImg* cg, const float* r_in, const float* w_in,
                           const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
                           float* d, double* part, int cap, hipStream_t st);
+// The CG iterations but the last of the images with cg32 set, over the 32x32 tile list (PSF
+// padded to 9x9, no decimation): r and p double-buffered, d in place.
+void launch_cg_iter32_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int k,
+                            const CgImg* cg, const float* r_in, const float* p_in, float* r_out,
+                            float* p_out, float* d, double* part, int cap, hipStream_t st);
 // Batched VE (see ve.hip).
 void launch_diff_gram_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int L, float* U,
                             size_t ustride, double* part, int cap, hipStream_t st);

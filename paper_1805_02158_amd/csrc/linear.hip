@@ -9,6 +9,7 @@
 // 2 kh kw). Reducing kernels loop over tiles with at most kMaxRedBlocks workgroups, publish
 // one FP64 partial per workgroup, and the next kernel re-sums them (see reduce.h).
 #include <algorithm>
+#include <atomic>
 
 #include "internal.h"
 #include "reduce.h"
@@ -830,29 +831,244 @@ __global__ __launch_bounds__(NTH) void k_cg_iter(
 // ---- CG iteration on 32x32 tiles keeping only r, p and d in HBM (large images) ------------
 //
 // The single-reduction iteration above stores w = A r and s = A p beside r, p, d (40 B per pixel
-// and iteration). Here they are recomputed instead: with r_k and p_{k-1} read on the tile + 2R
-// halo (R = 2 RS, the radius of A = B^T B / sigma^2 + lambda I),
-//   p_k = r_k + beta p_{k-1}                on the tile + 2R,
-//   s_k = A p_k,  r_{k+1} = r_k - alpha s_k  on the tile + R,
-//   w_{k+1} = A r_{k+1}                      on the tile,
-//   d_{k+1} = d_k + alpha p_k,  rho_{k+1} = r.r,  mu_{k+1} = w.r   at the tile's pixels,
+// and iteration). Here s is recomputed instead, and w is not formed at all: mu = r.A r =
+// ||B^T r||^2 / sigma^2 + lambda ||r||^2 for A = B^T B / sigma^2 + lambda I, and with the
+// periodic boundary B is circulant, hence normal (B^T B = B B^T), so ||B^T r|| = ||B r||.
+// With r_k and p_{k-1} read on the tile + 3 RS halo (2 RS: the radius of A; RS: that of B),
+//   p_k = r_k + beta p_{k-1}                  on the tile + 3 RS   (P region)
+//   s_k = A p_k,  r_{k+1} = r_k - alpha s_k    on the tile + RS     (S region)
+//   q = B^T r_{k+1} (the PSF's correlation)   at the tile's pixels
+//   d_{k+1} = d_k + alpha p_k,  rho_{k+1} = r.r,  mu_{k+1} = q.q / sigma^2 + lambda rho
 // storing r_{k+1}, p_k (double-buffered: neighbours read p_{k-1} on their halos) and d_{k+1}:
-// 24 B per pixel and iteration, the algorithm's own traffic, for two applications of A on
-// regions 2.25x and 1x the tile. The scalars alpha_k, beta_k come from rho_k, mu_k as in
-// k_cg_iter, so the iterates are those of the single-reduction form in exact arithmetic.
+// 24 B per pixel and iteration, the algorithm's own traffic, for one application of A on a
+// region 1.56x (RS = 4) the tile and one of B on the tile. The scalars alpha_k, beta_k come from
+// rho_k, mu_k as in k_cg_iter, so the iterates are those of the single-reduction form in exact
+// arithmetic. Region sides are rounded up to multiples of 4 (16-byte LDS rows; the extra rows
+// and columns are halo that no output uses).
 constexpr int T32 = 32;
 constexpr int kCg32Threads = 512;
 
 template <int RS>
 struct __align__(16) Cg32Smem {
-    static constexpr int R = 2 * RS;        // radius of A
-    static constexpr int PS = T32 + 4 * R;  // side of the P region (tile + 2R halo)
-    static constexpr int SS = T32 + 2 * R;  // side of the S region (tile + R halo)
-    float r[PS * PS];    // r_k on the P region, then the second row pass
-    float p[PS * PS];    // p_k on the P region
-    float h[PS * SS];    // the first row pass, then r_{k+1} on the S region
-    float s[SS * SS];    // s_k = A p_k on the S region, then w_{k+1} on the tile
+    static constexpr int PR = (T32 + 6 * RS + 3) / 4 * 4;  // P region side (origin tile - 3 RS)
+    static constexpr int SR = (T32 + 2 * RS + 3) / 4 * 4;  // S region side (origin tile - RS)
+    static_assert(PR >= SR + 4 * RS, "the S region's A reads stay in the P region");
+    static_assert(SR >= T32 + 2 * RS + 0, "the tile's B reads stay in the S region");
+    float p[PR * PR];  // p_k on the P region
+    float r[SR * SR];  // r_k, then r_{k+1}, on the S region
+    float h[PR * SR];  // A's row pass over the P rows at the S columns, then B's over the S rows
 };
+
+// A's row pass over the P rows at the S columns (the autocorrelation of the PSF's row factor),
+// into h with stride SR: four outputs per item from one window of 4 RS + 4 values read as
+// 16-byte words. The item loop stays rolled: an unrolled pair of items doubles the live window.
+template <int RS, int NT>
+__device__ inline void cg32_a_rows(const LinOp& op, Cg32Smem<RS>& sm) {
+    using M = Cg32Smem<RS>;
+    constexpr int SR = M::SR, PR = M::PR, KA = 4 * RS + 1, NWIN = KA + 3;
+    static_assert(NWIN % 4 == 0, "whole 16-byte words");
+    constexpr int NQ = SR / 4;
+#pragma unroll 1
+    for (int e = threadIdx.x; e < PR * NQ; e += NT) {
+        const int r = e / NQ, c = (e % NQ) * 4;
+        const float4* x4 = reinterpret_cast<const float4*>(sm.p + r * PR + c);
+        float x[NWIN];
+#pragma unroll
+        for (int i = 0; i < NWIN / 4; ++i) {
+            const float4 v = x4[i];
+            x[4 * i] = v.x;
+            x[4 * i + 1] = v.y;
+            x[4 * i + 2] = v.z;
+            x[4 * i + 3] = v.w;
+        }
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < KA; ++j) {
+            o0 += op.acr[j] * x[j];
+            o1 += op.acr[j] * x[j + 1];
+            o2 += op.acr[j] * x[j + 2];
+            o3 += op.acr[j] * x[j + 3];
+        }
+        *reinterpret_cast<float4*>(sm.h + r * SR + c) = make_float4(o0, o1, o2, o3);
+    }
+}
+
+// r_{k+1} = r_k - alpha (A p)_k on the S region, in place in sm.r: the column pass of A from
+// its row pass h (stride SR, PR rows), four outputs down a column per item.
+template <int RS, int NT>
+__device__ inline void cg32_update_r(const LinOp& op, Cg32Smem<RS>& sm, float alpha) {
+    using M = Cg32Smem<RS>;
+    constexpr int SR = M::SR, PR = M::PR, KA = 4 * RS + 1, NWIN = KA + 3;
+#pragma unroll 1
+    for (int e = threadIdx.x; e < (SR / 4) * SR; e += NT) {
+        const int r = (e / SR) * 4, c = e % SR;
+        const float* hc = sm.h + r * SR + c;
+        float x[NWIN];
+#pragma unroll
+        for (int i = 0; i < NWIN; ++i) x[i] = hc[i * SR];
+        float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < KA; ++i)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[k] += op.acc[i] * x[i + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float sv =
+                op.inv_s2 * o[k] + op.lambda * sm.p[(r + k + 2 * RS) * PR + c + 2 * RS];
+            float& rv = sm.r[(r + k) * SR + c];
+            rv = rv - alpha * sv;
+        }
+    }
+}
+
+// B^T's row pass over the S rows at the tile's columns (the PSF's row factor, correlation
+// form), into h with stride T32: four outputs per item from three 16-byte LDS reads.
+template <int RS, int NT>
+__device__ inline void cg32_b_rows(const LinOp& op, Cg32Smem<RS>& sm) {
+    using M = Cg32Smem<RS>;
+    constexpr int SR = M::SR, KB = 2 * RS + 1, NWIN = (KB + 3 + 3) / 4 * 4;
+    static_assert(T32 - 4 + NWIN <= SR, "the window stays in the S row");
+#pragma unroll 1
+    for (int e = threadIdx.x; e < SR * (T32 / 4); e += NT) {
+        const int r = e / (T32 / 4), c = (e % (T32 / 4)) * 4;
+        const float4* x4 = reinterpret_cast<const float4*>(sm.r + r * SR + c);
+        float x[NWIN];
+#pragma unroll
+        for (int i = 0; i < NWIN / 4; ++i) {
+            const float4 v = x4[i];
+            x[4 * i] = v.x;
+            x[4 * i + 1] = v.y;
+            x[4 * i + 2] = v.z;
+            x[4 * i + 3] = v.w;
+        }
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+            o0 += op.row[j] * x[j];
+            o1 += op.row[j] * x[j + 1];
+            o2 += op.row[j] * x[j + 2];
+            o3 += op.row[j] * x[j + 3];
+        }
+        *reinterpret_cast<float4*>(sm.h + r * T32 + c) = make_float4(o0, o1, o2, o3);
+    }
+}
+
+// The per-tile steps, shared by the single-image kernel (a loop over tiles with the next tile's
+// loads in flight) and the batched one (one tile per workgroup). The loader: thread t <
+// LR * PR takes column t % PR of rows t / PR + LR i of the P region.
+template <int RS>
+struct Cg32Geo {
+    static constexpr int NT = kCg32Threads, PR = Cg32Smem<RS>::PR, SR = Cg32Smem<RS>::SR;
+    static constexpr int LR = NT / PR, NL = (PR + LR - 1) / LR;
+    static constexpr int NOUT = T32 * T32 / NT;  // tile pixels per thread
+};
+
+// r_k and p_{k-1} of the tile at (r0, c0) on its P region into the loader's registers (zeros
+// for the threads that load nothing; p only for k > 0). Indexes wrap periodically.
+template <int RS>
+__device__ inline void cg32_fetch(int H, int W, int r0, int c0, int k, const float* r_in,
+                                  const float* p_in, float (&fr)[Cg32Geo<RS>::NL],
+                                  float (&fp)[Cg32Geo<RS>::NL]) {
+    using G = Cg32Geo<RS>;
+    constexpr int PR = G::PR, LR = G::LR, NL = G::NL;
+    const int lcol = threadIdx.x % PR, lrow = threadIdx.x / PR;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) fr[i] = fp[i] = 0.f;
+    if (lrow >= LR) return;
+    const int pr0 = r0 - 3 * RS, pc0 = c0 - 3 * RS;
+    if (pr0 >= 0 && pc0 >= 0 && pr0 + PR <= H && pc0 + PR <= W) {
+        // the region lies inside the image (every tile but those at the border)
+        const float* rb = r_in + ((size_t)(pr0 + lrow) * W + pc0 + lcol);
+        const float* pb = p_in + ((size_t)(pr0 + lrow) * W + pc0 + lcol);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            if (lrow + LR * i < PR) {
+                fr[i] = rb[(size_t)LR * i * W];
+                if (k) fp[i] = pb[(size_t)LR * i * W];
+            }
+        }
+    } else {
+        const int gc = wrapi(pc0 + lcol, W);
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            if (lrow + LR * i < PR) {
+                const size_t g = (size_t)wrapi(pr0 + lrow + LR * i, H) * W + gc;
+                fr[i] = r_in[g];
+                if (k) fp[i] = p_in[g];
+            }
+        }
+    }
+}
+
+// p_k = r_k + beta p_{k-1} into the P region, r_k into the S region (from the loader's
+// registers); the caller synchronizes.
+template <int RS>
+__device__ inline void cg32_stage(int k, float beta, const float (&fr)[Cg32Geo<RS>::NL],
+                                  const float (&fp)[Cg32Geo<RS>::NL], Cg32Smem<RS>& sm) {
+    using G = Cg32Geo<RS>;
+    constexpr int PR = G::PR, SR = G::SR, LR = G::LR, NL = G::NL;
+    const int lcol = threadIdx.x % PR, lrow = threadIdx.x / PR;
+    if (lrow >= LR) return;
+    const int scol = lcol - 2 * RS;
+    const bool scol_in = (unsigned)scol < (unsigned)SR;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int row = lrow + LR * i;
+        if (row < PR) {
+            sm.p[row * PR + lcol] = k ? fr[i] + beta * fp[i] : fr[i];
+            const int srow = row - 2 * RS;
+            if (scol_in && (unsigned)srow < (unsigned)SR) sm.r[srow * SR + scol] = fr[i];
+        }
+    }
+}
+
+// d_k at the thread's pixels of the tile (0 for k = 0 and outside the image).
+template <int RS>
+__device__ inline void cg32_load_d(int H, int W, int r0, int c0, int k, const float* d,
+                                   float (&dk)[Cg32Geo<RS>::NOUT]) {
+#pragma unroll
+    for (int o = 0; o < Cg32Geo<RS>::NOUT; ++o) {
+        const int idx = threadIdx.x + o * kCg32Threads, gr = r0 + idx / T32, gc = c0 + idx % T32;
+        dk[o] = k && gr < H && gc < W ? d[(size_t)gr * W + gc] : 0.f;
+    }
+}
+
+// With p_k and r_k staged: r_{k+1} = r_k - alpha A p_k on the S region, q = B^T r_{k+1} at the
+// tile, then the stores of r_{k+1}, p_k, d_{k+1} and the sums r.r and q.q. Leaves the
+// workgroup synchronized (LDS free for the next tile).
+template <int RS>
+__device__ inline void cg32_finish(const LinOp& op, int H, int W, int r0, int c0, int k,
+                                   float alpha, Cg32Smem<RS>& sm,
+                                   const float (&dk)[Cg32Geo<RS>::NOUT], float* r_out,
+                                   float* p_out, float* d, double (&acc)[2]) {
+    using G = Cg32Geo<RS>;
+    constexpr int NT = G::NT, PR = G::PR, SR = G::SR, KB = 2 * RS + 1;
+    cg32_a_rows<RS, NT>(op, sm);
+    __syncthreads();
+    cg32_update_r<RS, NT>(op, sm, alpha);  // r_{k+1} on the S region
+    __syncthreads();
+    cg32_b_rows<RS, NT>(op, sm);
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < G::NOUT; ++o) {
+        const int idx = threadIdx.x + o * NT, tr = idx / T32, tc = idx % T32;
+        const int gr = r0 + tr, gc = c0 + tc;
+        float q = 0.f;  // B^T r_{k+1}: the column pass at this pixel
+#pragma unroll
+        for (int i = 0; i < KB; ++i) q += op.col[i] * sm.h[(tr + i) * T32 + tc];
+        if (gr < H && gc < W) {
+            const size_t g = (size_t)gr * W + gc;
+            const float rv = sm.r[(tr + RS) * SR + tc + RS];
+            const float pv = sm.p[(tr + 3 * RS) * PR + tc + 3 * RS];
+            r_out[g] = rv;
+            p_out[g] = pv;
+            d[g] = k ? dk[o] + alpha * pv : alpha * pv;
+            acc[0] += (double)rv * (double)rv;
+            acc[1] += (double)q * (double)q;
+        }
+    }
+    __syncthreads();
+}
 
 template <int RS>
 __global__ __launch_bounds__(kCg32Threads) void k_cg_iter32(
@@ -860,39 +1076,24 @@ __global__ __launch_bounds__(kCg32Threads) void k_cg_iter32(
     const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ p_out,
     float* __restrict__ d, Partials rm, const double* __restrict__ hist_prev,
     double* __restrict__ hist_cur, double* __restrict__ part) {
-    using M = Cg32Smem<RS>;
-    constexpr int NT = kCg32Threads, R = M::R, PS = M::PS, SS = M::SS;
-    constexpr int NE = (PS * PS + NT - 1) / NT;  // P-region values per thread
-    constexpr int NOUT = T32 * T32 / NT;         // tile pixels per thread
-    __shared__ M sm;
+    using G = Cg32Geo<RS>;
+    constexpr int NT = G::NT;
+    __shared__ Cg32Smem<RS> sm;
     __shared__ double sred[2 * NT / 64];
     __shared__ double bc[2];
     const int ntx = (W + T32 - 1) / T32, nt = ntx * ((H + T32 - 1) / T32);
-    // the published partials and the previous step lengths first, then the first tile's
-    // inputs, so that these loads overlap the reduction
+    // the published partials and the previous step lengths first
     Early2 early;
     const bool early_ok = rm.n <= kEarlyPartials;
     if (early_ok) consume2_issue(rm.p, kMaxRedBlocks, rm.n, early);
     const double alpha_prev = k ? hist_prev[0] : 0.0, rho_prev = k ? hist_prev[1] : 0.0;
-    float fr[NE], fp[NE];
+    float fr[G::NL], fp[G::NL];
     int r0 = 0, c0 = 0;
-    auto fetch = [&](int t) {
+    auto origin = [&](int t) {
         const int tt = xcd_tile(t, nt);
         r0 = (tt / ntx) * T32;
         c0 = (tt % ntx) * T32;
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-            const int e = threadIdx.x + i * NT;
-            fr[i] = fp[i] = 0.f;
-            if (e < PS * PS) {
-                const size_t g =
-                    (size_t)wrapi(r0 - 2 * R + e / PS, H) * W + wrapi(c0 - 2 * R + e % PS, W);
-                fr[i] = r_in[g];
-                if (k) fp[i] = p_in[g];
-            }
-        }
     };
-    if ((int)blockIdx.x < nt) fetch(blockIdx.x);
     double rho, mu;
     if (early_ok)
         consume2_finish(early, bc, rho, mu);
@@ -905,58 +1106,54 @@ __global__ __launch_bounds__(kCg32Threads) void k_cg_iter32(
         hist_cur[1] = rho;
     }
     const float alpha = (float)alpha_d, beta = (float)beta_d;
-    double acc[2] = {0.0, 0.0};
+    double acc[2] = {0.0, 0.0};  // r.r, (B^T r).(B^T r)
+    // one tile at a time: three workgroups per CU overlap one another's loads and passes (a
+    // prefetch of the next tile into registers cost the registers of the third workgroup)
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-        const int tr0 = r0, tc0 = c0;  // this tile (fetch below moves r0, c0 to the next)
-        float dk[NOUT];
-#pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-            const int idx = threadIdx.x + o * NT, gr = tr0 + idx / T32, gc = tc0 + idx % T32;
-            dk[o] = k && gr < H && gc < W ? d[(size_t)gr * W + gc] : 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < NE; ++i) {
-            const int e = threadIdx.x + i * NT;
-            if (e < PS * PS) {
-                sm.r[e] = fr[i];
-                sm.p[e] = k ? fr[i] + beta * fp[i] : fr[i];
-            }
-        }
+        origin(t);
+        float dk[G::NOUT];
+        cg32_fetch<RS>(H, W, r0, c0, k, r_in, p_in, fr, fp);
+        cg32_load_d<RS>(H, W, r0, c0, k, d, dk);
+        cg32_stage<RS>(k, beta, fr, fp, sm);
         __syncthreads();
-        // the next tile's loads are in flight while this one computes
-        if (t + (int)gridDim.x < nt) fetch(t + gridDim.x);
-        ac_rows<RS, NT>(op, sm.p, PS, PS, SS, sm.h);
-        __syncthreads();
-        ac_cols<RS, NT>(op, sm.h, sm.p, PS, SS, SS, sm.s);  // s_k = A p_k
-        __syncthreads();
-        float* rn = sm.h;  // r_{k+1} on the S region
-        for (int e = threadIdx.x; e < SS * SS; e += NT)
-            rn[e] = sm.r[(e / SS + R) * PS + e % SS + R] - alpha * sm.s[e];
-        __syncthreads();
-        ac_rows<RS, NT>(op, rn, SS, SS, T32, sm.r);
-        __syncthreads();
-        ac_cols<RS, NT>(op, sm.r, rn, SS, T32, T32, sm.s);  // w_{k+1} = A r_{k+1}
-        __syncthreads();
-#pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-            const int idx = threadIdx.x + o * NT, tr = idx / T32, tc = idx % T32;
-            const int gr = tr0 + tr, gc = tc0 + tc;
-            if (gr < H && gc < W) {
-                const size_t g = (size_t)gr * W + gc;
-                const float rv = rn[(tr + R) * SS + tc + R];
-                const float wv = sm.s[tr * T32 + tc];
-                const float pv = sm.p[(tr + 2 * R) * PS + tc + 2 * R];
-                r_out[g] = rv;
-                p_out[g] = pv;
-                d[g] = k ? dk[o] + alpha * pv : alpha * pv;
-                acc[0] += (double)rv * (double)rv;
-                acc[1] += (double)wv * (double)rv;
-            }
-        }
-        __syncthreads();
+        cg32_finish<RS>(op, H, W, r0, c0, k, alpha, sm, dk, r_out, p_out, d, acc);
     }
     block_sum<2, NT>(acc, sred);
+    // mu's partial: ||B^T r||^2 / sigma^2 + lambda ||r||^2 over this workgroup's pixels
+    acc[1] = op.inv_s2_d * acc[1] + op.lambda_d * acc[0];
     publish<2>(acc, part, kMaxRedBlocks, blockIdx.x);
+}
+
+// Batched form: one workgroup per entry of the 32x32 tile list (image, tile t of ceil(W/32)
+// per row); images whose 32x32 tiles are in the list have cg32 set. The tile's sums go to
+// partial index tile0 + t of its image (one per 32x32 tile), summed by k_cg_fin_batch.
+template <int RS>
+__global__ __launch_bounds__(kCg32Threads) void k_cg_iter32_batch(
+    const ImgDesc* __restrict__ desc, const TileRef* __restrict__ tiles, int k,
+    const CgImg* __restrict__ cg, const float* __restrict__ r_in, const float* __restrict__ p_in,
+    float* __restrict__ r_out, float* __restrict__ p_out, float* __restrict__ dd,
+    double* __restrict__ part, int cap) {
+    using G = Cg32Geo<RS>;
+    __shared__ Cg32Smem<RS> sm;
+    __shared__ double sred[2 * G::NT / 64];
+    const TileRef e = tiles[blockIdx.x];
+    const ImgDesc* d = desc + e.img;
+    if (!d->active || !d->cg32) return;
+    const int H = d->H, W = d->W, ntx = (W + T32 - 1) / T32;
+    const int r0 = (e.t / ntx) * T32, c0 = (e.t % ntx) * T32;
+    const size_t o = d->off;
+    float fr[G::NL], fp[G::NL], dk[G::NOUT];
+    cg32_fetch<RS>(H, W, r0, c0, k, r_in + o, p_in + o, fr, fp);
+    cg32_load_d<RS>(H, W, r0, c0, k, dd + o, dk);
+    const CgImg c = cg[e.img];
+    cg32_stage<RS>(k, (float)c.beta, fr, fp, sm);
+    __syncthreads();
+    double acc[2] = {0.0, 0.0};
+    cg32_finish<RS>(d->op, H, W, r0, c0, k, (float)c.alpha, sm, dk, r_out + o, p_out + o,
+                    dd + o, acc);
+    block_sum<2, G::NT>(acc, sred);
+    acc[1] = d->op.inv_s2_d * acc[1] + d->op.lambda_d * acc[0];
+    publish<2>(acc, part, cap, d->tile0 + e.t);
 }
 
 // The last CG iteration of an FP call and the difference pass of vector extrapolation
@@ -1117,7 +1314,9 @@ __global__ __launch_bounds__(512) void k_cg_fin_batch(const ImgDesc* __restrict_
     if (!d.active) return;
     const int v = threadIdx.x >> 8, tid = threadIdx.x & 255;
     const double* pv = part + (size_t)v * cap + d.tile0;
-    const int n = d.ntiles;
+    // partials of the previous kernel: one per 16x16 tile, or per 32x32 tile after an
+    // iteration of the 32x32 form (every iteration but the first: k_cg_w0_batch runs on 16x16)
+    const int n = d.cg32 && k > 0 ? ((d.H + T32 - 1) / T32) * ((d.W + T32 - 1) / T32) : d.ntiles;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int i = tid;
     for (; i + 768 < n; i += 1024) {
@@ -1158,11 +1357,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter_batch(
     if (!d) return;
     const size_t o = d->off;
     if (last) {
+        // p_{k-1}: the 32x32 form keeps it double-buffered in the s arrays (this call's s_out)
         const CgImg c = cg[d - desc];
-        cg_last_tile(d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, r_in + o, p + o,
-                     dd + o, d->x_in, d->x_out);
+        cg_last_tile(d->H, d->W, r0, c0, k, (float)c.alpha, (float)c.beta, r_in + o,
+                     (d->cg32 ? s_out : p) + o, dd + o, d->x_in, d->x_out);
         return;
     }
+    if (d->cg32) return;  // the 32x32 tile list takes this image's iteration
     double acc[2] = {0.0, 0.0};
     if constexpr (RS > 0) {
         // the workgroup sum first, then every store of the tile at once
@@ -1678,11 +1879,47 @@ bool cg_iter32_ok(const LinOp& op, int iters, int H, int W) {
     const bool eligible = op.decim == 1 && op.separable && op.kh == op.kw &&
                           (op.kh == 7 || op.kh == 9) && iters >= 2;
     if (!eligible) return false;
-    const int nt16 = ntiles_host(H, W);
-    // rule (measured at 512^2 to 4096^2): the 32x32 form up to 4095 16x16 tiles (1024 x 1024)
-    // and from 32768 (about 2900 x 2900); the 16x16 form between
-    return op.cg_tile ? op.cg_tile == 32
-                      : nt16 >= kWideBelowTiles && (nt16 < 4096 || nt16 >= 32768);
+    // rule (measured at 512^2 to 4096^2): the 32x32 form from 512 16x16 tiles (two per CU);
+    // below, the two-iteration kernel
+    return op.cg_tile ? op.cg_tile == 32 : ntiles_host(H, W) >= kWideBelowTiles;
+}
+
+// Workgroups of the 32x32 kernel: as many as the device holds at once (CUs x resident
+// workgroups per CU, at most kMaxRedBlocks), so that every workgroup runs from the start and
+// takes an equal run of tiles; a grid beyond that leaves a second, partial wave of workgroups.
+// The count is rounded down to a multiple of the XCD count, so that a workgroup's successive
+// tiles stay on its XCD's contiguous run (xcd_tile).
+template <int RS>
+static int cg32_resident(int device) {
+    static std::atomic<int> cache[64];
+    if (device < 0 || device >= 64) return kMaxRedBlocks;
+    const int known = cache[device].load(std::memory_order_relaxed);
+    if (known > 0) return known;
+    int cus = 0, per_cu = 0, lds_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_iter32<RS>, kCg32Threads, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+        return kMaxRedBlocks;
+    // the register and LDS limits of the kernel itself, where they allow more than the
+    // occupancy query reports (a grid that matches what runs together was 1.2-1.3x faster at
+    // 2048^2 than one of 1024)
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_cg_iter32<RS>)) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              device) == hipSuccess &&
+        fa.numRegs > 0 && fa.sharedSizeBytes > 0 && lds_cu > 0) {
+        constexpr int kWavesPerSimd = 8, kVgprsPerLane = 512, kSimds = 4;
+        const int regs = (fa.numRegs + 7) / 8 * 8;
+        const int wg_waves_per_simd = (kCg32Threads / 64 + kSimds - 1) / kSimds;
+        const int by_regs = std::min(kWavesPerSimd, kVgprsPerLane / regs) / wg_waves_per_simd;
+        const int by_lds = lds_cu / (int)fa.sharedSizeBytes;
+        per_cu = std::max(per_cu, std::min(by_regs, by_lds));
+    }
+    int g = std::min(kMaxRedBlocks, cus * per_cu);
+    if (g >= kXcds) g -= g % kXcds;
+    cache[device].store(g, std::memory_order_relaxed);
+    return g;
 }
 
 Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_in,
@@ -1690,7 +1927,10 @@ Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_i
                           const double* hist_prev, double* hist_cur, double* part,
                           hipStream_t st) {
     const int nt = ((H + T32 - 1) / T32) * ((W + T32 - 1) / T32);
-    const int g = nt < kMaxRedBlocks ? nt : kMaxRedBlocks;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) device = -1;
+    const int cap = op.kh == 9 ? cg32_resident<4>(device) : cg32_resident<3>(device);
+    const int g = nt < cap ? nt : cap;
     if (op.kh == 9)
         k_cg_iter32<4><<<g, kCg32Threads, 0, st>>>(op, H, W, k, r_in, p_in, r_out, p_out, d, rm,
                                                    hist_prev, hist_cur, part);
@@ -1698,6 +1938,13 @@ Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_i
         k_cg_iter32<3><<<g, kCg32Threads, 0, st>>>(op, H, W, k, r_in, p_in, r_out, p_out, d, rm,
                                                    hist_prev, hist_cur, part);
     return Partials{part, g};
+}
+
+void launch_cg_iter32_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int k,
+                            const CgImg* cg, const float* r_in, const float* p_in, float* r_out,
+                            float* p_out, float* d, double* part, int cap, hipStream_t st) {
+    k_cg_iter32_batch<4><<<ntiles, kCg32Threads, 0, st>>>(desc, tiles, k, cg, r_in, p_in, r_out,
+                                                          p_out, d, part, cap);
 }
 
 int launch_cg_last_diff(int n, int k, const float* r_in, const float* p, const float* d,

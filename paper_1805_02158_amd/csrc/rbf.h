@@ -6,12 +6,17 @@
 // spacings add less than eps of a weight: eps = 1e-12 in the FP32 form (K = 7 for gamma = dmu),
 // 1e-6 in the BF16 form (K = 5), whose operands carry 3.9e-3 relative error.
 //
-// Inside the centre range (|d0| <= dmu / 2): phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w_{j0+m-K} A^m
-// by Horner in A, c_k = B^(k^2) precomputed, the prefactor one exp2 (two exp2 and 2K FMA +
-// 2K+1 multiplies per evaluation). Every intermediate stays below 2^(K c dmu^2) there. Outside
-// (z beyond the first or last centre) A^2K could overflow, so the terms are built by the
-// two-sided recurrence term(k+1) = term(k) R_k, R_{k+1} = R_k B^2, which stays bounded; past
-// the cut-off (K + 1/2) dmu every term is negligible and the result is 0.
+// Compile-time window (K fixed): phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w_{j0+m-K} A^m by Horner
+// in A, c_k = B^(k^2) precomputed, the prefactor one exp2 (two exp2 and 2K FMA + 2K+1
+// multiplies per evaluation), with no branch: j0 is clamped to -K .. J-1+K, where the window's
+// weights lie in the row's zero padding, and d0 to [-dmu, dmu]. Inside that range the sum is
+// the window's exactly (j0 is the nearest centre up to rounding at a midpoint, where the window
+// then misses a term beyond (K + 1/2) dmu); the d0 clamp binds only for z more than K + 1
+// spacings beyond the first or last centre, where every term is below eps of a weight. With
+// |d0| <= dmu every intermediate stays below 2^(4 K c dmu^2), far inside FP32 for the
+// gamma / dmu the compile-time windows serve. Runtime K: the two-sided recurrence
+// term(k+1) = term(k) R_k, R_{k+1} = R_k B^2, which stays bounded for any z; past the cut-off
+// (K + 1/2) dmu every term is negligible and the result is 0.
 //
 // Tabulated form (BF16 stage): phi is read from a per-filter table of the cubic Hermite
 // interpolant of the exact sum (all J terms, built in FP64 from phi and phi' at knots spaced
@@ -28,6 +33,8 @@ namespace redve {
 
 struct RbfParams {
     float mu0, dmu, inv_dmu, half_dmu;
+    float t0;      // -mu0 / dmu: (z - mu0) / dmu = z inv_dmu + t0
+    float jlast;   // J - 1
     float c;       // log2(e) / (2 gamma^2)
     float two_cd;  // 2 c dmu
     float kpre;    // K 2 c dmu: the A^-K factor of the prefactor
@@ -46,6 +53,8 @@ inline RbfParams rbf_params(const TnrdDev& d) {
     p.dmu = d.dmu;
     p.inv_dmu = 1.0f / d.dmu;
     p.half_dmu = 0.5f * d.dmu;
+    p.t0 = (float)(-(double)d.mu0 / (double)d.dmu);
+    p.jlast = (float)(d.nrbf - 1);
     const double c = 1.4426950408889634 / (2.0 * (double)d.gamma * d.gamma);
     const double cd2 = c * (double)d.dmu * d.dmu;
     p.c = (float)c;
@@ -81,18 +90,21 @@ __device__ inline float phi_table(float z, const float* tab, const RbfParams& p)
 // recurrence only.
 template <int KC>
 __device__ inline float phi_eval(float z, const float* wrow, const RbfParams& p) {
-    // nearest centre, clamped in floating point before the conversion, so that any z (NaN and
-    // infinities included) reads inside the padded weight row
-    const int j0 = (int)fminf(fmaxf(rintf((z - p.mu0) * p.inv_dmu), 0.f), (float)(p.J - 1));
-    const float d0r = z - (p.mu0 + p.dmu * (float)j0);
-    const float* wc = wrow + kRbfPad + j0;
-    if (KC > 0 && fabsf(d0r) <= p.half_dmu) {
+    if constexpr (KC > 0) {
+        static_assert(2 * KC <= kRbfPad, "the clamped window stays inside the padded row");
+        // nearest centre, clamped in floating point before the conversion, so that any z (NaN
+        // and infinities included) reads inside the padded weight row
+        const float jf =
+            fminf(fmaxf(rintf(fmaf(z, p.inv_dmu, p.t0)), (float)-KC), p.jlast + (float)KC);
+        const int j0 = (int)jf;
+        const float d0 = fminf(fmaxf(z - fmaf(p.dmu, jf, p.mu0), -p.dmu), p.dmu);
+        const float* wc = wrow + kRbfPad + j0;
         // the 2K+1 weights first, so their reads are in flight together ahead of the chain
-        float wv[2 * (KC > 0 ? KC : 1) + 1];
+        float wv[2 * KC + 1];
 #pragma unroll
         for (int m = 0; m <= 2 * KC; ++m) wv[m] = wc[m - KC];
-        const float a = __builtin_amdgcn_exp2f(p.two_cd * d0r);
-        const float pre = __builtin_amdgcn_exp2f(-(p.c * d0r + p.kpre) * d0r);
+        const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
+        const float pre = __builtin_amdgcn_exp2f(-(p.c * d0 + p.kpre) * d0);
         float poly = p.ck[KC] * wv[2 * KC];
 #pragma unroll
         for (int m = 2 * KC - 1; m >= 0; --m) {
@@ -100,25 +112,29 @@ __device__ inline float phi_eval(float z, const float* wrow, const RbfParams& p)
             poly = fmaf(poly, a, p.ck[k < 0 ? -k : k] * wv[m]);
         }
         return pre * poly;
-    }
-    const int K = KC > 0 ? KC : p.K;
-    const bool live = fabsf(d0r) <= p.cutoff;
-    const float d0 = live ? d0r : 0.f;
-    const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
-    const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
-    const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
-    float acc = wc[0] * g0;
-    float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
+    } else {
+        const int j0 = (int)fminf(fmaxf(rintf((z - p.mu0) * p.inv_dmu), 0.f), p.jlast);
+        const float d0r = z - (p.mu0 + p.dmu * (float)j0);
+        const float* wc = wrow + kRbfPad + j0;
+        const int K = p.K;
+        const bool live = fabsf(d0r) <= p.cutoff;
+        const float d0 = live ? d0r : 0.f;
+        const float g0 = live ? __builtin_amdgcn_exp2f(-p.c * d0 * d0) : 0.f;
+        const float a = __builtin_amdgcn_exp2f(p.two_cd * d0);
+        const float ai = __builtin_amdgcn_exp2f(-p.two_cd * d0);
+        float acc = wc[0] * g0;
+        float gu = g0, ru = a * p.b, gd = g0, rd = ai * p.b;
 #pragma unroll
-    for (int k = 1; k <= (KC > 0 ? KC : kMaxRbfWindow); ++k) {
-        if (KC == 0 && k > K) break;
-        gu *= ru;
-        ru *= p.b2;
-        gd *= rd;
-        rd *= p.b2;
-        acc += wc[k] * gu + wc[-k] * gd;
+        for (int k = 1; k <= kMaxRbfWindow; ++k) {
+            if (k > K) break;
+            gu *= ru;
+            ru *= p.b2;
+            gd *= rd;
+            rd *= p.b2;
+            acc += wc[k] * gu + wc[-k] * gd;
+        }
+        return acc;
     }
-    return acc;
 }
 
 }  // namespace redve

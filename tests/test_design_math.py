@@ -49,16 +49,17 @@ def test_rbf_window_recurrence_matches_full_sum(orc):
 
 
 def _window_horner(z, w, mu0, dmu, gamma, K):
-    """The denoiser kernel's evaluation for z inside the centre range (|d0| <= dmu / 2), in
-    float64: phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w[j0+m-K] A^m by Horner in A, with
-    A = exp2(2 c dmu d0), c_k = exp2(-c dmu^2 k^2) and the prefactor G0 A^-K one exp2.
-    Outside the range the recurrence above is used."""
+    """The denoiser kernel's evaluation with a compile-time window, in float64, branch-free:
+    j0 = the nearest centre clamped to -K .. J-1+K (the weight row is zero-padded by 2K), d0 =
+    z - mu_j0 clamped to [-dmu, dmu], then phi = G0 A^-K sum_{m=0}^{2K} c_|m-K| w[j0+m-K] A^m
+    by Horner in A, with A = exp2(2 c dmu d0), c_k = exp2(-c dmu^2 k^2) and the prefactor
+    G0 A^-K one exp2."""
     J = len(w)
     c = math.log2(math.e) / (2 * gamma * gamma)
-    j0 = int(np.clip(np.rint((z - mu0) / dmu), 0, J - 1))
-    d0 = z - (mu0 + dmu * j0)
-    if abs(d0) > 0.5 * dmu:
-        return _window_recurrence(z, w, mu0, dmu, gamma, K)
+    t = (z - mu0) / dmu
+    j0 = int(min(max(np.rint(t) if np.isfinite(t) else (np.inf if t > 0 else -np.inf), -K),
+                 J - 1 + K))
+    d0 = min(max(z - (mu0 + dmu * j0), -dmu), dmu)
     wp = lambda j: w[j] if 0 <= j < J else 0.0  # noqa: E731
     ck = [2.0 ** (-c * dmu * dmu * k * k) for k in range(K + 1)]
     a = 2.0 ** (2 * c * dmu * d0)
@@ -69,17 +70,25 @@ def _window_horner(z, w, mu0, dmu, gamma, K):
     return pre * poly
 
 
-def test_rbf_window_horner_matches_full_sum(orc):
-    """The Horner arrangement of the same window reproduces the 63-term sum to 1e-12 of the
-    largest weight inside the centre range, and hands over to the recurrence beyond it."""
+@pytest.mark.parametrize("K,eps", [(7, 1e-12), (5, 1e-6)])
+def test_rbf_window_horner_matches_full_sum(orc, K, eps):
+    """The branch-free Horner arrangement of the window reproduces the 63-term sum to eps of
+    the largest weight for every z: inside the centre range, past it (where the clamped j0 and
+    the zero padding take the last weights), far beyond it (where the d0 clamp binds) and at
+    infinity. K = 7 is the FP32 form's window (eps 1e-12), K = 5 the BF16 form's (1e-6)."""
     d = W.make_denoiser()
-    z = np.concatenate([np.linspace(-420, 420, 1201), [0.0, 5.0, -5.0, 4.999, 305.0, 315.0]])
-    K = 7
+    far = [1e4, -1e4, 3e38, -3e38]
+    z = np.concatenate([np.linspace(-420, 420, 1201), [0.0, 5.0, -5.0, 4.999, 305.0, 315.0],
+                        d.mu0 + d.dmu * (np.arange(-12, 75) + 0.5)])
     for t, i in [(0, 0), (1, 7), (3, 19), (4, 23)]:
         w = d.rbf_w[t, i]
         full = orc.phi(z, w, d.mu0, d.dmu, d.gamma)
         hor = np.array([_window_horner(v, w, d.mu0, d.dmu, d.gamma, K) for v in z])
-        assert np.abs(hor - full).max() <= 1e-12 * np.abs(w).max()
+        assert np.abs(hor - full).max() <= eps * np.abs(w).max()
+        tail = np.array([_window_horner(v, w, d.mu0, d.dmu, d.gamma, K) for v in far])
+        assert np.all(np.isfinite(tail)) and np.abs(tail).max() <= eps * np.abs(w).max()
+        inf = [_window_horner(v, w, d.mu0, d.dmu, d.gamma, K) for v in (np.inf, -np.inf)]
+        assert all(np.isfinite(v) and abs(v) <= eps * np.abs(w).max() for v in inf)
     # a mistake in the coefficient order (c_k paired with the wrong weight) is caught
     w = d.rbf_w[2, 5]
     bad = 0.0

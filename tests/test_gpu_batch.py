@@ -146,6 +146,59 @@ def test_batch_result_independent_of_the_batch(torch, orc):
     assert torch.equal(alone[0], rev[3])
 
 
+def deblur_problems(orc, seed=0):
+    """Deblurring only (every image on the 32x32 CG form): images smaller than one 32x32 tile
+    and than its 12-pixel halo, ragged tiles, and images with interior tiles; both blurs."""
+    sizes = [(2, 3), (8, 8), (37, 53), (96, 33), (130, 97), (300, 260)]
+    out = []
+    for i, (h, w) in enumerate(sizes):
+        psf = W.psf_gaussian(7, 1.6) if i % 2 else W.psf_uniform(9)
+        sigma = math.sqrt(2) if i % 2 == 0 else 5.0
+        prob = W.Problem(f"d{i}", W.make_image(h, w, 700 + 31 * seed + i), psf, 1, sigma, 0.02,
+                         W.make_noise((h, w), 800 + 31 * seed + i), 15, W.make_denoiser())
+        out.append((prob, f32(orc.OracleProblem(prob).y)))
+    return out
+
+
+def test_batch_cg32_fp_call(torch, orc):
+    """One batched FP call (FP32 banks) of deblurring images, whose CG iterations run on the
+    32x32 tile list, against the oracle's FP map."""
+    probs = deblur_problems(orc)
+    r = restorer("none", 5, 0.0, 1)
+    outs, stats = r.solve_batch(as_dicts(torch, probs))
+    for (prob, y32), xo, st in zip(probs, outs, stats):
+        op = orc.OracleProblem(prob, y=y32)
+        x0 = f32(op.x0())
+        xr = op.fp(x0)
+        xb = host(xo)
+        e, es = rel(xb, xr), rel(xb - x0, xr - x0)
+        say(f"  {prob.name} {prob.hr_shape}: rel L2 {e:.2e}, relative to the step {es:.2e}")
+        assert st["fp_calls"] == 1
+        assert e <= 2e-6 and es <= 2e-5
+
+
+def test_batch_cg32_solve_and_independence(torch, orc):
+    """Fixed-schedule RRE solves of the deblurring batch against the oracle, and each image's
+    result bitwise the same alone and beside images on the 16x16 form (3x SR)."""
+    probs = deblur_problems(orc, seed=1)
+    r = restorer("rre", 5, 0.0, 10)
+    outs, stats = r.solve_batch(as_dicts(torch, probs))
+    for (prob, y32), xo, st in zip(probs, outs, stats):
+        op = orc.OracleProblem(prob, y=y32)
+        ref = orc.solve(op, "rre", L=5, m=0, tol=0.0, max_calls=10)
+        e, bound = rel(host(xo), ref.x), _bound(orc, op, ref, "rre", 5, 10)
+        say(f"  {prob.name} {prob.hr_shape}: rel L2 vs oracle {e:.2e} (bound {bound:.1e})")
+        assert st["fp_calls"] == ref.calls and st["cycles"] == ref.cycles
+        assert e <= bound
+    sr = [pq for pq in mixed_problems(orc, 6) if pq[0].decim > 1]
+    mix = [probs[4]] + sr + [probs[5]]
+    alone4, _ = r.solve_batch(as_dicts(torch, probs[4:5]))
+    alone5, _ = r.solve_batch(as_dicts(torch, probs[5:6]))
+    mixed, _ = r.solve_batch(as_dicts(torch, mix))
+    assert torch.equal(alone4[0], outs[4]) and torch.equal(alone4[0], mixed[0])
+    assert torch.equal(alone5[0], outs[5]) and torch.equal(alone5[0], mixed[-1])
+
+
 def test_batch_engine_reuse(torch, orc):
     """The handle keeps the batched engine between calls: a repeated batch is bitwise the
     same; after a settings change (CG count, extrapolation method) the result is bitwise that
