@@ -589,9 +589,10 @@ def whole_solve_roofline(px_calls_per_s, prec="bf16", n_cg=15, linear="cg"):
 
 def batch_kernels(torch, run, prec, px_calls, n_cg=15):
     """Per kernel class of one batched solve (profiler device times): launches, total time,
-    share, and for the two dominant classes the achieved rate over the whole solve: the stage
+    share, and for the dominant classes the achieved rate over the whole solve: the stage
     (5 per FP call; influence-function FLOP-equivalents against the unpacked vector peak) and
-    the CG iteration (15 per FP call; 24 B per pixel and iteration against HBM)."""
+    the CG iterations (24 B per pixel and iteration against HBM; the 32x32 form takes 14 of the
+    15 per FP call, every image of this workload being on it)."""
     kt = kernel_times(torch, run)
     by = {}
     for name, (c, us) in kt.items():
@@ -608,10 +609,13 @@ def batch_kernels(torch, run, prec, px_calls, n_cg=15):
             a = 5 * px_calls * w["phi_flop_eq_px"] / t / 1e12
             out[k].update({"bound": "alu", "achieved_tflops": a, "peak": VALU_PEAK_TFLOPS,
                            "frac": a / VALU_PEAK_TFLOPS})
-        elif k == "k_cg_iter_batch":
-            a = n_cg * px_calls * CG_BYTES_PER_PX / t / 1e9
+        elif k in ("k_cg_iter_batch", "k_cg_iter32_batch"):
+            # the 32x32 form takes every iteration but the last (pointwise, on the 16x16 list)
+            # of the images on it; where it runs, the 16x16 form takes only those last ones
+            iters = n_cg - 1 if k == "k_cg_iter32_batch" else (1 if "k_cg_iter32_batch" in out else n_cg)
+            a = iters * px_calls * CG_BYTES_PER_PX / t / 1e9
             out[k].update({"bound": "hbm", "achieved_gbs": a, "peak": HBM_PEAK_GBS,
-                           "frac": a / HBM_PEAK_GBS})
+                           "frac": a / HBM_PEAK_GBS, "iterations_per_fp_call": iters})
     return out
 
 
@@ -847,13 +851,14 @@ def kernel_times(torch, fn):
 
 # Algorithmic HBM bytes per pixel of the extrapolation passes (window column j, L = 5):
 # the difference pass reads x_new and x_old and the j earlier columns and writes u (12 + 4 j);
-# the last CG iteration fused with it also reads r, p, d and x_in (another 16: 28 + 4 j); the
-# combination reads x_m and kappa columns and writes the result (4 (kappa + 2)).
+# the last CG iteration fused with it reads r, p, d and x_in (x_new is formed there, x_old is
+# x_in) and the j columns and writes x_out and u (24 + 4 j, what the counters see); the
+# combination reads x_m and the L - 1 columns of U_(kappa-1) and writes the result (4 (L + 1)).
 def ve_bytes_per_px(kernel, L=5):
     if kernel.startswith("k_diff_gram<"):
         return 12 + 4 * int(kernel[len("k_diff_gram<"):-1])
     if kernel.startswith("k_cg_last_diff<"):
-        return 28 + 4 * int(kernel[len("k_cg_last_diff<"):-1])
+        return 24 + 4 * int(kernel[len("k_cg_last_diff<"):-1])
     if kernel == "k_ve_combine":
         return 4 * (L - 1 + 2)
     return None

@@ -104,12 +104,14 @@ struct Engine {
     int tiles_used = 0;    // tiles of the admitted images
     int launch_tiles = 0;  // length of the packed, padded tile list
     int launch_tiles32 = 0;  // length of the 32x32 tile list (0: no image takes that form)
+    int launch_tiles16r = 0;  // length of the 16x16 list of the other images (0: none)
     void* arena = nullptr;
     float* vec[kVecs] = {};
     float* U = nullptr;
     ImgDesc* d_desc = nullptr;
     TileRef* d_tile = nullptr;
     TileRef* d_tile32 = nullptr;  // 32x32 tiles of the cg32 images (at most cap_tiles)
+    TileRef* d_tile16r = nullptr;  // 16x16 tiles of the images not on the 32x32 CG form
     CgImg* d_cg = nullptr;
     double* d_part = nullptr;
     double* d_G = nullptr;
@@ -120,12 +122,16 @@ struct Engine {
     ImgDesc* h_desc = nullptr;  // pinned
     ImgStat* h_stat = nullptr;  // pinned
     TileRef* h_tile = nullptr;  // pinned
-    TileRef* h_tile32 = nullptr;  // pinned
-    std::vector<TileRef> live, live32;  // live tiles in partial-index order (repack scratch)
+    TileRef* h_tile32 = nullptr;   // pinned
+    TileRef* h_tile16r = nullptr;  // pinned
+    // live tiles in partial-index order (repack scratch): all, 32x32 of the cg32 images, 16x16
+    // of the others
+    std::vector<TileRef> live, live32, live16r;
     bool tiles_dirty = true;
     std::vector<Slot> slots;
-    // graphs keyed by (stencil radius class, tile list length, 32x32 tile list length)
-    using GraphKey = std::tuple<int, int, int>;
+    // graphs keyed by (stencil radius class, lengths of the tile list, the 32x32 list and the
+    // 16x16 list of the images not on the 32x32 form)
+    using GraphKey = std::tuple<int, int, int, int>;
     std::map<GraphKey, hipGraphExec_t> fp_graph, ve_graph;
     int part_vals = 2;
 
@@ -151,11 +157,13 @@ struct Engine {
         if (h_stat) hipHostFree(h_stat);
         if (h_tile) hipHostFree(h_tile);
         if (h_tile32) hipHostFree(h_tile32);
+        if (h_tile16r) hipHostFree(h_tile16r);
         arena = nullptr;
         h_desc = nullptr;
         h_stat = nullptr;
         h_tile = nullptr;
         h_tile32 = nullptr;
+        h_tile16r = nullptr;
     }
 
     // Allocates capacity for cap_img images, cap_px pixels, cap_tiles tiles.
@@ -182,6 +190,7 @@ struct Engine {
         const size_t o_desc = take(sizeof(ImgDesc) * (cap_img + 1));
         const size_t o_tile = take(sizeof(TileRef) * cap_tiles);
         const size_t o_tile32 = take(sizeof(TileRef) * cap_tiles);
+        const size_t o_tile16r = take(sizeof(TileRef) * cap_tiles);
         const size_t o_cg = take(sizeof(CgImg) * (cap_img + 1));
         const size_t o_part = take(sizeof(double) * (size_t)part_vals * cap_tiles);
         const size_t o_G = take(sizeof(double) * 256 * (cap_img + 1));
@@ -199,6 +208,7 @@ struct Engine {
         d_desc = (ImgDesc*)(b + o_desc);
         d_tile = (TileRef*)(b + o_tile);
         d_tile32 = (TileRef*)(b + o_tile32);
+        d_tile16r = (TileRef*)(b + o_tile16r);
         d_cg = (CgImg*)(b + o_cg);
         d_part = (double*)(b + o_part);
         d_G = (double*)(b + o_G);
@@ -213,6 +223,8 @@ struct Engine {
             hipHostMalloc((void**)&h_tile, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
                 hipSuccess ||
             hipHostMalloc((void**)&h_tile32, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
+                hipSuccess ||
+            hipHostMalloc((void**)&h_tile16r, sizeof(TileRef) * cap_tiles, hipHostMallocDefault) !=
                 hipSuccess)
             return REDVE_E_NOMEM;
         memset(h_desc, 0, sizeof(ImgDesc) * (cap_img + 1));
@@ -383,11 +395,12 @@ struct Engine {
     // 0..pos-1 (each image a contiguous range from its tile0); the list length B is a power of
     // two (at least 64, at most the capacity; both multiples of 8). Workgroup b runs on XCD
     // b mod 8; XCD x's workgroups take the x-th contiguous chunk of the live tiles, then padding.
-    // The images on the 32x32 CG form get a second list of their 32x32 tiles, built the same
-    // way (length 0 when there are none).
+    // The CG iterations but the last take two more lists, built the same way (length 0 when
+    // empty): the 32x32 tiles of the images on that form, the 16x16 tiles of the others.
     int repack() {
         live.clear();
         live32.clear();
+        live16r.clear();
         for (int i = 0; i < cap_img; ++i) {
             Slot& sl = slots[i];
             if (!sl.running) continue;
@@ -396,14 +409,20 @@ struct Engine {
             if (takes_cg32(sl)) {
                 const int n32 = tiles32_of(sl.item.hx, sl.item.wx);
                 for (int t = 0; t < n32; ++t) live32.push_back(TileRef{i, t});
+            } else {
+                for (int t = 0; t < sl.ntiles; ++t) live16r.push_back(TileRef{i, t});
             }
         }
         launch_tiles = pack(live, h_tile);
         launch_tiles32 = live32.empty() ? 0 : pack(live32, h_tile32);
+        launch_tiles16r = live16r.empty() ? 0 : pack(live16r, h_tile16r);
         if (hipMemcpyAsync(d_tile, h_tile, sizeof(TileRef) * launch_tiles, hipMemcpyHostToDevice,
                            st) != hipSuccess ||
             (launch_tiles32 && hipMemcpyAsync(d_tile32, h_tile32, sizeof(TileRef) * launch_tiles32,
-                                              hipMemcpyHostToDevice, st) != hipSuccess))
+                                              hipMemcpyHostToDevice, st) != hipSuccess) ||
+            (launch_tiles16r &&
+             hipMemcpyAsync(d_tile16r, h_tile16r, sizeof(TileRef) * launch_tiles16r,
+                            hipMemcpyHostToDevice, st) != hipSuccess))
             return REDVE_E_HIP;
         return REDVE_OK;
     }
@@ -440,7 +459,7 @@ struct Engine {
 
     // The launches of one round (captured): denoiser stages, CG, differences + Gram, over the
     // first nt entries of the tile list.
-    int record_fp(int rs, int nt, int nt32) {
+    int record_fp(int rs, int nt, int nt32, int nt16r) {
         TnrdDev d = redve_tnrd_dev(h);
         const float* s_in = nullptr;
         if (h->T > 0) {
@@ -472,11 +491,17 @@ struct Engine {
             for (int k = 0; k < n; ++k) {
                 const int a = k & 1, b = a ^ 1;
                 launch_cg_fin_batch(d_desc, cap_img, k, d_part, cap_tiles, d_cg, st);
-                launch_cg_iter_batch(d_desc, d_tile, nt, rs, k, k == n - 1 ? 1 : 0, d_cg, r(a),
-                                     w(a), s(b), r(b), w(b), s(a), p(), dd(), d_part, cap_tiles, st);
-                // the cg32 images (skipped above but in the last iteration): p_{k-1} in s(a),
-                // p_k to s(b), which the next call's 16x16 kernel passes on as its s_out
-                if (nt32 > 0 && k < n - 1)
+                if (k == n - 1) {  // the last iteration: every image on the 16x16 list
+                    launch_cg_iter_batch(d_desc, d_tile, nt, rs, k, 1, d_cg, r(a), w(a), s(b),
+                                         r(b), w(b), s(a), p(), dd(), d_part, cap_tiles, st);
+                    continue;
+                }
+                if (nt16r > 0)
+                    launch_cg_iter_batch(d_desc, d_tile16r, nt16r, rs, k, 0, d_cg, r(a), w(a),
+                                         s(b), r(b), w(b), s(a), p(), dd(), d_part, cap_tiles, st);
+                // the cg32 images: p_{k-1} in s(a), p_k to s(b), which the last iteration's
+                // 16x16 kernel reads as its s_out
+                if (nt32 > 0)
                     launch_cg_iter32_batch(d_desc, d_tile32, nt32, k, d_cg, r(a), s(a), r(b), s(b),
                                            dd(), d_part, cap_tiles, st);
             }
@@ -498,7 +523,8 @@ struct Engine {
         hipGraph_t g;
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return REDVE_E_HIP;
-        const int rc = fp ? record_fp(std::get<0>(key), std::get<1>(key), std::get<2>(key))
+        const int rc = fp ? record_fp(std::get<0>(key), std::get<1>(key), std::get<2>(key),
+                                      std::get<3>(key))
                           : record_ve(std::get<1>(key));
         if (hipStreamEndCapture(st, &g) != hipSuccess || rc) return REDVE_E_HIP;
         hipGraphExec_t ex;
@@ -561,6 +587,25 @@ struct Engine {
             ++got32;
         }
         if (got32 != want32) return false;
+        // the 16x16 list of the other images: each of their tiles exactly once, nothing else
+        if (launch_tiles16r > cap_tiles || launch_tiles16r % kXcds) return false;
+        std::fill(seen.begin(), seen.end(), 0);
+        int want16r = 0, got16r = 0;
+        for (int i = 0; i < cap_img; ++i)
+            if (slots[i].running && !h_desc[i].cg32) want16r += h_desc[i].ntiles;
+        if ((want16r > 0) != (launch_tiles16r > 0) || want16r > launch_tiles16r) return false;
+        for (int b = 0; b < launch_tiles16r; ++b) {
+            const TileRef e = h_tile16r[b];
+            if (e.img == cap_img) continue;
+            if (e.img < 0 || e.img > cap_img || !slots[e.img].running || h_desc[e.img].cg32 ||
+                e.t < 0 || e.t >= h_desc[e.img].ntiles)
+                return false;
+            const int pi = h_desc[e.img].tile0 + e.t;
+            if (seen[pi]) return false;
+            seen[pi] = 1;
+            ++got16r;
+        }
+        if (got16r != want16r) return false;
         return !h_desc[cap_img].active;
     }
 
@@ -614,7 +659,8 @@ struct Engine {
         if (hipMemcpyAsync(d_desc, h_desc, sizeof(ImgDesc) * (cap_img + 1), hipMemcpyHostToDevice,
                            st) != hipSuccess)
             return REDVE_E_HIP;
-        const GraphKey kf{rs, launch_tiles, launch_tiles32}, kv{0, launch_tiles, 0};
+        const GraphKey kf{rs, launch_tiles, launch_tiles32, launch_tiles16r},
+            kv{0, launch_tiles, 0, 0};
         if ((rc = graph(fp_graph, kf, true))) return rc;
         if (hipGraphLaunch(fp_graph[kf], st) != hipSuccess) return REDVE_E_HIP;
         if (any_ve) {

@@ -26,6 +26,7 @@
 
 using namespace redve;
 
+namespace redve {
 namespace {
 
 constexpr int kFftMaxStages = 24;
@@ -373,6 +374,7 @@ int make_solve(redve_t h, FftSolve& f, int H, int W) {
 }
 
 }  // namespace
+}  // namespace redve
 
 bool redve_fft_size_ok(int H, int W) { return H <= kFftMaxSide && W <= kFftMaxSide; }
 
