@@ -853,25 +853,37 @@ struct __align__(16) Cg32Smem {
     static constexpr int PR = (T32 + 6 * RS + 3) / 4 * 4;  // P region side (origin tile - 3 RS)
     static constexpr int SR = (T32 + 2 * RS + 3) / 4 * 4;  // S region side (origin tile - RS)
     static_assert(PR >= SR + 4 * RS, "the S region's A reads stay in the P region");
-    static_assert(SR >= T32 + 2 * RS + 0, "the tile's B reads stay in the S region");
-    float p[PR * PR];  // p_k on the P region
-    float r[SR * SR];  // r_k, then r_{k+1}, on the S region
-    float h[PR * SR];  // A's row pass over the P rows at the S columns, then B's over the S rows
+    static_assert(SR >= T32 + 2 * RS, "the tile's B reads stay in the S region");
+    // the loader: thread t < LR * PR takes column t % PR of rows t / PR + LR i, i < NL; rows
+    // PR .. LR NL - 1 are stored too (they repeat row PR - 1) and never read
+    static constexpr int LR = kCg32Threads / PR, NL = (PR + LR - 1) / LR, PRX = LR * NL;
+    // row strides: an odd number of 16-byte words (16 lanes reading one word each from 16
+    // consecutive rows hit 16 different groups of four LDS banks); r is stored RO columns to
+    // the right, so that its S region starts on a 16-byte boundary
+    static constexpr int RO = (4 - (2 * RS) % 4) % 4;
+    static constexpr int odd_words(int n) { return (n / 4) % 2 ? n : n + 4; }
+    static constexpr int PS = odd_words(PR);
+    static constexpr int RSS = odd_words((PR + RO + 3) / 4 * 4);
+    static constexpr int HS = odd_words(SR);
+    float p[PRX * PS];   // p_k on the P region
+    float r[PRX * RSS];  // r_k on the P region, then r_{k+1} on its S part
+    float h[PR * HS];    // A's row pass over the P rows at the S columns, then B's over the S rows
 };
 
 // A's row pass over the P rows at the S columns (the autocorrelation of the PSF's row factor),
-// into h with stride SR: four outputs per item from one window of 4 RS + 4 values read as
-// 16-byte words. The item loop stays rolled: an unrolled pair of items doubles the live window.
+// into h: four outputs per item from one window of 4 RS + 4 values read as 16-byte words,
+// consecutive lanes on consecutive rows. The item loop stays rolled: an unrolled pair of items
+// doubles the live window.
 template <int RS, int NT>
 __device__ inline void cg32_a_rows(const LinOp& op, Cg32Smem<RS>& sm) {
     using M = Cg32Smem<RS>;
-    constexpr int SR = M::SR, PR = M::PR, KA = 4 * RS + 1, NWIN = KA + 3;
+    constexpr int SR = M::SR, PR = M::PR, PS = M::PS, HS = M::HS, KA = 4 * RS + 1, NWIN = KA + 3;
     static_assert(NWIN % 4 == 0, "whole 16-byte words");
     constexpr int NQ = SR / 4;
 #pragma unroll 1
     for (int e = threadIdx.x; e < PR * NQ; e += NT) {
-        const int r = e / NQ, c = (e % NQ) * 4;
-        const float4* x4 = reinterpret_cast<const float4*>(sm.p + r * PR + c);
+        const int r = e % PR, c = (e / PR) * 4;
+        const float4* x4 = reinterpret_cast<const float4*>(sm.p + r * PS + c);
         float x[NWIN];
 #pragma unroll
         for (int i = 0; i < NWIN / 4; ++i) {
@@ -889,23 +901,24 @@ __device__ inline void cg32_a_rows(const LinOp& op, Cg32Smem<RS>& sm) {
             o2 += op.acr[j] * x[j + 2];
             o3 += op.acr[j] * x[j + 3];
         }
-        *reinterpret_cast<float4*>(sm.h + r * SR + c) = make_float4(o0, o1, o2, o3);
+        *reinterpret_cast<float4*>(sm.h + r * HS + c) = make_float4(o0, o1, o2, o3);
     }
 }
 
 // r_{k+1} = r_k - alpha (A p)_k on the S region, in place in sm.r: the column pass of A from
-// its row pass h (stride SR, PR rows), four outputs down a column per item.
+// its row pass h, four outputs down a column per item.
 template <int RS, int NT>
 __device__ inline void cg32_update_r(const LinOp& op, Cg32Smem<RS>& sm, float alpha) {
     using M = Cg32Smem<RS>;
-    constexpr int SR = M::SR, PR = M::PR, KA = 4 * RS + 1, NWIN = KA + 3;
+    constexpr int SR = M::SR, PS = M::PS, RSS = M::RSS, HS = M::HS, RO = M::RO;
+    constexpr int KA = 4 * RS + 1, NWIN = KA + 3;
 #pragma unroll 1
     for (int e = threadIdx.x; e < (SR / 4) * SR; e += NT) {
         const int r = (e / SR) * 4, c = e % SR;
-        const float* hc = sm.h + r * SR + c;
+        const float* hc = sm.h + r * HS + c;
         float x[NWIN];
 #pragma unroll
-        for (int i = 0; i < NWIN; ++i) x[i] = hc[i * SR];
+        for (int i = 0; i < NWIN; ++i) x[i] = hc[i * HS];
         float o[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int i = 0; i < KA; ++i)
@@ -914,8 +927,8 @@ __device__ inline void cg32_update_r(const LinOp& op, Cg32Smem<RS>& sm, float al
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float sv =
-                op.inv_s2 * o[k] + op.lambda * sm.p[(r + k + 2 * RS) * PR + c + 2 * RS];
-            float& rv = sm.r[(r + k) * SR + c];
+                op.inv_s2 * o[k] + op.lambda * sm.p[(r + k + 2 * RS) * PS + c + 2 * RS];
+            float& rv = sm.r[(r + k + 2 * RS) * RSS + c + 2 * RS + RO];
             rv = rv - alpha * sv;
         }
     }
@@ -926,12 +939,15 @@ __device__ inline void cg32_update_r(const LinOp& op, Cg32Smem<RS>& sm, float al
 template <int RS, int NT>
 __device__ inline void cg32_b_rows(const LinOp& op, Cg32Smem<RS>& sm) {
     using M = Cg32Smem<RS>;
-    constexpr int SR = M::SR, KB = 2 * RS + 1, NWIN = (KB + 3 + 3) / 4 * 4;
+    constexpr int SR = M::SR, RSS = M::RSS, RO = M::RO, KB = 2 * RS + 1;
+    constexpr int NWIN = (KB + 3 + 3) / 4 * 4;
     static_assert(T32 - 4 + NWIN <= SR, "the window stays in the S row");
+    static_assert((2 * RS + RO) % 4 == 0 && RSS % 4 == 0, "16-byte aligned S rows");
 #pragma unroll 1
     for (int e = threadIdx.x; e < SR * (T32 / 4); e += NT) {
         const int r = e / (T32 / 4), c = (e % (T32 / 4)) * 4;
-        const float4* x4 = reinterpret_cast<const float4*>(sm.r + r * SR + c);
+        const float4* x4 =
+            reinterpret_cast<const float4*>(sm.r + (r + 2 * RS) * RSS + c + 2 * RS + RO);
         float x[NWIN];
 #pragma unroll
         for (int i = 0; i < NWIN / 4; ++i) {
@@ -953,18 +969,19 @@ __device__ inline void cg32_b_rows(const LinOp& op, Cg32Smem<RS>& sm) {
     }
 }
 
-// The per-tile steps, shared by the single-image kernel (a loop over tiles with the next tile's
-// loads in flight) and the batched one (one tile per workgroup). The loader: thread t <
-// LR * PR takes column t % PR of rows t / PR + LR i of the P region.
+// The per-tile steps, shared by the single-image kernel (a loop over tiles) and the batched
+// one (one tile per workgroup).
 template <int RS>
 struct Cg32Geo {
-    static constexpr int NT = kCg32Threads, PR = Cg32Smem<RS>::PR, SR = Cg32Smem<RS>::SR;
-    static constexpr int LR = NT / PR, NL = (PR + LR - 1) / LR;
+    using M = Cg32Smem<RS>;
+    static constexpr int NT = kCg32Threads, PR = M::PR, SR = M::SR, PS = M::PS, RSS = M::RSS;
+    static constexpr int LR = M::LR, NL = M::NL, RO = M::RO;
     static constexpr int NOUT = T32 * T32 / NT;  // tile pixels per thread
 };
 
-// r_k and p_{k-1} of the tile at (r0, c0) on its P region into the loader's registers (zeros
-// for the threads that load nothing; p only for k > 0). Indexes wrap periodically.
+// r_k and p_{k-1} of the tile at (r0, c0) on its P region into the loader's registers (p only
+// for k > 0). Straight-line loads: the rows past the region repeat its last row. Indexes wrap
+// periodically.
 template <int RS>
 __device__ inline void cg32_fetch(int H, int W, int r0, int c0, int k, const float* r_in,
                                   const float* p_in, float (&fr)[Cg32Geo<RS>::NL],
@@ -972,53 +989,46 @@ __device__ inline void cg32_fetch(int H, int W, int r0, int c0, int k, const flo
     using G = Cg32Geo<RS>;
     constexpr int PR = G::PR, LR = G::LR, NL = G::NL;
     const int lcol = threadIdx.x % PR, lrow = threadIdx.x / PR;
-#pragma unroll
-    for (int i = 0; i < NL; ++i) fr[i] = fp[i] = 0.f;
     if (lrow >= LR) return;
     const int pr0 = r0 - 3 * RS, pc0 = c0 - 3 * RS;
+    size_t g[NL];
     if (pr0 >= 0 && pc0 >= 0 && pr0 + PR <= H && pc0 + PR <= W) {
         // the region lies inside the image (every tile but those at the border)
-        const float* rb = r_in + ((size_t)(pr0 + lrow) * W + pc0 + lcol);
-        const float* pb = p_in + ((size_t)(pr0 + lrow) * W + pc0 + lcol);
+        const size_t base = (size_t)(pr0 + lrow) * W + pc0 + lcol;
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            if (lrow + LR * i < PR) {
-                fr[i] = rb[(size_t)LR * i * W];
-                if (k) fp[i] = pb[(size_t)LR * i * W];
-            }
+            const int dr = i == NL - 1 ? min(LR * i, PR - 1 - lrow) : LR * i;
+            g[i] = base + (size_t)dr * W;
         }
     } else {
-        const int gc = wrapi(pc0 + lcol, W);
+        const size_t gc = wrapi(pc0 + lcol, W);
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            if (lrow + LR * i < PR) {
-                const size_t g = (size_t)wrapi(pr0 + lrow + LR * i, H) * W + gc;
-                fr[i] = r_in[g];
-                if (k) fp[i] = p_in[g];
-            }
-        }
+        for (int i = 0; i < NL; ++i)
+            g[i] = (size_t)wrapi(pr0 + min(lrow + LR * i, PR - 1), H) * W + gc;
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) fr[i] = r_in[g[i]];
+    if (k) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) fp[i] = p_in[g[i]];
     }
 }
 
-// p_k = r_k + beta p_{k-1} into the P region, r_k into the S region (from the loader's
-// registers); the caller synchronizes.
+// p_k = r_k + beta p_{k-1} and r_k into the P region (from the loader's registers); the caller
+// synchronizes.
 template <int RS>
 __device__ inline void cg32_stage(int k, float beta, const float (&fr)[Cg32Geo<RS>::NL],
                                   const float (&fp)[Cg32Geo<RS>::NL], Cg32Smem<RS>& sm) {
     using G = Cg32Geo<RS>;
-    constexpr int PR = G::PR, SR = G::SR, LR = G::LR, NL = G::NL;
+    constexpr int PR = G::PR, PS = G::PS, RSS = G::RSS, RO = G::RO, LR = G::LR, NL = G::NL;
     const int lcol = threadIdx.x % PR, lrow = threadIdx.x / PR;
     if (lrow >= LR) return;
-    const int scol = lcol - 2 * RS;
-    const bool scol_in = (unsigned)scol < (unsigned)SR;
+    float* pp = sm.p + lrow * PS + lcol;
+    float* rr = sm.r + lrow * RSS + lcol + RO;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-        const int row = lrow + LR * i;
-        if (row < PR) {
-            sm.p[row * PR + lcol] = k ? fr[i] + beta * fp[i] : fr[i];
-            const int srow = row - 2 * RS;
-            if (scol_in && (unsigned)srow < (unsigned)SR) sm.r[srow * SR + scol] = fr[i];
-        }
+        pp[LR * i * PS] = k ? fr[i] + beta * fp[i] : fr[i];
+        rr[LR * i * RSS] = fr[i];
     }
 }
 
@@ -1042,7 +1052,7 @@ __device__ inline void cg32_finish(const LinOp& op, int H, int W, int r0, int c0
                                    const float (&dk)[Cg32Geo<RS>::NOUT], float* r_out,
                                    float* p_out, float* d, double (&acc)[2]) {
     using G = Cg32Geo<RS>;
-    constexpr int NT = G::NT, PR = G::PR, SR = G::SR, KB = 2 * RS + 1;
+    constexpr int NT = G::NT, PS = G::PS, RSS = G::RSS, RO = G::RO, KB = 2 * RS + 1;
     cg32_a_rows<RS, NT>(op, sm);
     __syncthreads();
     cg32_update_r<RS, NT>(op, sm, alpha);  // r_{k+1} on the S region
@@ -1058,8 +1068,8 @@ __device__ inline void cg32_finish(const LinOp& op, int H, int W, int r0, int c0
         for (int i = 0; i < KB; ++i) q += op.col[i] * sm.h[(tr + i) * T32 + tc];
         if (gr < H && gc < W) {
             const size_t g = (size_t)gr * W + gc;
-            const float rv = sm.r[(tr + RS) * SR + tc + RS];
-            const float pv = sm.p[(tr + 3 * RS) * PR + tc + 3 * RS];
+            const float rv = sm.r[(tr + 3 * RS) * RSS + tc + 3 * RS + RO];
+            const float pv = sm.p[(tr + 3 * RS) * PS + tc + 3 * RS];
             r_out[g] = rv;
             p_out[g] = pv;
             d[g] = k ? dk[o] + alpha * pv : alpha * pv;
@@ -1112,8 +1122,8 @@ __global__ __launch_bounds__(kCg32Threads) void k_cg_iter32(
     for (int t = blockIdx.x; t < nt; t += gridDim.x) {
         origin(t);
         float dk[G::NOUT];
-        cg32_fetch<RS>(H, W, r0, c0, k, r_in, p_in, fr, fp);
         cg32_load_d<RS>(H, W, r0, c0, k, d, dk);
+        cg32_fetch<RS>(H, W, r0, c0, k, r_in, p_in, fr, fp);
         cg32_stage<RS>(k, beta, fr, fp, sm);
         __syncthreads();
         cg32_finish<RS>(op, H, W, r0, c0, k, alpha, sm, dk, r_out, p_out, d, acc);
@@ -1143,8 +1153,8 @@ __global__ __launch_bounds__(kCg32Threads) void k_cg_iter32_batch(
     const int r0 = (e.t / ntx) * T32, c0 = (e.t % ntx) * T32;
     const size_t o = d->off;
     float fr[G::NL], fp[G::NL], dk[G::NOUT];
-    cg32_fetch<RS>(H, W, r0, c0, k, r_in + o, p_in + o, fr, fp);
     cg32_load_d<RS>(H, W, r0, c0, k, dd + o, dk);
+    cg32_fetch<RS>(H, W, r0, c0, k, r_in + o, p_in + o, fr, fp);
     const CgImg c = cg[e.img];
     cg32_stage<RS>(k, (float)c.beta, fr, fp, sm);
     __syncthreads();
