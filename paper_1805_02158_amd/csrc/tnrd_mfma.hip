@@ -194,26 +194,24 @@ __device__ inline void stage_tile_mfma(const float* __restrict__ w, const float*
     }
     __syncthreads();
     // ---- influence functions on the window (tabulated: applied in the forward bank above),
-    // dense over (filter, position) pairs, FP32, at every position
-    // (the adjoint bank zeroes those outside the image). Consecutive lanes take consecutive
-    // positions of one filter: they gather weights from the same LDS row, mostly at the same
-    // or nearby centres (broadcast instead of bank conflicts), and read z at the odd stride ZS
-    // (conflict-free). The pair index advances by NT per step, i.e. by NT / NPOS filters and
-    // NT % NPOS positions, so the offsets are stepped, not divided out.
+    // dense over (filter, position) pairs, FP32, at every position (the adjoint bank zeroes
+    // those outside the image). A wave takes filters wave, wave + NWAVE, ... and its lanes 64
+    // consecutive positions at a time over the first QM positions: the lanes gather weights
+    // from one LDS row, mostly at the same or nearby centres (broadcast instead of bank
+    // conflicts), read z at the odd stride ZS (conflict-free), and step by an immediate offset;
+    // the last QT positions of every filter are shared out over all threads afterwards.
     if constexpr (KC >= 0) {
-        constexpr int ISTEP = NT / NPOS, QSTEP = NT % NPOS;
-        int q = threadIdx.x % NPOS;
-        int zoff = q * ZS + threadIdx.x / NPOS, woff = (threadIdx.x / NPOS) * wstride;
-        const int zstep = QSTEP * ZS + ISTEP, zwrap = NPOS * ZS - 1;
-        for (int e = threadIdx.x; e < NPOS * F; e += NT) {
-            sz[zoff] = phi_eval<KC>(sz[zoff], sw + woff, rc);
-            q += QSTEP;
-            zoff += zstep;
-            woff += ISTEP * wstride;
-            if (q >= NPOS) {
-                q -= NPOS;
-                zoff -= zwrap;
-                woff += wstride;
+        constexpr int QM = NPOS / 64 * 64, QT = NPOS - QM;
+        for (int i = wave; i < F; i += NWAVE) {
+            const float* wr = sw + i * wstride;
+            float* zp = sz + lane * ZS + i;
+#pragma unroll
+            for (int s = 0; s < QM / 64; ++s) zp[s * 64 * ZS] = phi_eval<KC>(zp[s * 64 * ZS], wr, rc);
+        }
+        if constexpr (QT > 0) {
+            for (int e = threadIdx.x; e < QT * F; e += NT) {
+                const int q = QM + e % QT, i = e / QT;
+                sz[q * ZS + i] = phi_eval<KC>(sz[q * ZS + i], sw + i * wstride, rc);
             }
         }
         __syncthreads();
