@@ -95,6 +95,7 @@ def main():
     import workload as W
     from paper_1805_02158_amd import Restorer
 
+    set_denoiser_shape(W.make_denoiser())
     target = json.load(open(os.path.join(ROOT, "tests", "golden", "bench_target_deblur256.json")))
     psnr_star = target["psnr_star_db"]
 
@@ -408,29 +409,50 @@ TERM_FLOP_EQ = 16
 STAGE_STATE_BYTES = 12
 
 
-def stage_work(prec, nfilt=24, nrbf=63):
-    K = 5 if prec == "bf16" else 7
-    terms = nfilt * min(2 * K + 1, nrbf)
-    return {"bank_flop_px": 2 * nfilt * 25 * 2,
-            "bank_issued_flop_px": 6400 if prec == "bf16" else 5200,
+# The denoiser whose stages are rated (set from the workload in main): filters F, their side k,
+# RBF centres J and their spacing / width, stages T.
+DENOISER = {"nfilt": 24, "ksize": 5, "nrbf": 63, "gamma_over_dmu": 1.0, "stages": 5}
+
+
+def set_denoiser_shape(d):
+    DENOISER.update(nfilt=int(d.nfilt), ksize=int(d.ksize), nrbf=int(d.nrbf),
+                    gamma_over_dmu=float(d.gamma) / float(d.dmu), stages=int(d.stages))
+
+
+def stage_work(prec):
+    """Work of one stage per output pixel for the denoiser in DENOISER. The window half-width K
+    follows the library's rule, (K + 1/2) dmu >= reach gamma with reach 5.2565 (BF16: terms
+    below 1e-6 of a weight) or 7.4338 (FP32: 1e-12); the issued bank FLOP count the MFMA tile's
+    padding (taps to 32, filters to 32, 400 positions per 256 outputs; FP32 K-steps stop at the
+    last real tap or filter)."""
+    F, k, J = DENOISER["nfilt"], DENOISER["ksize"], DENOISER["nrbf"]
+    reach = 5.2565 if prec == "bf16" else 7.4338
+    K = max(1, math.ceil(reach * DENOISER["gamma_over_dmu"] - 0.5))
+    terms = F * min(2 * K + 1, J)
+    taps = k * k
+    if prec == "bf16":
+        issued = 2 * 32 * 32 * 2 * 400 / 256
+    else:
+        issued = (math.ceil(taps / 4) * 4 * 32 + math.ceil(F / 4) * 4 * 32) * 2 * 400 / 256
+    return {"bank_flop_px": 2 * F * taps * 2, "bank_issued_flop_px": issued,
             "phi_terms_px": terms, "phi_flop_eq_px": terms * TERM_FLOP_EQ,
-            "state_bytes_px": STAGE_STATE_BYTES, "window_K": K}
+            "state_bytes_px": STAGE_STATE_BYTES, "window_K": K, "filters": F, "centres": J}
 
 
-def stage_bound_ps(prec, nfilt=24, nrbf=63):
+def stage_bound_ps(prec):
     """Roofline time of one stage per pixel (ps): the slowest of banks, phi and state."""
-    w = stage_work(prec, nfilt, nrbf)
+    w = stage_work(prec)
     return max(w["bank_flop_px"] / MFMA_PEAK_TFLOPS[prec], w["phi_flop_eq_px"] / VALU_PEAK_TFLOPS,
                w["state_bytes_px"] / HBM_PEAK_GBS * 1e3)
 
 
-def roofline_stage(npx, stage_us, kernel, prec, nfilt=24, nrbf=63):
+def roofline_stage(npx, stage_us, kernel, prec):
     """The fused denoiser stage: bound by the influence functions on the vector ALUs (their
     roofline time is 30-50x the banks' on MFMA and 35-50x the state traffic's). achieved = the
     influence functions' FLOP-equivalents per launch / average launch time, against the unpacked
     vector peak; the banks' MFMA utilisation (algorithmic and issued FLOP against the MFMA peak
     of their operand type) and the state traffic are reported beside it."""
-    w = stage_work(prec, nfilt, nrbf)
+    w = stage_work(prec)
     t = stage_us * 1e-6
     achieved = npx * w["phi_flop_eq_px"] / t / 1e12
     return {"kernel": kernel, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
@@ -571,7 +593,7 @@ FFT_BYTES_PER_PX = 36
 
 
 def roofline_ps_per_px_call(prec="bf16", n_cg=15, linear="cg"):
-    stages = 5 * stage_bound_ps(prec)
+    stages = DENOISER["stages"] * stage_bound_ps(prec)
     lin = (n_cg * CG_BYTES_PER_PX if linear == "cg" else FFT_BYTES_PER_PX) / HBM_PEAK_GBS * 1e3
     ve = 16.8 / HBM_PEAK_GBS * 1e3
     return {"stages_ps": stages, "linear_ps": lin, "ve_ps": ve, "total_ps": stages + lin + ve,
@@ -606,7 +628,7 @@ def batch_kernels(torch, run, prec, px_calls, n_cg=15):
     for k in out:
         t = out[k]["total_ms"] * 1e-3
         if k.startswith("k_tnrd_stage"):
-            a = 5 * px_calls * w["phi_flop_eq_px"] / t / 1e12
+            a = DENOISER["stages"] * px_calls * w["phi_flop_eq_px"] / t / 1e12
             out[k].update({"bound": "alu", "achieved_tflops": a, "peak": VALU_PEAK_TFLOPS,
                            "frac": a / VALU_PEAK_TFLOPS})
         elif k in ("k_cg_iter_batch", "k_cg_iter32_batch"):
