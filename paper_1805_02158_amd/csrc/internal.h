@@ -126,6 +126,8 @@ void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
                           int last, const CgImg* cg, const float* r_in, const float* w_in,
                           const float* s_in, float* r_out, float* w_out, float* s_out, float* p,
                           float* d, double* part, int cap, hipStream_t st);
+// Workgroups of kernel `fn` the current device holds at once (a multiple of the XCD count).
+int resident_workgroups(const void* fn, int threads, size_t dyn_smem);
 // The CG iterations but the last of the images with cg32 set, over the 32x32 tile list (PSF
 // padded to 9x9, no decimation): r and p double-buffered, d in place.
 void launch_cg_iter32_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles, int k,

@@ -10,6 +10,9 @@
 // one FP64 partial per workgroup, and the next kernel re-sums them (see reduce.h).
 #include <algorithm>
 #include <atomic>
+#include <tuple>
+#include <mutex>
+#include <map>
 
 #include "internal.h"
 #include "reduce.h"
@@ -1894,42 +1897,14 @@ bool cg_iter32_ok(const LinOp& op, int iters, int H, int W) {
     return op.cg_tile ? op.cg_tile == 32 : ntiles_host(H, W) >= kWideBelowTiles;
 }
 
-// Workgroups of the 32x32 kernel: as many as the device holds at once (CUs x resident
-// workgroups per CU, at most kMaxRedBlocks), so that every workgroup runs from the start and
-// takes an equal run of tiles; a grid beyond that leaves a second, partial wave of workgroups.
-// The count is rounded down to a multiple of the XCD count, so that a workgroup's successive
-// tiles stay on its XCD's contiguous run (xcd_tile).
+// Workgroups of the 32x32 kernel: as many as the device holds at once (at most kMaxRedBlocks),
+// so that every workgroup runs from the start and takes an equal run of tiles; a grid beyond
+// that leaves a second, partial wave of workgroups.
 template <int RS>
-static int cg32_resident(int device) {
-    static std::atomic<int> cache[64];
-    if (device < 0 || device >= 64) return kMaxRedBlocks;
-    const int known = cache[device].load(std::memory_order_relaxed);
-    if (known > 0) return known;
-    int cus = 0, per_cu = 0, lds_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cg_iter32<RS>, kCg32Threads, 0) !=
-            hipSuccess ||
-        cus <= 0 || per_cu <= 0)
-        return kMaxRedBlocks;
-    // the register and LDS limits of the kernel itself, where they allow more than the
-    // occupancy query reports (a grid that matches what runs together was 1.2-1.3x faster at
-    // 2048^2 than one of 1024)
-    hipFuncAttributes fa{};
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_cg_iter32<RS>)) == hipSuccess &&
-        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
-                              device) == hipSuccess &&
-        fa.numRegs > 0 && fa.sharedSizeBytes > 0 && lds_cu > 0) {
-        constexpr int kWavesPerSimd = 8, kVgprsPerLane = 512, kSimds = 4;
-        const int regs = (fa.numRegs + 7) / 8 * 8;
-        const int wg_waves_per_simd = (kCg32Threads / 64 + kSimds - 1) / kSimds;
-        const int by_regs = std::min(kWavesPerSimd, kVgprsPerLane / regs) / wg_waves_per_simd;
-        const int by_lds = lds_cu / (int)fa.sharedSizeBytes;
-        per_cu = std::max(per_cu, std::min(by_regs, by_lds));
-    }
-    int g = std::min(kMaxRedBlocks, cus * per_cu);
-    if (g >= kXcds) g -= g % kXcds;
-    cache[device].store(g, std::memory_order_relaxed);
-    return g;
+static int cg32_resident() {
+    return std::min(kMaxRedBlocks,
+                    resident_workgroups(reinterpret_cast<const void*>(k_cg_iter32<RS>),
+                                        kCg32Threads, 0));
 }
 
 Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_in,
@@ -1937,9 +1912,8 @@ Partials launch_cg_iter32(const LinOp& op, int H, int W, int k, const float* r_i
                           const double* hist_prev, double* hist_cur, double* part,
                           hipStream_t st) {
     const int nt = ((H + T32 - 1) / T32) * ((W + T32 - 1) / T32);
-    int device = 0;
-    if (hipGetDevice(&device) != hipSuccess) device = -1;
-    const int cap = op.kh == 9 ? cg32_resident<4>(device) : cg32_resident<3>(device);
+    int cap = op.kh == 9 ? cg32_resident<4>() : cg32_resident<3>();
+    if (cap >= kXcds) cap -= cap % kXcds;
     const int g = nt < cap ? nt : cap;
     if (op.kh == 9)
         k_cg_iter32<4><<<g, kCg32Threads, 0, st>>>(op, H, W, k, r_in, p_in, r_out, p_out, d, rm,
@@ -2024,6 +1998,58 @@ void launch_cg_iter_batch(const ImgDesc* desc, const TileRef* tiles, int ntiles,
     else
         k_cg_iter_batch<0><<<ntiles, kThreads, 0, st>>>(desc, tiles, k, last, cg, r_in, w_in,
                                                         s_in, r_out, w_out, s_out, p, d, part, cap);
+}
+
+// Workgroups of `fn` (threads per workgroup, dynamic LDS bytes) the current device holds at once,
+// a multiple of the XCD count: CUs x per-CU residency, where the per-CU figure is the larger of
+// the occupancy query and the kernel's own register and LDS limits (the query reported 2 on
+// gfx950 where 3 ran together; a grid matching what runs together was 1.2-1.3x faster for the
+// 32x32 CG kernel than one of 1024). Cached per device, kernel and configuration.
+int resident_workgroups(const void* fn, int threads, size_t dyn_smem) {
+    struct Key {
+        int device;
+        const void* fn;
+        int threads;
+        size_t smem;
+        bool operator<(const Key& o) const {
+            return std::tie(device, fn, threads, smem) < std::tie(o.device, o.fn, o.threads, o.smem);
+        }
+    };
+    static std::mutex mu;
+    static std::map<Key, int> cache;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return 1024;
+    const Key key{device, fn, threads, dyn_smem};
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    int cus = 0, per_cu = 0, lds_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, dyn_smem) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+        return 1024;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, fn) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              device) == hipSuccess &&
+        fa.numRegs > 0 && lds_cu > 0) {
+        constexpr int kWavesPerSimd = 8, kVgprsPerLane = 512, kSimds = 4;
+        const int regs = (fa.numRegs + 7) / 8 * 8;
+        const int waves = (threads + 63) / 64;
+        const int wg_waves_per_simd = (waves + kSimds - 1) / kSimds;
+        const int by_regs = std::min(kWavesPerSimd, kVgprsPerLane / regs) / wg_waves_per_simd;
+        const size_t lds = fa.sharedSizeBytes + dyn_smem;
+        const int by_lds = lds > 0 ? (int)(lds_cu / lds) : by_regs;
+        per_cu = std::max(per_cu, std::min(by_regs, by_lds));
+    }
+    int g = cus * per_cu;
+    if (g >= kXcds) g -= g % kXcds;
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = g;
+    return g;
 }
 
 }  // namespace redve
