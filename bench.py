@@ -86,7 +86,7 @@ def main():
     NO_TORCH_PROFILER = args.no_torch_profiler
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the restoration of one image runs on one device and "
-              "this build has no multi-GPU path (--gpus 1 only).", file=sys.stderr)
+              "the library has no multi-GPU path (--gpus 1 only).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -400,8 +400,8 @@ def pmc_probe(torch, R, prob, y):
 #    of a weight, so this is the defined sum to the form's precision; all 63 centres would be
 #    4.2x to 5.7x more), each term 8 vector-ALU slots (difference, square, scale; exp at a
 #    quarter rate: 4; multiply-add), i.e. 16 FLOP-equivalents at the unpacked FP32 vector peak
-#    (256 CUs x 64 lanes x 2.4 GHz x 2 = 78.6 TFLOP/s; packed FP32 is off in this build, so the
-#    published 157.3 is not reachable).
+#    (256 CUs x 64 lanes x 2.4 GHz x 2 = 78.6 TFLOP/s; the library is compiled with packed FP32
+#    off, so the published 157.3 is not reachable).
 #  * state: read u and f, write u: 12 B at 8 TB/s.
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 VALU_PEAK_TFLOPS = 78.6
