@@ -1435,7 +1435,11 @@ struct __align__(16) BlkSmem {
     float hw[QH * TW];
     float Bn[TH * TW];
     float An[TH * TW];
+    // the Gram sums' per-thread values once the tile loop is done (the regions are free then)
+    __device__ double* sums() { return reinterpret_cast<double*>(this); }
 };
+static_assert(sizeof(BlkSmem<3>) >= sizeof(double) * kGram * TH * TW,
+              "the Gram sums' values fit the regions");
 
 // The published Gram sums: wave v < kGram sums array v, in partial order (as consume2). For at most
 // kEarlyPartials partials the loads are issued first (gram_issue, before the tile's loads) and
@@ -1632,7 +1636,6 @@ __global__ __launch_bounds__(kWideThreadsBlk) void k_cg_block(
     double* __restrict__ part) {
     constexpr int NTH = kWideThreadsBlk;
     __shared__ BlkSmem<RS> sm;
-    __shared__ double sred[kGram * (TH * TW / 64)];
     __shared__ double bc[kGram];
     const int nt = ntiles(H, W);
     GramEarly early;
@@ -1658,7 +1661,7 @@ __global__ __launch_bounds__(kWideThreadsBlk) void k_cg_block(
         if (t != (int)blockIdx.x) blk_fetch<RS, NTH>(H, W, r0, c0, k, vs.in, p, d, f);
         blk_tile<RS, NTH>(op, H, W, r0, c0, q, f, vs.out, p, d, sm, g);
     }
-    block_sum_publish<kGram, NTH, TH * TW>(g, sred, part, kMaxRedBlocks, blockIdx.x);
+    block_sum_publish<kGram, NTH, TH * TW>(g, sm.sums(), part, kMaxRedBlocks, blockIdx.x);
 }
 
 // Block start at k = 0: from r_0, w_0 = A r_0 and a_0 = A w_0 on the tile and the Gram sums
@@ -1670,7 +1673,6 @@ __global__ __launch_bounds__(kWideThreadsBlk) void k_cg_w0_block(
     constexpr int NTH = kWideThreadsBlk;
     using M = BlkSmem<RS>;
     __shared__ BlkSmem<RS> sm;
-    __shared__ double sred[kGram * (TH * TW / 64)];
     const int nt = ntiles(H, W);
     double g[kGram];
 #pragma unroll
@@ -1707,7 +1709,7 @@ __global__ __launch_bounds__(kWideThreadsBlk) void k_cg_w0_block(
         }
         __syncthreads();
     }
-    block_sum_publish<kGram, NTH, TH * TW>(g, sred, part, kMaxRedBlocks, blockIdx.x);
+    block_sum_publish<kGram, NTH, TH * TW>(g, sm.sums(), part, kMaxRedBlocks, blockIdx.x);
 }
 
 inline int ntiles_host(int H, int W) { return ((H + TH - 1) / TH) * ((W + TW - 1) / TW); }

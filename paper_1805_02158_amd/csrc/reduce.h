@@ -66,30 +66,26 @@ __device__ inline void block_sum(double (&v)[NV], double* scratch /* NV * NACT/6
     __syncthreads();
 }
 
-// block_sum and publish of many values at once: the active waves' DPP sums of all NV values
-// go to LDS, then thread v < NV of the first wave sums value v over the waves (in wave order,
-// as block_sum) and writes it to part[v * stride + blk].
+// block_sum and publish of many values at once: every active thread stores its NV values to
+// LDS, then wave v < NV sums value v (lane l adds the values of threads l, l + 64, ... in that
+// order, then the DPP wave sum) and writes it to part[v * stride + blk]. One DPP sum per wave,
+// in parallel over the values, instead of NV sums in a row in each active wave.
 template <int NV, int NTH, int NACT>
-__device__ inline void block_sum_publish(const double (&v)[NV], double* scratch /* NV * NACT/64 */,
+__device__ inline void block_sum_publish(const double (&v)[NV], double* scratch /* NV * NACT */,
                                          double* part, int stride, int blk) {
-    constexpr int NW = NACT / 64;
-    static_assert(NACT % 64 == 0 && NACT <= NTH && NV <= 64, "active waves");
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w < NW) {
-        double s[NV];
+    static_assert(NACT % 64 == 0 && NACT <= NTH && NV <= NTH / 64, "one wave per value");
+    if ((int)threadIdx.x < NACT) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] = wave_sum(v[k]);
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < NV; ++k) scratch[k * NW + w] = s[k];
-        }
+        for (int k = 0; k < NV; ++k) scratch[k * NACT + threadIdx.x] = v[k];
     }
     __syncthreads();
-    if ((int)threadIdx.x < NV) {
-        double t = 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w < NV) {
+        double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < NW; ++i) t += scratch[threadIdx.x * NW + i];
-        part[(size_t)threadIdx.x * stride + blk] = t;
+        for (int i = 0; i < NACT / 64; ++i) s += scratch[w * NACT + i * 64 + lane];
+        s = wave_sum(s);
+        if (lane == 0) part[(size_t)w * stride + blk] = s;
     }
 }
 
