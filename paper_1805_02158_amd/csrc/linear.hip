@@ -1435,6 +1435,8 @@ struct __align__(16) BlkSmem {
     float hw[QH * TW];
     float Bn[TH * TW];
     float An[TH * TW];
+    float T0[TH * TW];  // r_k at the tile's pixels
+    float T1[TH * TW];  // r_{k+1} there
     // the Gram sums' per-thread values once the tile loop is done (the regions are free then)
     __device__ double* sums() { return reinterpret_cast<double*>(this); }
 };
@@ -1510,13 +1512,14 @@ __device__ inline BlkScalars blk_scalars(int k, const double* G, double alpha_pr
     return q;
 }
 
-// V on the r_{k+2} region of one tile (NE positions per thread), and V, p, d at the pixel.
+// V on the r_{k+2} region of one tile (NE positions per thread), and p, d at the pixel (V
+// there is part of the region).
 template <int RS, int NTH>
 struct BlkIn {
     static constexpr int RH = TH + 8 * RS, RW = TW + 8 * RS;
     static constexpr int NE = (RH * RW + NTH - 1) / NTH;
     float v[NE][5];
-    float vo[5], po, dn;
+    float po, dn;
 };
 
 template <int RS, int NTH>
@@ -1538,19 +1541,12 @@ __device__ inline void blk_fetch(int H, int W, int r0, int c0, int k, const floa
                 if (j != 2 && j != 4 ? true : nv == 5) f.v[i][j] = vin[j][g];
         }
     }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) f.vo[j] = 0.f;
     f.po = f.dn = 0.f;
     const int gr = r0 + threadIdx.x / TW, gc = c0 + threadIdx.x % TW;
-    if ((int)threadIdx.x < TH * TW && gr < H && gc < W) {
+    if (k && (int)threadIdx.x < TH * TW && gr < H && gc < W) {
         const size_t g = (size_t)gr * W + gc;
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            if (j != 2 && j != 4 ? true : nv == 5) f.vo[j] = vin[j][g];
-        if (k) {
-            f.po = p[g];
-            f.dn = d[g];
-        }
+        f.po = p[g];
+        f.dn = d[g];
     }
 }
 
@@ -1563,7 +1559,8 @@ __device__ inline void blk_tile(const LinOp& op, int H, int W, int r0, int c0,
                                 BlkSmem<RS>& sm, double (&g)[kGram]) {
     using M = BlkSmem<RS>;
     using C = BlkIn<RS, NTH>;
-    // r_{k+2} on the whole region, s_{k+1} on its inner 2 RS halo
+    // r_{k+2} on the whole region, s_{k+1} on its inner 2 RS halo, r_k and r_{k+1} at the
+    // tile's pixels (the region covers them)
 #pragma unroll
     for (int i = 0; i < C::NE; ++i) {
         const int e = threadIdx.x + i * NTH;
@@ -1578,6 +1575,14 @@ __device__ inline void blk_tile(const LinOp& op, int H, int W, int r0, int c0,
             sm.R[e] = rv;
             const int qr = rr - 2 * RS, qc = rc - 2 * RS;
             if (qr >= 0 && qr < M::QH && qc >= 0 && qc < M::QW) sm.S[qr * M::QW + qc] = sv;
+            const int tr = rr - 4 * RS, tc = rc - 4 * RS;
+            if (tr >= 0 && tr < TH && tc >= 0 && tc < TW) {
+                float r1 = 0.f;
+#pragma unroll
+                for (int j = 0; j < 5; ++j) r1 += q.cr1[j] * f.v[i][j];
+                sm.T0[tr * TW + tc] = f.v[i][0];
+                sm.T1[tr * TW + tc] = r1;
+            }
         }
     }
     __syncthreads();
@@ -1595,10 +1600,8 @@ __device__ inline void blk_tile(const LinOp& op, int H, int W, int r0, int c0,
     const int gr = r0 + tr, gc = c0 + tc;
     if ((int)threadIdx.x < TH * TW && gr < H && gc < W) {
         const size_t gi = (size_t)gr * W + gc;
-        float r1 = 0.f;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) r1 += q.cr1[j] * f.vo[j];
-        const float pk = f.vo[0] + (float)q.b1 * f.po;
+        const float r1 = sm.T1[tr * TW + tc];
+        const float pk = sm.T0[tr * TW + tc] + (float)q.b1 * f.po;
         const float pk1 = r1 + (float)q.b2 * pk;
         const float dn = f.dn + (float)q.a0 * pk + (float)q.a1 * pk1;
         const float v[5] = {sm.R[(tr + 4 * RS) * M::RW + tc + 4 * RS],
