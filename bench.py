@@ -253,6 +253,7 @@ def main():
     if not args.no_sd:
         res["steepest_descent"] = bench_sd(args, torch, np, R, prob, y, out, psnr, psnr_star)
     res["ve_kernels_2048x2048"] = bench_ve_kernels(torch, W, Restorer, prob)
+    res["fft_kernels_2048x2048"] = bench_fft_kernels(torch, W, Restorer, prob)
     if not args.no_sr:
         res["sr512"] = bench_sr(args, torch, np, W, Restorer)
     if not args.no_batch:
@@ -586,10 +587,12 @@ def observe(torch, R, probs):
 # own roofline, summed (the classes run one after another): the denoiser's 5 stages (each the
 # slowest of its banks on MFMA, its influence functions on the vector ALUs and its 12 B of
 # state, see stage_bound_ps), the linear step (CG: n_cg x 24 B, x, r, p read and written once
-# per iteration; the exact Fourier step: 36 B, see fft.hip) and the extrapolation's difference
-# and combination passes (16.8 B per FP call for L = 5: u written, the Gram reads and the
-# combination spread over a cycle of 5 calls).
-FFT_BYTES_PER_PX = 36
+# per iteration; the exact Fourier step: 30 B, r0 read and the half spectrum written by the row
+# pass (4 + 4), the half spectrum and its scale factors read and the spectrum written by the
+# column pass (4 + 2 + 4), the spectrum, x_in read and x_out written by the inverse row pass
+# (4 + 4 + 4)) and the extrapolation's difference and combination passes (16.8 B per FP call
+# for L = 5: u written, the Gram reads and the combination spread over a cycle of 5 calls).
+FFT_BYTES_PER_PX = 30
 
 
 def roofline_ps_per_px_call(prec="bf16", n_cg=15, linear="cg"):
@@ -917,6 +920,40 @@ def bench_ve_kernels(torch, W, Restorer, prob):
         out[name] = e
     R.close()
     log("ve kernels 2048x2048", out)
+    return {"pixels": npx, "peak_gbs": HBM_PEAK_GBS, "kernels": out}
+
+
+# Algorithmic HBM bytes per pixel of the Fourier linear step's kernels (FFT_BYTES_PER_PX).
+FFT_KERNEL_BYTES = {"k_fft_rows_fwd": 8, "k_fft_cols": 10, "k_fft_rows_inv": 12}
+
+
+def bench_fft_kernels(torch, W, Restorer, prob):
+    """The exact Fourier linear step's three kernels on a 2048 x 2048 image (device times from
+    the profiler over five FP calls with BF16 banks): achieved GB/s = algorithmic bytes /
+    average duration."""
+    npx = 2048 * 2048
+    R = Restorer(0)
+    R.configure(prob, precision="bf16", method="none", tol=0.0)
+    R.set_linear_solver("fft")
+    big = torch.tensor(W.make_image(2048, 2048, 77), dtype=torch.float32, device="cuda")
+    R.fp_step(big, big)
+
+    def run():
+        for _ in range(5):
+            R.fp_step(big, big)
+
+    times = kernel_times(torch, run)
+    out = {}
+    for name, (count, us) in sorted(times.items()):
+        b = FFT_KERNEL_BYTES.get(name)
+        if b is None:
+            continue
+        avg = us / count
+        gbs = npx * b / (avg * 1e-6) / 1e9
+        out[name] = {"launches": count, "avg_us": avg, "bytes_per_px": b, "achieved_gbs": gbs,
+                     "frac": gbs / HBM_PEAK_GBS}
+    R.close()
+    log("fft kernels 2048x2048", out)
     return {"pixels": npx, "peak_gbs": HBM_PEAK_GBS, "kernels": out}
 
 
