@@ -96,6 +96,12 @@ struct Slot {
 
 struct Engine {
     redve_t h = nullptr;      // settings (denoiser, method, solver)
+    // the first failure of a copy or wait queued outside a round (admission, retirement); the
+    // next round, and the end of a batch, report it as REDVE_E_HIP
+    hipError_t queue_err = hipSuccess;
+    void note(hipError_t e) {
+        if (e != hipSuccess && queue_err == hipSuccess) queue_err = e;
+    }
     unsigned long long gen = 0;  // the settings generation the graphs were recorded for
     hipStream_t st = nullptr; // the engine's own stream (capturable; never the null stream)
     int cap_img = 0, cap_tiles = 0, L = 1;
@@ -148,16 +154,16 @@ struct Engine {
     ~Engine() { release(); }
 
     void release() {
-        for (auto& kv : fp_graph) hipGraphExecDestroy(kv.second);
-        for (auto& kv : ve_graph) hipGraphExecDestroy(kv.second);
+        for (auto& kv : fp_graph) (void)hipGraphExecDestroy(kv.second);
+        for (auto& kv : ve_graph) (void)hipGraphExecDestroy(kv.second);
         fp_graph.clear();
         ve_graph.clear();
-        if (arena) hipFree(arena);
-        if (h_desc) hipHostFree(h_desc);
-        if (h_stat) hipHostFree(h_stat);
-        if (h_tile) hipHostFree(h_tile);
-        if (h_tile32) hipHostFree(h_tile32);
-        if (h_tile16r) hipHostFree(h_tile16r);
+        if (arena) (void)hipFree(arena);
+        if (h_desc) (void)hipHostFree(h_desc);
+        if (h_stat) (void)hipHostFree(h_stat);
+        if (h_tile) (void)hipHostFree(h_tile);
+        if (h_tile32) (void)hipHostFree(h_tile32);
+        if (h_tile16r) (void)hipHostFree(h_tile16r);
         arena = nullptr;
         h_desc = nullptr;
         h_stat = nullptr;
@@ -238,6 +244,7 @@ struct Engine {
 
     // Forgets every image (keeps buffers and graphs) for the next batch.
     void reset() {
+        queue_err = hipSuccess;
         slots.assign(cap_img, Slot{});
         px_alloc.used.clear();
         tiles_used = 0;
@@ -262,11 +269,11 @@ struct Engine {
         const int kh = it.kh, kw = it.kw;
         std::vector<float> pf(kh * kw);
         for (int k = 0; k < kh * kw; ++k) pf[k] = (float)it.psf[k];
-        hipMemcpyAsync(d_psf + (size_t)i * 225, pf.data(), sizeof(float) * kh * kw,
-                       hipMemcpyHostToDevice, st);
-        hipMemcpyAsync(d_psf64 + (size_t)i * 225, it.psf, sizeof(double) * kh * kw,
-                       hipMemcpyHostToDevice, st);
-        hipStreamSynchronize(st);  // pf is a host temporary
+        note(hipMemcpyAsync(d_psf + (size_t)i * 225, pf.data(), sizeof(float) * kh * kw,
+                            hipMemcpyHostToDevice, st));
+        note(hipMemcpyAsync(d_psf64 + (size_t)i * 225, it.psf, sizeof(double) * kh * kw,
+                            hipMemcpyHostToDevice, st));
+        note(hipStreamSynchronize(st));  // pf is a host temporary
         op.psf = d_psf + (size_t)i * 225;
         op.psf64 = d_psf64 + (size_t)i * 225;
         op.decim = it.decim;
@@ -348,15 +355,15 @@ struct Engine {
         // a fresh CG state for the slot, then the operator (set_operator waits for the stream,
         // so both host-to-device copies are done before their host sources go away)
         CgImg z{};
-        hipMemcpyAsync(d_cg + i, &z, sizeof(CgImg), hipMemcpyHostToDevice, st);
+        note(hipMemcpyAsync(d_cg + i, &z, sizeof(CgImg), hipMemcpyHostToDevice, st));
         set_operator(i, it);
         // initial vector: x0, y (deblurring) or decim^2 H^T y (needs the operator above)
         const size_t bytes = sizeof(float) * it.hx * it.wx;
         float* x0 = x(0) + off;
         if (it.x0)
-            hipMemcpyAsync(x0, it.x0, bytes, hipMemcpyDeviceToDevice, st);
+            note(hipMemcpyAsync(x0, it.x0, bytes, hipMemcpyDeviceToDevice, st));
         else if (it.decim == 1)
-            hipMemcpyAsync(x0, it.y, bytes, hipMemcpyDeviceToDevice, st);
+            note(hipMemcpyAsync(x0, it.y, bytes, hipMemcpyDeviceToDevice, st));
         else {
             LinOp o2 = sl.op;
             o2.kh = it.kh;
@@ -377,7 +384,7 @@ struct Engine {
     void retire(int i) {
         Slot& sl = slots[i];
         const size_t bytes = sizeof(float) * sl.item.hx * sl.item.wx;
-        hipMemcpyAsync(sl.item.x, x(sl.cur) + sl.off, bytes, hipMemcpyDeviceToDevice, st);
+        note(hipMemcpyAsync(sl.item.x, x(sl.cur) + sl.off, bytes, hipMemcpyDeviceToDevice, st));
         px_alloc.release(sl.off);
         tiles_used -= sl.ntiles;
         tiles_dirty = true;
@@ -529,7 +536,7 @@ struct Engine {
         if (hipStreamEndCapture(st, &g) != hipSuccess || rc) return REDVE_E_HIP;
         hipGraphExec_t ex;
         const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return REDVE_E_HIP;
         cache[key] = ex;
         return REDVE_OK;
@@ -618,6 +625,7 @@ struct Engine {
     // One FP call for every running slot, extrapolation for those completing a window, and the
     // Algorithm 3 bookkeeping. Returns an error code for HIP failures only.
     int round() {
+        if (queue_err != hipSuccess) return REDVE_E_HIP;
         const int m = h->m;
         const bool ve = h->method != REDVE_VE_NONE;
         bool all_padded = true, any_ve = false;
@@ -822,7 +830,8 @@ extern "C" int redve_solve_batch(redve_t h, int n, const redve_item_t* items, re
             return drop(rc, rc == REDVE_E_STATE ? "internal: inconsistent batched round (not launched)"
                                                 : "HIP failure in a batched round");
     }
-    if (hipStreamSynchronize(h->bstream) != hipSuccess) return drop(REDVE_E_HIP, "HIP failure");
+    if (hipStreamSynchronize(h->bstream) != hipSuccess || eng->queue_err != hipSuccess)
+        return drop(REDVE_E_HIP, "HIP failure");
     const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
     int worst = REDVE_OK;
     for (int i = 0; i < n; ++i) {
@@ -867,7 +876,7 @@ struct redve_server {
     // memory, tiles), runs one round, publishes finished requests. Engine state is touched by
     // this thread only; everything the API functions read is published under mu.
     void run() {
-        hipSetDevice(ctx.device);
+        eng.note(hipSetDevice(ctx.device));  // a failure fails the first round
         while (true) {
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -877,9 +886,9 @@ struct redve_server {
                     int slot;
                     Req& q = queue.front();
                     q.item.psf = q.psf.data();
-                    hipStreamWaitEvent(eng.st, q.ready, 0);  // inputs written on the caller's stream
+                    eng.note(hipStreamWaitEvent(eng.st, q.ready, 0));  // inputs: caller's stream
                     if (!eng.admit(q.item, q.ticket, q.t_submit, slot)) break;
-                    hipEventDestroy(q.ready);
+                    (void)hipEventDestroy(q.ready);
                     queue.pop_front();
                     ++active;
                 }
@@ -890,8 +899,9 @@ struct redve_server {
                 if (!queue.empty() && active > 0) ++waited;
             }
             if (active == 0) continue;  // cannot happen: an empty engine admits any queued head
-            const int rc = eng.round();
-            if (rc == REDVE_OK) hipStreamSynchronize(eng.st);  // the retire copies
+            int rc = eng.round();
+            if (rc == REDVE_OK) eng.note(hipStreamSynchronize(eng.st));  // the retire copies
+            if (rc == REDVE_OK && eng.queue_err != hipSuccess) rc = REDVE_E_HIP;
             std::lock_guard<std::mutex> lk(mu);
             ++rounds;
             if (rc) {
@@ -907,7 +917,7 @@ struct redve_server {
                     redve_stats_t s{};
                     s.status = rc;
                     results[q.ticket] = s;
-                    hipEventDestroy(q.ready);
+                    (void)hipEventDestroy(q.ready);
                 }
                 queue.clear();
             }
@@ -978,7 +988,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     const size_t per_px = Engine::bytes_per_px(L);
     const size_t cap_px = hbm_budget / per_px;
     if (cap_px < 64 * 64) {
-        hipStreamDestroy(c.stream);
+        (void)hipStreamDestroy(c.stream);
         return REDVE_E_ARG;
     }
     s->max_active = max_active;
@@ -986,7 +996,7 @@ extern "C" int redve_server_create(redve_server_t* out, redve_t proto, size_t hb
     // requests thinner than 4 pixels may need more than cap_px / 64 and are refused at submit
     const int cap_tiles = (int)std::min<size_t>(cap_px / 64 + 64 * (size_t)max_active, 1 << 26);
     if (s->eng.init(&c, c.stream, max_active, cap_px, cap_tiles)) {
-        hipStreamDestroy(c.stream);
+        (void)hipStreamDestroy(c.stream);
         return REDVE_E_NOMEM;
     }
     redve_server* raw = s.release();
@@ -1007,12 +1017,12 @@ extern "C" int redve_server_submit(redve_server_t s, const redve_item_t* item,
     hipEvent_t ev;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return REDVE_E_HIP;
     if (hipEventRecord(ev, s->caller) != hipSuccess) {
-        hipEventDestroy(ev);
+        (void)hipEventDestroy(ev);
         return REDVE_E_HIP;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error) {
-        hipEventDestroy(ev);
+        (void)hipEventDestroy(ev);
         return s->error;
     }
     *ticket = s->next_ticket++;
@@ -1076,10 +1086,10 @@ extern "C" int redve_server_destroy(redve_server_t s) {
     }
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
-    hipSetDevice(s->ctx.device);
-    hipStreamSynchronize(s->ctx.stream);
+    (void)hipSetDevice(s->ctx.device);
+    (void)hipStreamSynchronize(s->ctx.stream);
     s->eng.release();
-    hipStreamDestroy(s->ctx.stream);
+    (void)hipStreamDestroy(s->ctx.stream);
     // the denoiser buffers belong to the prototype handle
     s->ctx.d_filt = nullptr;
     s->ctx.d_rbfw = nullptr;

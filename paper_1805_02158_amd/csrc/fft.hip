@@ -17,7 +17,9 @@
 // 4, 2, 3 and 5 have closed-form butterflies; any other prime factor takes a direct DFT per
 // output (its cost grows with the factor, so lengths with a large prime factor are slow but
 // exact). Twiddles w_N^e = exp(-2 pi i e / N) come from per-length tables computed in FP64 on
-// the host and rounded to FP32; arithmetic is FP32 (relative error of order log2(N) 2^-24).
+// the host and rounded to FP32, which each workgroup copies into LDS beside its data (a stage
+// reads them there instead of from memory); arithmetic is FP32 (relative error of order
+// log2(N) 2^-24).
 #include <math.h>
 
 #include <vector>
@@ -55,7 +57,11 @@ FftPlan make_plan(int n) {
     take(2);
     take(3);
     take(5);
-    for (int r = 7; m > 1; r += 2) take(r);
+    int r = 7;
+    while (m > 1) {  // take() divides m by every factor r it finds
+        take(r);
+        r += 2;
+    }
     return p;
 }
 
@@ -221,13 +227,16 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_fwd(const float* __res
                                                              int W, FftPlan plan,
                                                              const float2* __restrict__ tw,
                                                              float2* __restrict__ spec) {
-    extern __shared__ float2 X[];
+    extern __shared__ float2 X[];  // the row, then the twiddles
+    float2* T = X + W;
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     const bool two = r1 < H;
-    for (int j = threadIdx.x; j < W; j += kRowThreads)
+    for (int j = threadIdx.x; j < W; j += kRowThreads) {
         X[j] = make_float2(r[(size_t)r0 * W + j], two ? r[(size_t)r1 * W + j] : 0.f);
+        T[j] = tw[j];
+    }
     __syncthreads();
-    fft_lds<kRowThreads>(X, 0, plan, tw, false);
+    fft_lds<kRowThreads>(X, 0, plan, T, false);
     // Z = F(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2 i)
     const int wc = W / 2 + 1;
     for (int k = threadIdx.x; k < wc; k += kRowThreads) {
@@ -245,22 +254,24 @@ __global__ __launch_bounds__(kColThreads) void k_fft_cols(float2* __restrict__ s
                                                          const float* __restrict__ scale, int H,
                                                          int wc, int lgnc, FftPlan plan,
                                                          const float2* __restrict__ tw) {
-    extern __shared__ float2 X[];
+    extern __shared__ float2 X[];  // the columns, then the twiddles
     const int nc = 1 << lgnc, c0 = xcd_tile(blockIdx.x, gridDim.x) * nc;
     const int total = H << lgnc;
+    float2* T = X + total;
     for (int e = threadIdx.x; e < total; e += kColThreads) {
         const int i = e >> lgnc, c = c0 + (e & (nc - 1));
         X[e] = c < wc ? spec[(size_t)i * wc + c] : make_float2(0.f, 0.f);
     }
+    for (int e = threadIdx.x; e < H; e += kColThreads) T[e] = tw[e];
     __syncthreads();
-    fft_lds<kColThreads>(X, lgnc, plan, tw, false);
+    fft_lds<kColThreads>(X, lgnc, plan, T, false);
     for (int e = threadIdx.x; e < total; e += kColThreads) {
         const int i = e >> lgnc, c = c0 + (e & (nc - 1));
         const float s = c < wc ? scale[(size_t)i * wc + c] : 0.f;
         X[e] = make_float2(X[e].x * s, X[e].y * s);
     }
     __syncthreads();
-    fft_lds<kColThreads>(X, lgnc, plan, tw, true);
+    fft_lds<kColThreads>(X, lgnc, plan, T, true);
     for (int e = threadIdx.x; e < total; e += kColThreads) {
         const int i = e >> lgnc, c = c0 + (e & (nc - 1));
         if (c < wc) spec[(size_t)i * wc + c] = X[e];
@@ -274,11 +285,13 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __re
                                                              float* __restrict__ x_out, int H,
                                                              int W, FftPlan plan,
                                                              const float2* __restrict__ tw) {
-    extern __shared__ float2 X[];
+    extern __shared__ float2 X[];  // the row, then the twiddles
+    float2* T = X + W;
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     const bool two = r1 < H;
     const int wc = W / 2 + 1;
     for (int j = threadIdx.x; j < W; j += kRowThreads) {
+        T[j] = tw[j];
         const bool lo = j < wc;
         const int k = lo ? j : W - j;
         float2 a = spec[(size_t)r0 * wc + k];
@@ -290,7 +303,7 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __re
         X[j] = make_float2(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    fft_lds<kRowThreads>(X, 0, plan, tw, true);
+    fft_lds<kRowThreads>(X, 0, plan, T, true);
     for (int j = threadIdx.x; j < W; j += kRowThreads) {
         const float2 z = X[j];
         x_out[(size_t)r0 * W + j] = x_in[(size_t)r0 * W + j] + z.x;
@@ -339,11 +352,11 @@ struct FftSolve {
     float2* spec = nullptr;
     float* scale = nullptr;
 
-    ~FftSolve() {
-        hipFree(tw_h);
-        hipFree(tw_w);
-        hipFree(spec);
-        hipFree(scale);
+    ~FftSolve() {  // teardown: a failed free leaves nothing to recover
+        (void)hipFree(tw_h);
+        (void)hipFree(tw_w);
+        (void)hipFree(spec);
+        (void)hipFree(scale);
     }
 };
 
@@ -390,7 +403,8 @@ int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, 
     }
     FftSolve* f = (FftSolve*)h->fft;
     if (f && (f->H != H || f->W != W)) {
-        hipStreamSynchronize(h->stream);
+        // the buffers of the old size may still be in use by queued work
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return REDVE_E_HIP;
         h->fft_free(f);
         f = nullptr;
         h->fft = nullptr;
@@ -413,9 +427,9 @@ int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, 
         f->op_gen = h->op_gen;
     }
     const int rows = (H + 1) / 2;
-    const size_t row_lds = sizeof(float2) * W;
+    const size_t row_lds = sizeof(float2) * 2 * W;  // a row and its twiddles
     const int lgnc = col_lgnc(H);
-    const size_t col_lds = sizeof(float2) * ((size_t)H << lgnc);
+    const size_t col_lds = sizeof(float2) * (((size_t)H << lgnc) + H);  // columns, twiddles
     k_fft_rows_fwd<<<rows, kRowThreads, row_lds, h->stream>>>(r0, H, W, f->pw, f->tw_w, f->spec);
     k_fft_cols<<<(wc + (1 << lgnc) - 1) >> lgnc, kColThreads, col_lds, h->stream>>>(
         f->spec, f->scale, H, wc, lgnc, f->ph, f->tw_h);

@@ -463,12 +463,12 @@ int capture_pass(redve_t h, const float* y, float* x_cur, int hx, int wx, PassGr
     hipGraphExec_t exec = nullptr;
     const bool ok = rc == REDVE_OK && ec == hipSuccess && graph &&
                     hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     if (!ok) {
         (void)hipGetLastError();
         return rc ? rc : REDVE_E_HIP;
     }
-    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g.exec = exec;
     g.from = x_cur;
     g.next = next;
@@ -658,8 +658,8 @@ int autotune(redve_t h, const float* y, const float* x_in, float* x_out, int hx,
             best.us = us;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return fail(h, rc, "autotuning failed: " + h->err);
     tune_key(h, hx, wx, best.key);
     return REDVE_OK;
@@ -741,25 +741,25 @@ int redve_create(redve_t* out, int device, void* hip_stream) {
 
 int redve_destroy(redve_t h) {
     if (!h) return REDVE_E_ARG;
-    hipSetDevice(h->device);
-    hipStreamSynchronize(h->stream);
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
     if (h->batch && h->batch_free) h->batch_free(h->batch);
     h->batch = nullptr;
     if (h->fft && h->fft_free) h->fft_free(h->fft);
     h->fft = nullptr;
-    if (h->ws.arena) hipFree(h->ws.arena);
-    hipFree(h->d_psf);
-    hipFree(h->d_psf64);
-    hipFree(h->d_filt);
-    hipFree(h->d_rbfw);
-    hipFree(h->d_frag);
-    hipFree(h->d_frag32);
-    hipFree(h->d_phitab);
-    if (h->bstream) hipStreamDestroy(h->bstream);
+    if (h->ws.arena) (void)hipFree(h->ws.arena);
+    (void)hipFree(h->d_psf);
+    (void)hipFree(h->d_psf64);
+    (void)hipFree(h->d_filt);
+    (void)hipFree(h->d_rbfw);
+    (void)hipFree(h->d_frag);
+    (void)hipFree(h->d_frag32);
+    (void)hipFree(h->d_phitab);
+    if (h->bstream) (void)hipStreamDestroy(h->bstream);
     for (auto& g : h->pass)
-        if (g.exec) hipGraphExecDestroy(g.exec);
-    if (h->gstream) hipStreamDestroy(h->gstream);
-    hipHostFree(h->host);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    (void)hipHostFree(h->host);
     delete h;
     return REDVE_OK;
 }
@@ -881,11 +881,11 @@ int redve_set_denoiser(redve_t h, const redve_tnrd_t* p) {
         return fail(h, REDVE_E_ARG, "BF16 stage: nfilt and nrbf exceed the LDS of a workgroup (use FP32)");
     HIP_TRY(h, hipSetDevice(h->device));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    hipFree(h->d_filt);
-    hipFree(h->d_rbfw);
-    hipFree(h->d_frag);
-    hipFree(h->d_frag32);
-    hipFree(h->d_phitab);
+    (void)hipFree(h->d_filt);
+    (void)hipFree(h->d_rbfw);
+    (void)hipFree(h->d_frag);
+    (void)hipFree(h->d_frag32);
+    (void)hipFree(h->d_phitab);
     h->d_filt = h->d_rbfw = nullptr;
     h->d_frag = nullptr;
     h->d_frag32 = nullptr;
