@@ -32,10 +32,14 @@ namespace redve {
 namespace {
 
 constexpr int kFftMaxStages = 24;
-constexpr int kFftMaxSide = 4096;   // W: 256 threads x 16 elements; H: see kColThreads
+constexpr int kFftMaxSide = 4096;   // W: 256 threads x 16 elements; H: 512 threads x 8
 constexpr int kRowThreads = 256;
 constexpr int kColThreads = 512;
-constexpr int kFftElems = 16;       // complex elements per thread and stage
+// complex elements per thread and stage: the registers a stage holds grow with it, so the column
+// pass takes 8 (under 128 registers: two workgroups of 512 threads per CU, against one with 16)
+constexpr int kRowElems = 16, kColElems = 8;
+static_assert(kRowThreads * kRowElems >= kFftMaxSide && kColThreads * kColElems >= kFftMaxSide,
+              "a workgroup holds a whole row, and a whole column");
 
 // Radix stages of one transform length.
 struct FftPlan {
@@ -125,10 +129,10 @@ __device__ inline float2 twiddle(const float2* __restrict__ tw, int e, bool inv)
 // l of the m = N / l decimated subsequences; butterfly (c', k1), c' < m / P, k1 < l, reads
 // a_q = X[k1 m + c' + (m / P) q], twiddles it by w_N^{q k1 m / P} and writes its P outputs to
 // X[(k1 + l k2) (m / P) + c'].
-template <int P, int NT>
+template <int P, int NT, int EL>
 __device__ inline void stage(float2* X, int N, int lgnc, int l, int m,
                              const float2* __restrict__ tw, bool inv) {
-    constexpr int NB = (kFftElems + P - 1) / P;  // butterflies per thread
+    constexpr int NB = (EL + P - 1) / P;  // butterflies per thread
     const int mp = m / P;
     const int nbf = (N / P) << lgnc;
     float2 y[NB][P];
@@ -163,15 +167,15 @@ __device__ inline void stage(float2* X, int N, int lgnc, int l, int m,
 
 // A stage of any prime radix p: each output is the direct sum over its p inputs, with the
 // combined twiddle w_N^{q k1 m/p + ((q k2) mod p) N/p}.
-template <int NT>
+template <int NT, int EL>
 __device__ inline void stage_any(float2* X, int N, int lgnc, int p, int l, int m,
                                  const float2* __restrict__ tw, bool inv) {
     const int mp = m / p, np = N / p;
     const int total = N << lgnc;
-    float2 y[kFftElems];
-    int o[kFftElems];
+    float2 y[EL];
+    int o[EL];
 #pragma unroll
-    for (int e = 0; e < kFftElems; ++e) {
+    for (int e = 0; e < EL; ++e) {
         const int oi = threadIdx.x + e * NT;
         o[e] = -1;
         if (oi < total) {
@@ -196,14 +200,14 @@ __device__ inline void stage_any(float2* X, int N, int lgnc, int p, int l, int m
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < kFftElems; ++e)
+    for (int e = 0; e < EL; ++e)
         if (o[e] >= 0) X[o[e]] = y[e];
     __syncthreads();
 }
 
 // The whole transform (forward: w = exp(-2 pi i / N); inverse: conjugate, unnormalised).
 // Expects the data in X and a workgroup barrier behind; ends with one.
-template <int NT>
+template <int NT, int EL>
 __device__ inline void fft_lds(float2* X, int lgnc, const FftPlan& plan,
                                const float2* __restrict__ tw, bool inv) {
     const int N = plan.n;
@@ -211,11 +215,11 @@ __device__ inline void fft_lds(float2* X, int lgnc, const FftPlan& plan,
     for (int s = 0; s < plan.nrad; ++s) {
         const int p = plan.rad[s];
         switch (p) {
-            case 4: stage<4, NT>(X, N, lgnc, l, m, tw, inv); break;
-            case 2: stage<2, NT>(X, N, lgnc, l, m, tw, inv); break;
-            case 3: stage<3, NT>(X, N, lgnc, l, m, tw, inv); break;
-            case 5: stage<5, NT>(X, N, lgnc, l, m, tw, inv); break;
-            default: stage_any<NT>(X, N, lgnc, p, l, m, tw, inv); break;
+            case 4: stage<4, NT, EL>(X, N, lgnc, l, m, tw, inv); break;
+            case 2: stage<2, NT, EL>(X, N, lgnc, l, m, tw, inv); break;
+            case 3: stage<3, NT, EL>(X, N, lgnc, l, m, tw, inv); break;
+            case 5: stage<5, NT, EL>(X, N, lgnc, l, m, tw, inv); break;
+            default: stage_any<NT, EL>(X, N, lgnc, p, l, m, tw, inv); break;
         }
         l *= p;
         m /= p;
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_fwd(const float* __res
         T[j] = tw[j];
     }
     __syncthreads();
-    fft_lds<kRowThreads>(X, 0, plan, T, false);
+    fft_lds<kRowThreads, kRowElems>(X, 0, plan, T, false);
     // Z = F(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2 i)
     const int wc = W / 2 + 1;
     for (int k = threadIdx.x; k < wc; k += kRowThreads) {
@@ -249,8 +253,10 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_fwd(const float* __res
 // Columns [c0, c0 + 2^lgnc) of the half spectrum: forward FFT of length H, times scale
 // (1 / (A_hat H W)), inverse FFT. Blocks of adjacent columns go to the same XCD (xcd_tile):
 // a block reads 2^lgnc x 8 bytes of each spectrum row, less than a cache line for narrow
-// blocks on tall images, and its neighbours on the same L2 read the rest of the line.
-__global__ __launch_bounds__(kColThreads) void k_fft_cols(float2* __restrict__ spec,
+// blocks on tall images, and its neighbours on the same L2 read the rest of the line. Bounded
+// to 80 registers (six waves per SIMD): three workgroups fit a CU, so the 513 blocks of a
+// 2048-row image run at once.
+__global__ __launch_bounds__(kColThreads, 6) void k_fft_cols(float2* __restrict__ spec,
                                                          const float* __restrict__ scale, int H,
                                                          int wc, int lgnc, FftPlan plan,
                                                          const float2* __restrict__ tw) {
@@ -264,14 +270,14 @@ __global__ __launch_bounds__(kColThreads) void k_fft_cols(float2* __restrict__ s
     }
     for (int e = threadIdx.x; e < H; e += kColThreads) T[e] = tw[e];
     __syncthreads();
-    fft_lds<kColThreads>(X, lgnc, plan, T, false);
+    fft_lds<kColThreads, kColElems>(X, lgnc, plan, T, false);
     for (int e = threadIdx.x; e < total; e += kColThreads) {
         const int i = e >> lgnc, c = c0 + (e & (nc - 1));
         const float s = c < wc ? scale[(size_t)i * wc + c] : 0.f;
         X[e] = make_float2(X[e].x * s, X[e].y * s);
     }
     __syncthreads();
-    fft_lds<kColThreads>(X, lgnc, plan, T, true);
+    fft_lds<kColThreads, kColElems>(X, lgnc, plan, T, true);
     for (int e = threadIdx.x; e < total; e += kColThreads) {
         const int i = e >> lgnc, c = c0 + (e & (nc - 1));
         if (c < wc) spec[(size_t)i * wc + c] = X[e];
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __re
         X[j] = make_float2(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    fft_lds<kRowThreads>(X, 0, plan, T, true);
+    fft_lds<kRowThreads, kRowElems>(X, 0, plan, T, true);
     for (int j = threadIdx.x; j < W; j += kRowThreads) {
         const float2 z = X[j];
         x_out[(size_t)r0 * W + j] = x_in[(size_t)r0 * W + j] + z.x;
@@ -335,13 +341,11 @@ __global__ __launch_bounds__(256) void k_fft_scale(const double* __restrict__ ps
     scale[idx] = (float)(1.0 / (((re * re + im * im) * inv_s2 + lambda) * (double)H * W));
 }
 
-// Column block width: adjacent spectrum columns per workgroup, a power of two with
-// H 2^lgnc <= kColThreads kFftElems (the elements one stage holds) and at most 16.
-// Columns per block of the column pass: two where the block fits the workgroup's elements (one
-// for H > 4096). Wider blocks read longer row segments but give fewer workgroups: at 256x256
-// (129 columns) 16 columns per block left 9 workgroups for the whole pass (16.2 us against
-// 8.8 us with two), at 2048x2048 four columns per block took 74.8 us against 70.8 us.
-int col_lgnc(int H) { return (H << 1) <= kColThreads * kFftElems ? 1 : 0; }
+// Columns per block of the column pass: two where the block fits the workgroup's elements
+// (H <= 2048), else one. Wider blocks read longer row segments but give fewer workgroups: at
+// 256x256 (129 columns) 16 columns per block left 9 workgroups for the whole pass (16.2 us
+// against 8.8 us with two), at 2048x2048 four columns per block took 74.8 us against 70.8 us.
+int col_lgnc(int H) { return (H << 1) <= kColThreads * kColElems ? 1 : 0; }
 
 // Tables and buffers for one image size and operator.
 struct FftSolve {
