@@ -22,6 +22,7 @@
 // log2(N) 2^-24).
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "context.h"
@@ -33,13 +34,11 @@ namespace {
 
 constexpr int kFftMaxStages = 24;
 constexpr int kFftMaxSide = 4096;   // W: 256 threads x 16 elements; H: 512 threads x 8
-constexpr int kRowThreads = 256;
 constexpr int kColThreads = 512;
 // complex elements per thread and stage: the registers a stage holds grow with it, so the column
 // pass takes 8 (under 128 registers: two workgroups of 512 threads per CU, against one with 16)
-constexpr int kRowElems = 16, kColElems = 8;
-static_assert(kRowThreads * kRowElems >= kFftMaxSide && kColThreads * kColElems >= kFftMaxSide,
-              "a workgroup holds a whole row, and a whole column");
+constexpr int kColElems = 8;
+static_assert(kColThreads * kColElems >= kFftMaxSide, "a workgroup holds a whole column");
 
 // Radix stages of one transform length.
 struct FftPlan {
@@ -227,7 +226,8 @@ __device__ inline void fft_lds(float2* X, int lgnc, const FftPlan& plan,
 }
 
 // Rows 2g and 2g + 1 of r (the second may be absent) -> their half spectra in spec (H x wc).
-__global__ __launch_bounds__(kRowThreads) void k_fft_rows_fwd(const float* __restrict__ r, int H,
+template <int NT, int EL>
+__global__ __launch_bounds__(NT) void k_fft_rows_fwd(const float* __restrict__ r, int H,
                                                              int W, FftPlan plan,
                                                              const float2* __restrict__ tw,
                                                              float2* __restrict__ spec) {
@@ -235,15 +235,15 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_fwd(const float* __res
     float2* T = X + W;
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     const bool two = r1 < H;
-    for (int j = threadIdx.x; j < W; j += kRowThreads) {
+    for (int j = threadIdx.x; j < W; j += NT) {
         X[j] = make_float2(r[(size_t)r0 * W + j], two ? r[(size_t)r1 * W + j] : 0.f);
         T[j] = tw[j];
     }
     __syncthreads();
-    fft_lds<kRowThreads, kRowElems>(X, 0, plan, T, false);
+    fft_lds<NT, EL>(X, 0, plan, T, false);
     // Z = F(a + i b): A_k = (Z_k + conj Z_{-k}) / 2, B_k = (Z_k - conj Z_{-k}) / (2 i)
     const int wc = W / 2 + 1;
-    for (int k = threadIdx.x; k < wc; k += kRowThreads) {
+    for (int k = threadIdx.x; k < wc; k += NT) {
         const float2 z = X[k], w = X[k == 0 ? 0 : W - k];
         spec[(size_t)r0 * wc + k] = make_float2(0.5f * (z.x + w.x), 0.5f * (z.y - w.y));
         if (two) spec[(size_t)r1 * wc + k] = make_float2(0.5f * (z.y + w.y), 0.5f * (w.x - z.x));
@@ -286,7 +286,8 @@ __global__ __launch_bounds__(kColThreads, 6) void k_fft_cols(float2* __restrict_
 
 // Rows 2g and 2g + 1: Z = A + i B on the full length (A_{W-k} = conj A_k), inverse FFT, and
 // x_out = x_in + (Re z, Im z) on the two rows.
-__global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __restrict__ spec,
+template <int NT, int EL>
+__global__ __launch_bounds__(NT) void k_fft_rows_inv(const float2* __restrict__ spec,
                                                              const float* __restrict__ x_in,
                                                              float* __restrict__ x_out, int H,
                                                              int W, FftPlan plan,
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __re
     const int r0 = 2 * blockIdx.x, r1 = r0 + 1;
     const bool two = r1 < H;
     const int wc = W / 2 + 1;
-    for (int j = threadIdx.x; j < W; j += kRowThreads) {
+    for (int j = threadIdx.x; j < W; j += NT) {
         T[j] = tw[j];
         const bool lo = j < wc;
         const int k = lo ? j : W - j;
@@ -309,8 +310,8 @@ __global__ __launch_bounds__(kRowThreads) void k_fft_rows_inv(const float2* __re
         X[j] = make_float2(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    fft_lds<kRowThreads, kRowElems>(X, 0, plan, T, true);
-    for (int j = threadIdx.x; j < W; j += kRowThreads) {
+    fft_lds<NT, EL>(X, 0, plan, T, true);
+    for (int j = threadIdx.x; j < W; j += NT) {
         const float2 z = X[j];
         x_out[(size_t)r0 * W + j] = x_in[(size_t)r0 * W + j] + z.x;
         if (two) x_out[(size_t)r1 * W + j] = x_in[(size_t)r1 * W + j] + z.y;
@@ -434,10 +435,34 @@ int redve_fft_correction(redve_t h, float* r0, const float* x_in, float* x_out, 
     const size_t row_lds = sizeof(float2) * 2 * W;  // a row and its twiddles
     const int lgnc = col_lgnc(H);
     const size_t col_lds = sizeof(float2) * (((size_t)H << lgnc) + H);  // columns, twiddles
-    k_fft_rows_fwd<<<rows, kRowThreads, row_lds, h->stream>>>(r0, H, W, f->pw, f->tw_w, f->spec);
+    // rows: four elements per thread on sides up to 2048 (256 or 512 threads), eight beyond
+    const auto rows_fwd = [&](auto nt, auto el) {
+        k_fft_rows_fwd<decltype(nt)::value, decltype(el)::value>
+            <<<rows, decltype(nt)::value, row_lds, h->stream>>>(r0, H, W, f->pw, f->tw_w, f->spec);
+    };
+    const auto rows_inv = [&](auto nt, auto el) {
+        k_fft_rows_inv<decltype(nt)::value, decltype(el)::value>
+            <<<rows, decltype(nt)::value, row_lds, h->stream>>>(f->spec, x_in, x_out, H, W, f->pw,
+                                                                f->tw_w);
+    };
+    using I256 = std::integral_constant<int, 256>;
+    using I512 = std::integral_constant<int, 512>;
+    using E4 = std::integral_constant<int, 4>;
+    using E8 = std::integral_constant<int, 8>;
+    static_assert(512 * 8 >= kFftMaxSide, "a workgroup holds a whole row");
+    if (W <= 1024)
+        rows_fwd(I256{}, E4{});
+    else if (W <= 2048)
+        rows_fwd(I512{}, E4{});
+    else
+        rows_fwd(I512{}, E8{});
     k_fft_cols<<<(wc + (1 << lgnc) - 1) >> lgnc, kColThreads, col_lds, h->stream>>>(
         f->spec, f->scale, H, wc, lgnc, f->ph, f->tw_h);
-    k_fft_rows_inv<<<rows, kRowThreads, row_lds, h->stream>>>(f->spec, x_in, x_out, H, W, f->pw,
-                                                              f->tw_w);
+    if (W <= 1024)
+        rows_inv(I256{}, E4{});
+    else if (W <= 2048)
+        rows_inv(I512{}, E4{});
+    else
+        rows_inv(I512{}, E8{});
     return hipGetLastError() == hipSuccess ? REDVE_OK : REDVE_E_HIP;
 }
