@@ -64,7 +64,13 @@ def sized(h, w, seed):
 PROBLEMS = {"tiny": lambda: W.problem("tiny"), "deblur64": lambda: W.problem("deblur64"),
             "ragged": ragged, "deblur256": lambda: W.problem("deblur256"),
             "45x60": lambda: sized(45, 60, 1901), "2x3": lambda: sized(2, 3, 1902),
-            "384x500": lambda: sized(384, 500, 1903), "17x1024": lambda: sized(17, 1024, 1904)}
+            "384x500": lambda: sized(384, 500, 1903), "17x1024": lambda: sized(17, 1024, 1904),
+            # every shape of the row and column workgroups: rows of 1536 (radix 3) and 2048
+            # (512 threads, four elements each), of 3125 (radix 5) and 4096 (eight each); columns
+            # of 2048 (two per workgroup) and 4096 (one)
+            "7x1536": lambda: sized(7, 1536, 1905), "9x2048": lambda: sized(9, 2048, 1906),
+            "3x3125": lambda: sized(3, 3125, 1907), "5x4096": lambda: sized(5, 4096, 1908),
+            "2048x9": lambda: sized(2048, 9, 1909), "4096x6": lambda: sized(4096, 6, 1910)}
 
 
 def restorer(prob, **kw):
