@@ -990,6 +990,9 @@ def cpu_baseline(prob, calls, min_seconds):
     oracle.set_num_threads(threads)
     return {"value": npx * n / dt / 1e6, "unit": "MPix/s", "cores": threads,
             "kind": "oracle",
+            # pixels x FP calls per second, the batched workload's unit of work (the oracle's
+            # cost per pixel and FP call does not depend on the image's size)
+            "mpix_fp_calls_per_s": npx * n * calls / dt / 1e6,
             "sample": f"{n} whole RRE solves ({calls} FP calls each, FP64) of the same 256x256 "
                       f"image, {dt:.1f} s",
             "one_core": {"value": npx / (dt1 * calls) / 1e6, "unit": "MPix/s", "cores": 1,
